@@ -1,0 +1,150 @@
+/*
+ * mckernel.h -- C interface of the MI355X (gfx950) Fastfood hot path.
+ *
+ * The library computes McKernel's approximate kernel expansion (Curto et al.,
+ * arXiv 1702.08159): for an input row x of length d, zero-padded to
+ * n = max(2, next power of two >= d) (figure 1 caption and section
+ * "Empirical Analysis and Experiments": xhat = [x]_2), and for each of E
+ * kernel expansions e (section "McKernel": i.i.d. instances of Z stacked),
+ *
+ *     z_e = S_e H G_e Pi_e H B_e xhat          (equation "mckernel")
+ *     phi = c [cos z_0 .. cos z_{E-1}, sin z_0 .. sin z_{E-1}]   (equation "mcfeatures")
+ *
+ * with H the unnormalised Sylvester-Hadamard matrix (section "Fast Walsh
+ * Hadamard"), B a +-1 diagonal, Pi a permutation (applied as the gather
+ * (Pi v)_i = v[perm[i]]), G a Gaussian diagonal, S the RBF calibration
+ * S_j = s_j / (sigma sqrt(n) ||G_e||_F) with s_j ~ chi(n), and
+ * c = 1/sqrt(n E).  In seed mode B, Pi, G and S are generated from a 32-bit
+ * seed by the hash-driven generator documented with the project (MurmurHash3
+ * bits for B, a hash-driven Fisher-Yates shuffle for Pi, Box-Muller for G,
+ * chi(n) by Marsaglia-Tsang for S: section "McKernel", items B, Pi, G, C),
+ * so nothing but the seed needs to be stored (section "API Description").
+ *
+ * Conventions for every call:
+ *  - Arrays are caller-owned DEVICE pointers (hipMalloc / torch CUDA
+ *    tensors), FP32 unless stated, row-major and contiguous.  Outputs must not
+ *    alias inputs.
+ *  - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL = the
+ *    null stream).  Argument validation is synchronous: on an error status
+ *    nothing has been enqueued.
+ *  - Seed-mode calls build (once per device, seed, n, E, sigma, calibration)
+ *    a cached parameter plan in device memory; building it allocates memory,
+ *    launches the generator kernels on `stream` and waits for them.  Calls
+ *    that reuse a cached plan allocate nothing except where noted.
+ *    mck_shutdown() frees the cache.  The cache is thread-safe.
+ *  - Gradient outputs are overwritten, not accumulated; a NULL gradient
+ *    pointer skips that gradient.
+ *  - batch == 0 is a no-op that returns MCK_OK.
+ *  - No C++ exception crosses this interface; failures are status codes, and
+ *    mck_last_error() returns a message for the calling thread's last failure.
+ */
+#ifndef MCKERNEL_H
+#define MCKERNEL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum mck_status {
+    MCK_OK = 0,
+    MCK_ERR_INVALID_ARG = 1, /* bad size, pointer, sigma, ... (nothing enqueued) */
+    MCK_ERR_UNSUPPORTED = 2, /* valid request this build does not implement */
+    MCK_ERR_HIP = 3,         /* a HIP runtime call or kernel launch failed */
+    MCK_ERR_NO_MEMORY = 4    /* device allocation failed */
+} mck_status;
+
+typedef enum mck_calibration {
+    MCK_CALIB_RBF = 0,   /* S from chi(n) radii: the Gaussian RBF kernel exp(-|x-y|^2 / 2 sigma^2) */
+    MCK_CALIB_MATERN = 1 /* RBF-Matern calibration (section "Customizing McKernel"); not implemented */
+} mck_calibration;
+
+typedef void* mck_stream; /* hipStream_t */
+
+/* Largest n a single call accepts (single-pass transform held in LDS). */
+#define MCK_MAX_N 32768
+
+/* n = max(2, smallest power of two >= d); 0 when d < 1 or n > MCK_MAX_N. */
+int64_t mck_padded_dim(int64_t d);
+
+/* Static description of a status code. */
+const char* mck_status_string(mck_status status);
+
+/* Message of the calling thread's most recent failed call ("" if none). */
+const char* mck_last_error(void);
+
+/*
+ * In-place batched Walsh-Hadamard transform: each of the `batch` rows of
+ * `data` (batch x n) is replaced by H_n row, unnormalised, natural Sylvester
+ * order: (H v)_i = sum_k (-1)^popcount(i & k) v_k (section "Fast Walsh
+ * Hadamard": H_0 = [1], H_k = [[H, H], [H, -H]]).
+ * n must be a power of two, 1 <= n <= MCK_MAX_N (n = 1 is the identity).
+ */
+mck_status mck_fwht(float* data, int64_t batch, int64_t n, mck_stream stream);
+
+/*
+ * Generated parameters of a seed-mode plan, copied to caller buffers
+ * (E x n each, n = a power of two in [2, MCK_MAX_N]): B (+-1 as float),
+ * perm (int32 gather indices), G, S (FP32, S = RNE of the FP64 value with the
+ * 1/(sigma sqrt n ||G||) factor included) and S64 (FP64, may be NULL).
+ * Any of the outputs may be NULL.  sigma must be finite and > 0.
+ */
+mck_status mck_fastfood_params(uint32_t seed, int64_t n, int64_t E, double sigma, mck_calibration calib,
+                               float* B, int32_t* perm, float* G, float* S, double* S64, mck_stream stream);
+
+/*
+ * Feature map.  x: batch x d (d >= 1, n = mck_padded_dim(d) <= MCK_MAX_N),
+ * E >= 1, sigma finite > 0.  phi: batch x (2 n E), per row the E cosine
+ * blocks of length n (expansion-major) followed by the E sine blocks.
+ */
+mck_status mck_fastfood_forward(const float* x, int64_t batch, int64_t d, int64_t E, uint32_t seed,
+                                double sigma, mck_calibration calib, float* phi, mck_stream stream);
+
+/* z = Z xhat without the trigonometric map: batch x (n E), expansion-major. */
+mck_status mck_fastfood_project(const float* x, int64_t batch, int64_t d, int64_t E, uint32_t seed,
+                                double sigma, mck_calibration calib, float* z, mck_stream stream);
+
+/*
+ * Adjoint of the feature map: given dphi (batch x 2nE, the cotangent of phi)
+ * computes dx (batch x d), and dB, dG, dS (E x n each): the gradients of
+ * <dphi, phi> with respect to x and to the diagonals B, G, S taken as free
+ * variables, summed over the batch.  The forward chain is recomputed, not
+ * read from memory.  Requesting dB, dG or dS allocates a temporary buffer of
+ * about 256 x E x 3n floats on `stream` (stream-ordered).
+ */
+mck_status mck_fastfood_backward(const float* x, const float* dphi, int64_t batch, int64_t d, int64_t E,
+                                 uint32_t seed, double sigma, mck_calibration calib, float* dx, float* dB,
+                                 float* dG, float* dS, mck_stream stream);
+
+/*
+ * Explicit-parameter forms: B, G, S (float) and perm (int32, a permutation of
+ * 0..n-1; entries are reduced mod n) are caller-provided E x n device arrays,
+ * with n = mck_padded_dim(d) given explicitly (must match) and S including
+ * every scale.  These calls allocate a small temporary plan (E x n x 12
+ * bytes) on `stream` (stream-ordered).
+ */
+mck_status mck_fastfood_forward_p(const float* x, int64_t batch, int64_t d, int64_t n, int64_t E, const float* B,
+                                  const int32_t* perm, const float* G, const float* S, float* phi,
+                                  mck_stream stream);
+
+mck_status mck_fastfood_backward_p(const float* x, const float* dphi, int64_t batch, int64_t d, int64_t n,
+                                   int64_t E, const float* B, const int32_t* perm, const float* G, const float* S,
+                                   float* dx, float* dB, float* dG, float* dS, mck_stream stream);
+
+/*
+ * Generator self-check: the FP32 Box-Muller pair of the generator for `count`
+ * pairs of hash words (a[k], b[k]) -> (g0[k], g1[k]); lets a test compare the
+ * device generator with an independent implementation over all 2^24 inputs.
+ */
+mck_status mck_gen_boxmuller(const uint32_t* a, const uint32_t* b, int64_t count, float* g0, float* g1,
+                             mck_stream stream);
+
+/* Frees every cached plan (waits for the device first). */
+void mck_shutdown(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MCKERNEL_H */

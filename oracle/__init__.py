@@ -62,6 +62,8 @@ def _load():
     lib.orc_sincos2pi32.argtypes = [u32, ctypes.POINTER(f32), ctypes.POINTER(f32)]
     lib.orc_boxmuller32.restype = None
     lib.orc_boxmuller32.argtypes = [u32, u32, ctypes.POINTER(f32), ctypes.POINTER(f32)]
+    lib.orc_boxmuller32_many.restype = None
+    lib.orc_boxmuller32_many.argtypes = [vp, vp, i64, vp, vp]
     lib.orc_ln64.restype = f64
     lib.orc_ln64.argtypes = [f64]
     lib.orc_cos2pi64.restype = f64
@@ -118,6 +120,16 @@ def boxmuller32(a: int, b: int):
     g0, g1 = ctypes.c_float(), ctypes.c_float()
     _load().orc_boxmuller32(a, b, ctypes.byref(g0), ctypes.byref(g1))
     return np.float32(g0.value), np.float32(g1.value)
+
+
+def boxmuller32_many(a, b):
+    """Vectorised boxmuller32 over uint32 arrays a, b."""
+    a = _c(a, np.uint32)
+    b = _c(b, np.uint32)
+    g0 = np.empty(a.shape, np.float32)
+    g1 = np.empty(a.shape, np.float32)
+    _load().orc_boxmuller32_many(_ptr(a), _ptr(b), a.size, _ptr(g0), _ptr(g1))
+    return g0, g1
 
 
 def ln64(v: float) -> float:

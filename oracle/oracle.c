@@ -186,6 +186,12 @@ void orc_boxmuller32(uint32_t a, uint32_t b, float *g0, float *g1)
     *g1 = r * s;
 }
 
+void orc_boxmuller32_many(const uint32_t *a, const uint32_t *b, int64_t count, float *g0, float *g1)
+{
+    for (int64_t k = 0; k < count; ++k)
+        orc_boxmuller32(a[k], b[k], &g0[k], &g1[k]);
+}
+
 /* Natural log in FP64 of a positive normal double; series to s^25. */
 double orc_ln64(double v)
 {

@@ -1,0 +1,215 @@
+"""MI355X-native Fastfood feature map (McKernel, arXiv 1702.08159).
+
+Python binding of libmckernel.so: argument marshalling only.  Every step of
+the computation runs in the library's HIP kernels; tensors must be float32
+CUDA (ROCm) tensors on the current device, and work is enqueued on torch's
+current stream.
+
+    phi = fastfood(x, E=16, seed=1398239763, sigma=2.0)   # autograd w.r.t. x
+    z = project(x, E, seed, sigma)                        # Z xhat, no trig
+    p = params(seed, n, E, sigma)                         # generated B, perm, G, S
+    y = fwht(v)                                           # H v along the last axis
+    phi = FastfoodExplicit.apply(x, B, perm, G, S)        # learnable diagonals
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import MCK_CALIB_RBF, MckError
+
+PAPER_SEED = 1398239763
+MAX_N = 32768
+
+__all__ = ["padded_dim", "fwht", "fwht_", "params", "forward", "project", "backward", "forward_p",
+           "backward_p", "fastfood", "FastfoodFunction", "FastfoodExplicit", "gen_boxmuller", "shutdown",
+           "MckError", "PAPER_SEED", "MAX_N"]
+
+
+def _stream(t: torch.Tensor):
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _check(t: torch.Tensor, name: str, dtype=torch.float32):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s" % (name, dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+
+
+def padded_dim(d: int) -> int:
+    return int(_lib.lib().mck_padded_dim(d))
+
+
+def fwht_(v: torch.Tensor) -> torch.Tensor:
+    """In-place H v along the last axis (unnormalised, natural order)."""
+    _check(v, "v")
+    n = v.shape[-1]
+    with torch.cuda.device(v.device):
+        _lib.call("mck_fwht", _ptr(v), v.numel() // max(n, 1), n, _stream(v))
+    return v
+
+
+def fwht(v: torch.Tensor) -> torch.Tensor:
+    return fwht_(v.contiguous().clone())
+
+
+def params(seed: int, n: int, E: int, sigma: float, device=None):
+    """Generated B, perm, G, S (FP32) and S64 (FP64) of a seed-mode plan (E x n)."""
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    out = {
+        "B": torch.empty((E, n), dtype=torch.float32, device=dev),
+        "perm": torch.empty((E, n), dtype=torch.int32, device=dev),
+        "G": torch.empty((E, n), dtype=torch.float32, device=dev),
+        "S": torch.empty((E, n), dtype=torch.float32, device=dev),
+        "S64": torch.empty((E, n), dtype=torch.float64, device=dev),
+    }
+    with torch.cuda.device(dev):
+        _lib.call("mck_fastfood_params", seed & 0xFFFFFFFF, n, E, float(sigma), MCK_CALIB_RBF, _ptr(out["B"]),
+                  _ptr(out["perm"]), _ptr(out["G"]), _ptr(out["S"]), _ptr(out["S64"]),
+                  _stream(out["B"]))
+    return out
+
+
+def _rows(x: torch.Tensor):
+    if x.dim() != 2:
+        raise ValueError("x must be 2-D (batch x d)")
+    return x.shape[0], x.shape[1]
+
+
+def forward(x: torch.Tensor, E: int, seed: int = PAPER_SEED, sigma: float = 1.0, out=None) -> torch.Tensor:
+    """phi(x): batch x 2nE features [cos blocks, sin blocks]."""
+    _check(x, "x")
+    batch, d = _rows(x)
+    n = padded_dim(d)
+    if out is None:
+        out = torch.empty((batch, 2 * n * E), dtype=torch.float32, device=x.device)
+    _check(out, "out")
+    with torch.cuda.device(x.device):
+        _lib.call("mck_fastfood_forward", _ptr(x), batch, d, E, seed & 0xFFFFFFFF, float(sigma), MCK_CALIB_RBF,
+                  _ptr(out), _stream(x))
+    return out
+
+
+def project(x: torch.Tensor, E: int, seed: int = PAPER_SEED, sigma: float = 1.0) -> torch.Tensor:
+    """z = Z xhat: batch x nE (expansion-major)."""
+    _check(x, "x")
+    batch, d = _rows(x)
+    n = padded_dim(d)
+    out = torch.empty((batch, n * E), dtype=torch.float32, device=x.device)
+    with torch.cuda.device(x.device):
+        _lib.call("mck_fastfood_project", _ptr(x), batch, d, E, seed & 0xFFFFFFFF, float(sigma), MCK_CALIB_RBF,
+                  _ptr(out), _stream(x))
+    return out
+
+
+def backward(x: torch.Tensor, dphi: torch.Tensor, E: int, seed: int = PAPER_SEED, sigma: float = 1.0,
+             need_dx: bool = True, need_params: bool = False):
+    """(dx, dB, dG, dS) of <dphi, phi(x)>; entries not requested are None."""
+    _check(x, "x")
+    _check(dphi, "dphi")
+    batch, d = _rows(x)
+    n = padded_dim(d)
+    if dphi.shape != (batch, 2 * n * E):
+        raise ValueError("dphi must be batch x 2nE")
+    dx = torch.empty_like(x) if need_dx else None
+    dB = dG = dS = None
+    if need_params:
+        dB, dG, dS = (torch.empty((E, n), dtype=torch.float32, device=x.device) for _ in range(3))
+    with torch.cuda.device(x.device):
+        _lib.call("mck_fastfood_backward", _ptr(x), _ptr(dphi), batch, d, E, seed & 0xFFFFFFFF, float(sigma),
+                  MCK_CALIB_RBF, _ptr(dx), _ptr(dB), _ptr(dG), _ptr(dS), _stream(x))
+    return dx, dB, dG, dS
+
+
+def forward_p(x, B, perm, G, S) -> torch.Tensor:
+    """phi(x) for explicit diagonals B, G, S (E x n float32) and perm (E x n int32)."""
+    _check(x, "x")
+    for t, nm in ((B, "B"), (G, "G"), (S, "S")):
+        _check(t, nm)
+    _check(perm, "perm", torch.int32)
+    batch, d = _rows(x)
+    E, n = B.shape
+    out = torch.empty((batch, 2 * n * E), dtype=torch.float32, device=x.device)
+    with torch.cuda.device(x.device):
+        _lib.call("mck_fastfood_forward_p", _ptr(x), batch, d, n, E, _ptr(B), _ptr(perm), _ptr(G), _ptr(S),
+                  _ptr(out), _stream(x))
+    return out
+
+
+def backward_p(x, dphi, B, perm, G, S, need_dx=True, need_params=True):
+    _check(x, "x")
+    _check(dphi, "dphi")
+    batch, d = _rows(x)
+    E, n = B.shape
+    dx = torch.empty_like(x) if need_dx else None
+    dB = dG = dS = None
+    if need_params:
+        dB, dG, dS = (torch.empty((E, n), dtype=torch.float32, device=x.device) for _ in range(3))
+    with torch.cuda.device(x.device):
+        _lib.call("mck_fastfood_backward_p", _ptr(x), _ptr(dphi), batch, d, n, E, _ptr(B), _ptr(perm), _ptr(G),
+                  _ptr(S), _ptr(dx), _ptr(dB), _ptr(dG), _ptr(dS), _stream(x))
+    return dx, dB, dG, dS
+
+
+class FastfoodFunction(torch.autograd.Function):
+    """phi(x) with seed-generated parameters; backward recomputes the forward."""
+
+    @staticmethod
+    def forward(ctx, x, E, seed, sigma):
+        ctx.save_for_backward(x)
+        ctx.cfg = (E, seed, sigma)
+        return forward(x, E, seed, sigma)
+
+    @staticmethod
+    def backward(ctx, dphi):
+        (x,) = ctx.saved_tensors
+        E, seed, sigma = ctx.cfg
+        dx = None
+        if ctx.needs_input_grad[0]:
+            dx, _, _, _ = backward(x, dphi.contiguous(), E, seed, sigma, need_dx=True, need_params=False)
+        return dx, None, None, None
+
+
+class FastfoodExplicit(torch.autograd.Function):
+    """phi(x) for learnable diagonals B, G, S (perm fixed)."""
+
+    @staticmethod
+    def forward(ctx, x, B, perm, G, S):
+        ctx.save_for_backward(x, B, perm, G, S)
+        return forward_p(x, B, perm, G, S)
+
+    @staticmethod
+    def backward(ctx, dphi):
+        x, B, perm, G, S = ctx.saved_tensors
+        need_p = any(ctx.needs_input_grad[i] for i in (1, 3, 4))
+        dx, dB, dG, dS = backward_p(x, dphi.contiguous(), B, perm, G, S, need_dx=ctx.needs_input_grad[0],
+                                    need_params=need_p)
+        return dx, dB, None, dG, dS
+
+
+def fastfood(x: torch.Tensor, E: int, seed: int = PAPER_SEED, sigma: float = 1.0) -> torch.Tensor:
+    return FastfoodFunction.apply(x, E, seed, sigma)
+
+
+def gen_boxmuller(a: torch.Tensor, b: torch.Tensor):
+    """Device generator's FP32 Box-Muller pair for hash words a, b (int32 views of uint32)."""
+    _check(a, "a", torch.int32)
+    _check(b, "b", torch.int32)
+    g0 = torch.empty(a.shape, dtype=torch.float32, device=a.device)
+    g1 = torch.empty_like(g0)
+    with torch.cuda.device(a.device):
+        _lib.call("mck_gen_boxmuller", _ptr(a), _ptr(b), a.numel(), _ptr(g0), _ptr(g1), _stream(a))
+    return g0, g1
+
+
+def shutdown() -> None:
+    _lib.lib().mck_shutdown()

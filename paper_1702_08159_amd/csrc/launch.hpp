@@ -1,0 +1,59 @@
+// launch.hpp -- host-side launchers of the device kernels (internal to the
+// library; the public interface is include/mckernel.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mck {
+
+// c-scaled coefficients of the feature map (see engine.hpp)
+struct FeatCoefHost {
+    float s[5];
+    float c[5];
+};
+
+// Parameter generator: B, perm, G, S64, S32 (E x n each); norm2 is E doubles
+// of scratch.  Six kernels on stream s.
+hipError_t launch_generate(uint32_t seed, int64_t n, int64_t E, double sigma, float* B, int32_t* perm, float* G,
+                           double* S64, float* S32, double* norm2, hipStream_t s);
+
+// Box-Muller pairs for given hash words (generator self-check).
+hipError_t launch_boxmuller(const uint32_t* a, const uint32_t* b, int64_t count, float* g0, float* g1,
+                            hipStream_t s);
+
+// Kernel-layout copies of the parameters: gather offsets (4 * LDS position of
+// perm[i]), G in the gather layout, S in half turns (S / pi) and S as FP32.
+// S64 may be null (then S32 is used).
+hipError_t launch_derive(int M, int64_t E, const int32_t* perm, const float* G, const double* S64, const float* S32,
+                         uint32_t* goff, float* Gk, float* Sh, hipStream_t s);
+
+// In-place batched Walsh-Hadamard transform, n = 2^M, 1 <= M <= 15.
+hipError_t launch_fwht(int M, float* data, int64_t batch, bool vec, hipStream_t s);
+
+// Forward: phi (trig = true) or z = S H G Pi H B xhat (trig = false).
+hipError_t launch_forward(int M, bool vec, bool trig, const float* x, int64_t batch, int d, int64_t E,
+                          const float* B, const uint32_t* goff, const float* Gk, const float* Sx,
+                          const FeatCoefHost& coef, float* out, hipStream_t s);
+
+// Backward geometry: blocks, passes per block.
+struct BwdGeometry {
+    int64_t blocks;
+    int passes;
+    int block_threads;
+};
+BwdGeometry backward_geometry(int M, int64_t batch);
+
+// Backward: dx (nullable) and, when partial != null, per-block partial sums
+// of dS, dG, dB (blocks x E x 3 x n) reduced afterwards by launch_reduce.
+hipError_t launch_backward(int M, bool vec, const float* x, const float* dphi, int64_t batch, int d, int64_t E,
+                           const float* B, const uint32_t* goff, const float* Gk, const float* S32,
+                           const float* Sh, const FeatCoefHost& coef, float* dx, float* partial,
+                           const BwdGeometry& geo, hipStream_t s);
+
+// Fixed-order sum of the partials: out_a[e][i] = sum_b partial[b][e][a][i]
+// for a = 0 (S), 1 (G), 2 (B); null outputs skipped.
+hipError_t launch_reduce(const float* partial, int64_t blocks, int64_t E, int64_t n, float* dS, float* dG,
+                         float* dB, hipStream_t s);
+
+}  // namespace mck

@@ -1,0 +1,497 @@
+// runtime.cpp -- host side of the C interface in include/mckernel.h:
+// argument validation, the per-device parameter-plan cache, variant selection
+// and kernel launches.  Every computation of the hot path runs in the HIP
+// kernels of kernels.hip and generator.hip; this file only moves pointers.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <list>
+#include <mutex>
+#include <string>
+
+#include "../../include/mckernel.h"
+#include "launch.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+mck_status fail(mck_status st, const std::string& msg)
+{
+    g_last_error = msg;
+    return st;
+}
+
+mck_status hip_fail(hipError_t err, const char* where)
+{
+    return fail(MCK_ERR_HIP, std::string(where) + ": " + hipGetErrorString(err));
+}
+
+bool is_pow2(int64_t v) { return v >= 1 && (v & (v - 1)) == 0; }
+
+int log2i(int64_t v)
+{
+    int m = 0;
+    while ((int64_t(1) << m) < v)
+        ++m;
+    return m;
+}
+
+int64_t padded_dim(int64_t d)
+{
+    if (d < 1)
+        return 0;
+    int64_t n = 2;
+    while (n < d)
+        n *= 2;
+    return n > MCK_MAX_N ? 0 : n;
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+// Near-minimax coefficients of sin(pi f)/f and cos(pi f) in u = f^2 on
+// |f| <= 1/2 (max errors 3.3e-9 and 4.7e-8), scaled by c = 1/sqrt(nE).
+mck::FeatCoefHost feature_coefficients(int64_t n, int64_t E)
+{
+    static const double ks[5] = {3.141592580044727, -5.167706878926373, 2.5500313772798826, -0.5980451741176938,
+                                 0.07722012894382006};
+    static const double kc[5] = {0.9999999534666582, -4.934792858674183, 4.0584119141457276, -1.3318801611124893,
+                                 0.21969679833150207};
+    const double c = 1.0 / std::sqrt((double)n * (double)E);
+    mck::FeatCoefHost h;
+    for (int i = 0; i < 5; ++i) {
+        h.s[i] = (float)(ks[i] * c);
+        h.c[i] = (float)(kc[i] * c);
+    }
+    return h;
+}
+
+mck_status check_sigma(double sigma)
+{
+    if (!(sigma > 0.0) || !std::isfinite(sigma))
+        return fail(MCK_ERR_INVALID_ARG, "sigma must be finite and > 0");
+    return MCK_OK;
+}
+
+mck_status check_common(int64_t batch, int64_t d, int64_t E, int64_t* n_out)
+{
+    if (batch < 0)
+        return fail(MCK_ERR_INVALID_ARG, "batch must be >= 0");
+    if (d < 1)
+        return fail(MCK_ERR_INVALID_ARG, "d must be >= 1");
+    if (E < 1 || E > (int64_t(1) << 20))
+        return fail(MCK_ERR_INVALID_ARG, "E must be in [1, 2^20]");
+    const int64_t n = padded_dim(d);
+    if (n == 0)
+        return fail(MCK_ERR_UNSUPPORTED, "padded dimension exceeds MCK_MAX_N");
+    if (d > (int64_t(1) << 30) || batch > (int64_t(1) << 40))
+        return fail(MCK_ERR_INVALID_ARG, "size out of range");
+    *n_out = n;
+    return MCK_OK;
+}
+
+// ------------------------------------------------------------------ plan cache
+struct Plan {
+    int device = 0;
+    uint32_t seed = 0;
+    int64_t n = 0, E = 0;
+    double sigma = 0.0;
+    int calib = 0;
+    void* block = nullptr;
+    size_t bytes = 0;
+    float* B = nullptr;
+    int32_t* perm = nullptr;
+    float* G = nullptr;
+    double* S64 = nullptr;
+    float* S32 = nullptr;
+    double* norm2 = nullptr;
+    uint32_t* goff = nullptr;
+    float* Gk = nullptr;
+    float* Sh = nullptr;
+};
+
+std::mutex g_mutex;
+std::list<Plan> g_plans;  // most recently used first
+constexpr size_t kMaxPlans = 32;
+constexpr size_t kMaxPlanBytes = size_t(2) << 30;
+
+size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+void free_plan(Plan& p)
+{
+    if (p.block) {
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(p.device);
+        (void)hipFree(p.block);
+        (void)hipSetDevice(cur);
+        p.block = nullptr;
+    }
+}
+
+// Returns the plan for the arguments, building it on `stream` if needed.
+mck_status get_plan(uint32_t seed, int64_t n, int64_t E, double sigma, int calib, hipStream_t stream,
+                    Plan** out)
+{
+    int dev = 0;
+    hipError_t err = hipGetDevice(&dev);
+    if (err != hipSuccess)
+        return hip_fail(err, "hipGetDevice");
+    std::lock_guard<std::mutex> lock(g_mutex);
+    for (auto it = g_plans.begin(); it != g_plans.end(); ++it) {
+        if (it->device == dev && it->seed == seed && it->n == n && it->E == E && it->sigma == sigma &&
+            it->calib == calib) {
+            g_plans.splice(g_plans.begin(), g_plans, it);
+            *out = &g_plans.front();
+            return MCK_OK;
+        }
+    }
+    Plan p;
+    p.device = dev;
+    p.seed = seed;
+    p.n = n;
+    p.E = E;
+    p.sigma = sigma;
+    p.calib = calib;
+    const size_t en = (size_t)(n * E);
+    size_t off[10], total = 0;
+    const size_t sz[10] = {en * 4, en * 4, en * 4, en * 8, en * 4, (size_t)E * 8, en * 4, en * 4, en * 4, 0};
+    for (int i = 0; i < 9; ++i) {
+        off[i] = total;
+        total += align_up(sz[i]);
+    }
+    // evict least recently used plans beyond the limits
+    size_t used = 0;
+    for (auto& q : g_plans)
+        used += q.bytes;
+    while (!g_plans.empty() && (g_plans.size() >= kMaxPlans || used + total > kMaxPlanBytes)) {
+        used -= g_plans.back().bytes;
+        free_plan(g_plans.back());
+        g_plans.pop_back();
+    }
+    err = hipMalloc(&p.block, total);
+    if (err != hipSuccess) {
+        p.block = nullptr;
+        return fail(MCK_ERR_NO_MEMORY, std::string("plan allocation: ") + hipGetErrorString(err));
+    }
+    p.bytes = total;
+    char* b = static_cast<char*>(p.block);
+    p.B = reinterpret_cast<float*>(b + off[0]);
+    p.perm = reinterpret_cast<int32_t*>(b + off[1]);
+    p.G = reinterpret_cast<float*>(b + off[2]);
+    p.S64 = reinterpret_cast<double*>(b + off[3]);
+    p.S32 = reinterpret_cast<float*>(b + off[4]);
+    p.norm2 = reinterpret_cast<double*>(b + off[5]);
+    p.goff = reinterpret_cast<uint32_t*>(b + off[6]);
+    p.Gk = reinterpret_cast<float*>(b + off[7]);
+    p.Sh = reinterpret_cast<float*>(b + off[8]);
+    err = mck::launch_generate(seed, n, E, sigma, p.B, p.perm, p.G, p.S64, p.S32, p.norm2, stream);
+    if (err == hipSuccess)
+        err = mck::launch_derive(log2i(n), E, p.perm, p.G, p.S64, p.S32, p.goff, p.Gk, p.Sh, stream);
+    if (err == hipSuccess)
+        err = hipStreamSynchronize(stream);  // the plan may be used from other streams next
+    if (err != hipSuccess) {
+        free_plan(p);
+        return hip_fail(err, "plan generation");
+    }
+    g_plans.push_front(p);
+    *out = &g_plans.front();
+    return MCK_OK;
+}
+
+struct TempPlan {
+    void* block = nullptr;
+    uint32_t* goff = nullptr;
+    float* Gk = nullptr;
+    float* Sh = nullptr;
+};
+
+mck_status make_temp_plan(int64_t n, int64_t E, const int32_t* perm, const float* G, const float* S,
+                          hipStream_t s, TempPlan* tp)
+{
+    const size_t en = (size_t)(n * E);
+    const size_t a = align_up(en * 4);
+    hipError_t err = hipMallocAsync(&tp->block, 3 * a, s);
+    if (err != hipSuccess) {
+        tp->block = nullptr;
+        return fail(MCK_ERR_NO_MEMORY, std::string("temporary plan: ") + hipGetErrorString(err));
+    }
+    char* b = static_cast<char*>(tp->block);
+    tp->goff = reinterpret_cast<uint32_t*>(b);
+    tp->Gk = reinterpret_cast<float*>(b + a);
+    tp->Sh = reinterpret_cast<float*>(b + 2 * a);
+    err = mck::launch_derive(log2i(n), E, perm, G, nullptr, S, tp->goff, tp->Gk, tp->Sh, s);
+    if (err != hipSuccess) {
+        (void)hipFreeAsync(tp->block, s);
+        return hip_fail(err, "derive kernel");
+    }
+    return MCK_OK;
+}
+
+bool vec_ok(const void* a, const void* b, int64_t d, int64_t n)
+{
+    return aligned16(a) && aligned16(b) && (d % 4 == 0) && n >= 4;
+}
+
+mck_status run_backward(const float* x, const float* dphi, int64_t batch, int64_t d, int64_t n, int64_t E,
+                        const float* B, const uint32_t* goff, const float* Gk, const float* S32, const float* Sh,
+                        float* dx, float* dB, float* dG, float* dS, hipStream_t s)
+{
+    const int M = log2i(n);
+    const bool want_params = dB || dG || dS;
+    const mck::BwdGeometry geo = mck::backward_geometry(M, batch);
+    float* partial = nullptr;
+    hipError_t err;
+    if (want_params) {
+        err = hipMallocAsync(reinterpret_cast<void**>(&partial), (size_t)geo.blocks * E * 3 * n * sizeof(float), s);
+        if (err != hipSuccess)
+            return fail(MCK_ERR_NO_MEMORY, std::string("backward partials: ") + hipGetErrorString(err));
+    }
+    const bool vec = vec_ok(x, dphi, d, n) && (dx == nullptr || aligned16(dx));
+    err = mck::launch_backward(M, vec, x, dphi, batch, (int)d, E, B, goff, Gk, S32, Sh, feature_coefficients(n, E), dx,
+                               partial, geo, s);
+    if (err == hipSuccess && want_params)
+        err = mck::launch_reduce(partial, geo.blocks, E, n, dS, dG, dB, s);
+    if (partial)
+        (void)hipFreeAsync(partial, s);
+    if (err != hipSuccess)
+        return hip_fail(err, "backward launch");
+    return MCK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t mck_padded_dim(int64_t d) { return padded_dim(d); }
+
+const char* mck_status_string(mck_status status)
+{
+    switch (status) {
+    case MCK_OK: return "success";
+    case MCK_ERR_INVALID_ARG: return "invalid argument";
+    case MCK_ERR_UNSUPPORTED: return "unsupported";
+    case MCK_ERR_HIP: return "HIP runtime error";
+    case MCK_ERR_NO_MEMORY: return "out of device memory";
+    }
+    return "unknown status";
+}
+
+const char* mck_last_error(void) { return g_last_error.c_str(); }
+
+mck_status mck_fwht(float* data, int64_t batch, int64_t n, mck_stream stream)
+{
+    if (batch < 0)
+        return fail(MCK_ERR_INVALID_ARG, "batch must be >= 0");
+    if (!is_pow2(n))
+        return fail(MCK_ERR_INVALID_ARG, "n must be a power of two >= 1");
+    if (n > MCK_MAX_N)
+        return fail(MCK_ERR_UNSUPPORTED, "n exceeds MCK_MAX_N");
+    if (batch > 0 && data == nullptr)
+        return fail(MCK_ERR_INVALID_ARG, "data is NULL");
+    if (batch == 0 || n == 1)
+        return MCK_OK;
+    const hipError_t err = mck::launch_fwht(log2i(n), data, batch, aligned16(data) && n >= 4,
+                                            static_cast<hipStream_t>(stream));
+    return err == hipSuccess ? MCK_OK : hip_fail(err, "mck_fwht");
+}
+
+mck_status mck_fastfood_params(uint32_t seed, int64_t n, int64_t E, double sigma, mck_calibration calib, float* B,
+                               int32_t* perm, float* G, float* S, double* S64, mck_stream stream)
+{
+    if (!is_pow2(n) || n < 2)
+        return fail(MCK_ERR_INVALID_ARG, "n must be a power of two >= 2");
+    if (n > MCK_MAX_N)
+        return fail(MCK_ERR_UNSUPPORTED, "n exceeds MCK_MAX_N");
+    if (E < 1 || E > (int64_t(1) << 20))
+        return fail(MCK_ERR_INVALID_ARG, "E must be in [1, 2^20]");
+    mck_status st = check_sigma(sigma);
+    if (st != MCK_OK)
+        return st;
+    if (calib != MCK_CALIB_RBF)
+        return fail(MCK_ERR_UNSUPPORTED, "only MCK_CALIB_RBF is implemented");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Plan* p = nullptr;
+    st = get_plan(seed, n, E, sigma, calib, s, &p);
+    if (st != MCK_OK)
+        return st;
+    const size_t en = (size_t)(n * E);
+    hipError_t err = hipSuccess;
+    if (B && err == hipSuccess)
+        err = hipMemcpyAsync(B, p->B, en * 4, hipMemcpyDeviceToDevice, s);
+    if (perm && err == hipSuccess)
+        err = hipMemcpyAsync(perm, p->perm, en * 4, hipMemcpyDeviceToDevice, s);
+    if (G && err == hipSuccess)
+        err = hipMemcpyAsync(G, p->G, en * 4, hipMemcpyDeviceToDevice, s);
+    if (S && err == hipSuccess)
+        err = hipMemcpyAsync(S, p->S32, en * 4, hipMemcpyDeviceToDevice, s);
+    if (S64 && err == hipSuccess)
+        err = hipMemcpyAsync(S64, p->S64, en * 8, hipMemcpyDeviceToDevice, s);
+    return err == hipSuccess ? MCK_OK : hip_fail(err, "mck_fastfood_params copy");
+}
+
+static mck_status forward_common(const float* x, int64_t batch, int64_t d, int64_t E, uint32_t seed, double sigma,
+                                 mck_calibration calib, float* out, bool trig, mck_stream stream)
+{
+    int64_t n = 0;
+    mck_status st = check_common(batch, d, E, &n);
+    if (st != MCK_OK)
+        return st;
+    st = check_sigma(sigma);
+    if (st != MCK_OK)
+        return st;
+    if (calib != MCK_CALIB_RBF)
+        return fail(MCK_ERR_UNSUPPORTED, "only MCK_CALIB_RBF is implemented");
+    if (batch > 0 && (x == nullptr || out == nullptr))
+        return fail(MCK_ERR_INVALID_ARG, "x or output is NULL");
+    if (batch == 0)
+        return MCK_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Plan* p = nullptr;
+    st = get_plan(seed, n, E, sigma, calib, s, &p);
+    if (st != MCK_OK)
+        return st;
+    const hipError_t err = mck::launch_forward(log2i(n), vec_ok(x, out, d, n), trig, x, batch, (int)d, E, p->B,
+                                               p->goff, p->Gk, trig ? p->Sh : p->S32, feature_coefficients(n, E),
+                                               out, s);
+    return err == hipSuccess ? MCK_OK : hip_fail(err, "forward launch");
+}
+
+mck_status mck_fastfood_forward(const float* x, int64_t batch, int64_t d, int64_t E, uint32_t seed, double sigma,
+                                mck_calibration calib, float* phi, mck_stream stream)
+{
+    return forward_common(x, batch, d, E, seed, sigma, calib, phi, true, stream);
+}
+
+mck_status mck_fastfood_project(const float* x, int64_t batch, int64_t d, int64_t E, uint32_t seed, double sigma,
+                                mck_calibration calib, float* z, mck_stream stream)
+{
+    return forward_common(x, batch, d, E, seed, sigma, calib, z, false, stream);
+}
+
+mck_status mck_fastfood_backward(const float* x, const float* dphi, int64_t batch, int64_t d, int64_t E,
+                                 uint32_t seed, double sigma, mck_calibration calib, float* dx, float* dB, float* dG,
+                                 float* dS, mck_stream stream)
+{
+    int64_t n = 0;
+    mck_status st = check_common(batch, d, E, &n);
+    if (st != MCK_OK)
+        return st;
+    st = check_sigma(sigma);
+    if (st != MCK_OK)
+        return st;
+    if (calib != MCK_CALIB_RBF)
+        return fail(MCK_ERR_UNSUPPORTED, "only MCK_CALIB_RBF is implemented");
+    if (batch > 0 && (x == nullptr || dphi == nullptr))
+        return fail(MCK_ERR_INVALID_ARG, "x or dphi is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!dx && !dB && !dG && !dS)
+        return MCK_OK;
+    Plan* p = nullptr;
+    if (batch == 0) {
+        if (!dB && !dG && !dS)
+            return MCK_OK;
+        // the sums over an empty batch are zero
+        hipError_t err = hipSuccess;
+        for (float* o : {dB, dG, dS})
+            if (o && err == hipSuccess)
+                err = hipMemsetAsync(o, 0, (size_t)(n * E) * sizeof(float), s);
+        return err == hipSuccess ? MCK_OK : hip_fail(err, "zero gradients");
+    }
+    st = get_plan(seed, n, E, sigma, calib, s, &p);
+    if (st != MCK_OK)
+        return st;
+    return run_backward(x, dphi, batch, d, n, E, p->B, p->goff, p->Gk, p->S32, p->Sh, dx, dB, dG, dS, s);
+}
+
+static mck_status check_explicit(int64_t batch, int64_t d, int64_t n, int64_t E, const float* B,
+                                 const int32_t* perm, const float* G, const float* S)
+{
+    int64_t nn = 0;
+    mck_status st = check_common(batch, d, E, &nn);
+    if (st != MCK_OK)
+        return st;
+    if (n != nn)
+        return fail(MCK_ERR_INVALID_ARG, "n must equal mck_padded_dim(d)");
+    if (!B || !perm || !G || !S)
+        return fail(MCK_ERR_INVALID_ARG, "B, perm, G and S must be non-NULL");
+    return MCK_OK;
+}
+
+mck_status mck_fastfood_forward_p(const float* x, int64_t batch, int64_t d, int64_t n, int64_t E, const float* B,
+                                  const int32_t* perm, const float* G, const float* S, float* phi, mck_stream stream)
+{
+    mck_status st = check_explicit(batch, d, n, E, B, perm, G, S);
+    if (st != MCK_OK)
+        return st;
+    if (batch > 0 && (x == nullptr || phi == nullptr))
+        return fail(MCK_ERR_INVALID_ARG, "x or phi is NULL");
+    if (batch == 0)
+        return MCK_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    TempPlan tp;
+    st = make_temp_plan(n, E, perm, G, S, s, &tp);
+    if (st != MCK_OK)
+        return st;
+    hipError_t err = mck::launch_forward(log2i(n), vec_ok(x, phi, d, n), true, x, batch, (int)d, E, B, tp.goff, tp.Gk,
+                                         tp.Sh, feature_coefficients(n, E), phi, s);
+    (void)hipFreeAsync(tp.block, s);
+    return err == hipSuccess ? MCK_OK : hip_fail(err, "forward launch");
+}
+
+mck_status mck_fastfood_backward_p(const float* x, const float* dphi, int64_t batch, int64_t d, int64_t n, int64_t E,
+                                   const float* B, const int32_t* perm, const float* G, const float* S, float* dx,
+                                   float* dB, float* dG, float* dS, mck_stream stream)
+{
+    mck_status st = check_explicit(batch, d, n, E, B, perm, G, S);
+    if (st != MCK_OK)
+        return st;
+    if (batch > 0 && (x == nullptr || dphi == nullptr))
+        return fail(MCK_ERR_INVALID_ARG, "x or dphi is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!dx && !dB && !dG && !dS)
+        return MCK_OK;
+    if (batch == 0) {
+        hipError_t err = hipSuccess;
+        for (float* o : {dB, dG, dS})
+            if (o && err == hipSuccess)
+                err = hipMemsetAsync(o, 0, (size_t)(n * E) * sizeof(float), s);
+        return err == hipSuccess ? MCK_OK : hip_fail(err, "zero gradients");
+    }
+    TempPlan tp;
+    st = make_temp_plan(n, E, perm, G, S, s, &tp);
+    if (st != MCK_OK)
+        return st;
+    st = run_backward(x, dphi, batch, d, n, E, B, tp.goff, tp.Gk, S, tp.Sh, dx, dB, dG, dS, s);
+    (void)hipFreeAsync(tp.block, s);
+    return st;
+}
+
+mck_status mck_gen_boxmuller(const uint32_t* a, const uint32_t* b, int64_t count, float* g0, float* g1,
+                             mck_stream stream)
+{
+    if (count < 0)
+        return fail(MCK_ERR_INVALID_ARG, "count must be >= 0");
+    if (count > 0 && (!a || !b || !g0 || !g1))
+        return fail(MCK_ERR_INVALID_ARG, "NULL pointer");
+    const hipError_t err = mck::launch_boxmuller(a, b, count, g0, g1, static_cast<hipStream_t>(stream));
+    return err == hipSuccess ? MCK_OK : hip_fail(err, "mck_gen_boxmuller");
+}
+
+void mck_shutdown(void)
+{
+    std::lock_guard<std::mutex> lock(g_mutex);
+    for (auto& p : g_plans) {
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(p.device);
+        (void)hipDeviceSynchronize();
+        (void)hipSetDevice(cur);
+        free_plan(p);
+    }
+    g_plans.clear();
+}
+
+}  // extern "C"

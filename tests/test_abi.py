@@ -1,0 +1,104 @@
+"""The C interface loads, exports every declared symbol, and rejects bad
+arguments before touching a GPU (CPU only)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mckernel.h")
+
+pytestmark = pytest.mark.skipif(
+    not os.path.exists(os.path.join(ROOT, "paper_1702_08159_amd", "libmckernel.so")),
+    reason="libmckernel.so not built (run __graft_entry__.build())")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mck_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1702_08159_amd import _lib
+
+    return _lib.lib()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_1702_08159_amd import _lib
+
+    syms = declared_symbols()
+    assert len(syms) >= 11
+    for s in syms:
+        assert hasattr(lib, s), s
+        assert s in _lib.SIGNATURES, "binding lacks " + s
+
+
+def test_padded_dim(lib):
+    assert [lib.mck_padded_dim(d) for d in (0, 1, 2, 3, 5, 784, 1024, 1025, 32768, 32769)] == \
+        [0, 2, 2, 4, 8, 1024, 1024, 2048, 32768, 0]
+
+
+def test_status_strings(lib):
+    for st in range(5):
+        assert lib.mck_status_string(st)
+    assert lib.mck_status_string(0) == b"success"
+
+
+def _st(lib, name, *args):
+    return getattr(lib, name)(*args)
+
+
+def test_validation_without_gpu(lib):
+    null = None
+    # mck_fwht: n not a power of two, negative batch, n too large, NULL data
+    assert _st(lib, "mck_fwht", null, 1, 3, null) == 1
+    assert _st(lib, "mck_fwht", null, -1, 4, null) == 1
+    assert _st(lib, "mck_fwht", null, 1, 65536, null) == 2
+    assert _st(lib, "mck_fwht", null, 2, 8, null) == 1
+    assert b"NULL" in lib.mck_last_error()
+    assert _st(lib, "mck_fwht", null, 0, 8, null) == 0       # empty batch
+    # forward: d < 1, E < 1, bad sigma, unsupported calibration, NULL x, too long
+    fwd = "mck_fastfood_forward"
+    assert _st(lib, fwd, null, 4, 0, 1, 1, 1.0, 0, null, null) == 1
+    assert _st(lib, fwd, null, 4, 8, 0, 1, 1.0, 0, null, null) == 1
+    for sig in (0.0, -1.0, float("nan"), float("inf")):
+        assert _st(lib, fwd, null, 4, 8, 1, 1, sig, 0, null, null) == 1
+    assert _st(lib, fwd, null, 4, 8, 1, 1, 1.0, 1, null, null) == 2
+    assert _st(lib, fwd, null, 4, 8, 1, 1, 1.0, 0, null, null) == 1
+    assert _st(lib, fwd, null, 4, 40000, 1, 1, 1.0, 0, null, null) == 2
+    assert _st(lib, fwd, null, 0, 8, 2, 1, 1.0, 0, null, null) == 0  # empty batch
+    # backward: NULL dphi; nothing requested is a no-op
+    bwd = "mck_fastfood_backward"
+    assert _st(lib, bwd, null, null, 3, 8, 1, 1, 1.0, 0, ctypes.c_void_p(16), null, null, null, null) == 1
+    assert _st(lib, bwd, ctypes.c_void_p(16), ctypes.c_void_p(16), 3, 8, 1, 1, 1.0, 0,
+               null, null, null, null, null) == 0
+    # explicit forms: n mismatch, NULL parameters
+    assert _st(lib, "mck_fastfood_forward_p", null, 1, 8, 16, 1, null, null, null, null, null, null) == 1
+    p = ctypes.c_void_p(16)
+    assert _st(lib, "mck_fastfood_forward_p", null, 1, 8, 16, 1, p, p, p, p, null, null) == 1
+    assert _st(lib, "mck_fastfood_forward_p", null, 1, 8, 8, 1, p, p, p, p, null, null) == 1
+    # params: n not a power of two, n = 1, bad sigma, unsupported calibration
+    prm = "mck_fastfood_params"
+    assert _st(lib, prm, 1, 12, 1, 1.0, 0, null, null, null, null, null, null) == 1
+    assert _st(lib, prm, 1, 1, 1, 1.0, 0, null, null, null, null, null, null) == 1
+    assert _st(lib, prm, 1, 8, 1, 0.0, 0, null, null, null, null, null, null) == 1
+    assert _st(lib, prm, 1, 8, 1, 1.0, 1, null, null, null, null, null, null) == 2
+    # generator self-check: negative count, NULL pointers
+    assert _st(lib, "mck_gen_boxmuller", null, null, -1, null, null, null) == 1
+    assert _st(lib, "mck_gen_boxmuller", null, null, 5, null, null, null) == 1
+    assert _st(lib, "mck_gen_boxmuller", null, null, 0, null, null, null) == 0
+
+
+def test_python_binding_refuses_cpu_tensors():
+    import torch
+
+    import paper_1702_08159_amd as mk
+
+    with pytest.raises(TypeError):
+        mk.forward(torch.zeros(2, 8), 1)
+    with pytest.raises(TypeError):
+        mk.fwht_(torch.zeros(2, 8))

@@ -1,0 +1,301 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Tolerances (per the FP32 target of the method and the oracle's error
+analysis): integer FWHT inputs bit-exact; generator outputs (B, perm, G, S,
+S64) bit-exact; float FWHT 1e-6 and features / projections / gradients
+1e-5, all as normwise relative errors per row (per tensor for the parameter
+gradients), since elementwise relative error is ill-posed where cos z = 0.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+FEAT_TOL = 1e-5
+FWHT_TOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def mk():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1702_08159_amd as mk
+
+    mk._lib.lib()
+    return mk
+
+
+@pytest.fixture(scope="module")
+def torch_mod(mk):
+    import torch
+
+    return torch
+
+
+def rowwise_rel(a, ref):
+    a = np.asarray(a, np.float64).reshape(ref.shape[0], -1)
+    ref = np.asarray(ref, np.float64).reshape(ref.shape[0], -1)
+    den = np.linalg.norm(ref, axis=1)
+    den[den == 0] = 1.0
+    return np.linalg.norm(a - ref, axis=1) / den
+
+
+def tensor_rel(a, ref):
+    a = np.asarray(a, np.float64)
+    ref = np.asarray(ref, np.float64)
+    return float(np.linalg.norm(a - ref) / max(np.linalg.norm(ref), 1e-300))
+
+
+def to_dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+# ------------------------------------------------------------------ FWHT
+@pytest.mark.parametrize("m", list(range(0, 16)))
+def test_fwht_integer_bit_exact(mk, torch_mod, orc, m):
+    torch = torch_mod
+    n = 1 << m
+    batch = 131 if m <= 11 else 5
+    rng = np.random.default_rng(m)
+    v = rng.integers(-8, 9, size=(batch, n)).astype(np.float32)
+    out = mk.fwht(to_dev(torch, v)).cpu().numpy()
+    ref = orc.fwht(v.astype(np.float64))
+    np.testing.assert_array_equal(out.astype(np.float64), ref)
+
+
+@pytest.mark.parametrize("m", [1, 3, 5, 7, 10, 12, 15])
+def test_fwht_float(mk, torch_mod, orc, m):
+    torch = torch_mod
+    n = 1 << m
+    rng = np.random.default_rng(100 + m)
+    v = rng.standard_normal((67, n)).astype(np.float32)
+    out = mk.fwht(to_dev(torch, v)).cpu().numpy()
+    ref = orc.fwht(v.astype(np.float64))
+    assert rowwise_rel(out, ref).max() <= FWHT_TOL
+
+
+def test_fwht_unaligned_rows_use_scalar_path(mk, torch_mod, orc):
+    torch = torch_mod
+    n, batch = 64, 9
+    rng = np.random.default_rng(5)
+    buf = torch.zeros(batch * n + 1, dtype=torch.float32, device="cuda")
+    v = rng.integers(-8, 9, size=(batch, n)).astype(np.float32)
+    view = buf[1:].view(batch, n)      # 4-byte offset: not 16-byte aligned
+    view.copy_(to_dev(torch, v))
+    mk.fwht_(view)
+    np.testing.assert_array_equal(view.cpu().numpy().astype(np.float64), orc.fwht(v.astype(np.float64)))
+    assert buf[0].item() == 0.0
+
+
+# ------------------------------------------------------------------ generator
+@pytest.mark.parametrize("seed,n,E,sigma", [(1398239763, 1024, 16, 2.0), (0, 1024, 1, 1.0), (7, 2, 3, 1.0),
+                                            (7, 4, 2, 0.5), (99, 64, 5, 3.0), (12345, 4096, 2, 64.0),
+                                            (2**32 - 1, 32768, 1, 1.0), (5, 2048, 3, 1.0)])
+def test_params_bit_exact(mk, torch_mod, orc, seed, n, E, sigma):
+    g = mk.params(seed, n, E, sigma)
+    r = orc.params(seed, n, E, sigma)
+    np.testing.assert_array_equal(g["B"].cpu().numpy(), r["B"])
+    np.testing.assert_array_equal(g["perm"].cpu().numpy(), r["perm"])
+    np.testing.assert_array_equal(g["G"].cpu().numpy().view(np.uint32), r["G"].view(np.uint32))
+    np.testing.assert_array_equal(g["S64"].cpu().numpy().view(np.uint64), r["S64"].view(np.uint64))
+    np.testing.assert_array_equal(g["S"].cpu().numpy().view(np.uint32), r["S32"].view(np.uint32))
+
+
+@pytest.mark.parametrize("which", ["radius", "angle"])
+def test_boxmuller_exhaustive(mk, torch_mod, orc, which):
+    # all 2^24 values of the radius uniform (a >> 8) and of the angle uniform (b >> 8)
+    torch = torch_mod
+    k = np.arange(1 << 24, dtype=np.uint32) << np.uint32(8)
+    fixed = np.full_like(k, 0x9E3779B9)
+    a, b = (k, fixed) if which == "radius" else (fixed, k)
+    g0, g1 = mk.gen_boxmuller(to_dev(torch, a.view(np.int32)), to_dev(torch, b.view(np.int32)))
+    g0 = g0.cpu().numpy()
+    g1 = g1.cpu().numpy()
+    r0, r1 = orc.boxmuller32_many(a, b)
+    np.testing.assert_array_equal(g0.view(np.uint32), r0.view(np.uint32))
+    np.testing.assert_array_equal(g1.view(np.uint32), r1.view(np.uint32))
+
+
+# ------------------------------------------------------------------ forward
+def _oracle_phi(orc, x, E, seed, sigma):
+    phi, z, p = orc.forward(x.astype(np.float64), E, seed, sigma)
+    return phi, z
+
+
+@pytest.mark.parametrize("seed", [workloads.FASTFOOD_SEED, 0])
+def test_forward_mnist_parity_case(mk, torch_mod, orc, seed):
+    # 64 uniform 28x28 images, n = 1024, E = 1, sigma = 1
+    torch = torch_mod
+    x = workloads.mnist_uniform(64)
+    phi = mk.forward(to_dev(torch, x), 1, seed, 1.0).cpu().numpy()
+    z = mk.project(to_dev(torch, x), 1, seed, 1.0).cpu().numpy()
+    ref_phi, ref_z = _oracle_phi(orc, x, 1, seed, 1.0)
+    assert phi.shape == (64, 2048)
+    assert rowwise_rel(z, ref_z).max() <= FEAT_TOL
+    assert rowwise_rel(phi, ref_phi).max() <= FEAT_TOL
+
+
+@pytest.mark.parametrize("d,E,batch", [(1, 1, 5), (2, 2, 70), (3, 3, 9), (4, 1, 65), (8, 2, 33), (13, 3, 17),
+                                       (16, 1, 64), (32, 2, 66), (33, 1, 31), (64, 3, 40), (100, 2, 19),
+                                       (128, 1, 17), (255, 2, 9), (256, 4, 12), (512, 2, 7), (784, 3, 5),
+                                       (1000, 2, 6), (1024, 2, 3), (2048, 2, 5), (1500, 1, 3), (4096, 2, 3),
+                                       (8192, 1, 2), (16384, 1, 2), (20000, 1, 2), (32768, 2, 2)])
+def test_forward_all_sizes(mk, torch_mod, orc, d, E, batch):
+    torch = torch_mod
+    n = mk.padded_dim(d)
+    sigma = math.sqrt(n)
+    x = workloads.normal(batch, d, seed=d + E)
+    phi = mk.forward(to_dev(torch, x), E, 4242, sigma).cpu().numpy()
+    ref_phi, ref_z = _oracle_phi(orc, x, E, 4242, sigma)
+    assert phi.shape == ref_phi.shape
+    assert rowwise_rel(phi, ref_phi).max() <= FEAT_TOL
+    z = mk.project(to_dev(torch, x), E, 4242, sigma).cpu().numpy()
+    assert rowwise_rel(z, ref_z).max() <= FEAT_TOL
+
+
+def test_forward_metric_workload_sampled(mk, torch_mod, orc):
+    # the full 8192 x 784, E = 16, sigma = 2 workload in the benchmark's launch
+    # configuration: sampled rows against the oracle, every row's norm
+    torch = torch_mod
+    x = workloads.mnist_sparse(8192)
+    phi = mk.forward(to_dev(torch, x), 16, workloads.FASTFOOD_SEED, 2.0)
+    norms = torch.linalg.vector_norm(phi.double(), dim=1).cpu().numpy()
+    assert np.abs(norms - 1.0).max() <= 1e-5
+    rows = np.random.default_rng(3).choice(8192, size=24, replace=False)
+    rows = np.concatenate([rows, [0, 8191]])
+    sub = phi[torch.from_numpy(rows).cuda()].cpu().numpy()
+    ref_phi, _ = _oracle_phi(orc, x[rows], 16, workloads.FASTFOOD_SEED, 2.0)
+    assert rowwise_rel(sub, ref_phi).max() <= FEAT_TOL
+
+
+def test_forward_unaligned_and_empty(mk, torch_mod, orc):
+    torch = torch_mod
+    d, E, batch = 16, 2, 5
+    x = workloads.normal(batch, d, seed=11)
+    buf = torch.zeros(batch * d + 1, dtype=torch.float32, device="cuda")
+    xv = buf[1:].view(batch, d)
+    xv.copy_(to_dev(torch, x))
+    phi = mk.forward(xv, E, 3, 1.0).cpu().numpy()
+    ref, _ = _oracle_phi(orc, x, E, 3, 1.0)
+    assert rowwise_rel(phi, ref).max() <= FEAT_TOL
+    empty = mk.forward(torch.zeros((0, d), device="cuda"), E, 3, 1.0)
+    assert empty.shape == (0, 2 * 16 * E)
+
+
+def test_forward_deterministic(mk, torch_mod):
+    torch = torch_mod
+    x = to_dev(torch, workloads.mnist_sparse(300))
+    a = mk.forward(x, 4, 1, 2.0)
+    b = mk.forward(x, 4, 1, 2.0)
+    assert torch.equal(a, b)
+
+
+def test_invalid_arguments_raise(mk, torch_mod):
+    torch = torch_mod
+    with pytest.raises(mk.MckError):
+        mk.forward(torch.zeros((2, 8), device="cuda"), 1, 1, -1.0)
+    with pytest.raises(mk.MckError):
+        mk.fwht_(torch.zeros((2, 12), device="cuda"))
+
+
+# ------------------------------------------------------------------ backward
+def _oracle_grads(orc, x, dphi, E, seed, sigma):
+    n = orc.padded_dim(x.shape[1])
+    p = orc.params(seed, n, E, sigma)
+    return orc.backward(x.astype(np.float64), dphi.astype(np.float64), n, E, p["B"], p["perm"], p["G"], p["S64"])
+
+
+@pytest.mark.parametrize("d,E,batch,sigma", [(784, 1, 64, 1.0), (784, 3, 37, 2.0), (5, 2, 70, 1.0),
+                                             (32, 2, 33, 4.0), (300, 2, 50, 10.0), (1024, 2, 19, 2.0),
+                                             (2048, 1, 9, 30.0), (4096, 1, 5, 50.0), (32768, 1, 2, 180.0)])
+def test_backward_parity(mk, torch_mod, orc, d, E, batch, sigma):
+    torch = torch_mod
+    n = mk.padded_dim(d)
+    x = workloads.mnist_uniform(batch)[:, :d] if d <= 784 else workloads.normal(batch, d, seed=d)
+    x = np.ascontiguousarray(x)
+    dphi = workloads.grad_features(batch, 2 * n * E)
+    dx, dB, dG, dS = mk.backward(to_dev(torch, x), to_dev(torch, dphi), E, 77, sigma, need_dx=True,
+                                 need_params=True)
+    rx, rB, rG, rS = _oracle_grads(orc, x, dphi, E, 77, sigma)
+    assert rowwise_rel(dx.cpu().numpy(), rx).max() <= FEAT_TOL
+    for got, ref in ((dB, rB), (dG, rG), (dS, rS)):
+        assert tensor_rel(got.cpu().numpy(), ref) <= FEAT_TOL
+
+
+def test_backward_metric_workload_sampled(mk, torch_mod, orc):
+    torch = torch_mod
+    batch, E = 1024, 16
+    x = workloads.mnist_sparse(batch)
+    dphi = workloads.grad_features(batch, 2 * 1024 * E)
+    dx, dB, dG, dS = mk.backward(to_dev(torch, x), to_dev(torch, dphi), E, workloads.FASTFOOD_SEED, 1.0,
+                                 need_dx=True, need_params=True)
+    rows = np.array([0, 5, 511, 1023])
+    rx, _, _, _ = _oracle_grads(orc, x[rows], dphi[rows], E, workloads.FASTFOOD_SEED, 1.0)
+    assert rowwise_rel(dx.cpu().numpy()[rows], rx).max() <= FEAT_TOL
+    _, rB, rG, rS = _oracle_grads(orc, x, dphi, E, workloads.FASTFOOD_SEED, 1.0)
+    for got, ref in ((dB, rB), (dG, rG), (dS, rS)):
+        assert tensor_rel(got.cpu().numpy(), ref) <= FEAT_TOL
+
+
+def test_backward_dx_only_and_determinism(mk, torch_mod):
+    torch = torch_mod
+    x = to_dev(torch, workloads.mnist_uniform(40))
+    dphi = to_dev(torch, workloads.grad_features(40, 2 * 1024 * 2))
+    a = mk.backward(x, dphi, 2, 5, 1.0, need_dx=True, need_params=True)
+    b = mk.backward(x, dphi, 2, 5, 1.0, need_dx=True, need_params=False)
+    c = mk.backward(x, dphi, 2, 5, 1.0, need_dx=True, need_params=True)
+    assert torch.equal(a[0], b[0])
+    for u, v in zip(a, c):
+        assert torch.equal(u, v)
+
+
+def test_explicit_parameters_parity(mk, torch_mod, orc):
+    torch = torch_mod
+    d, E, batch = 100, 2, 21
+    n = 128
+    rng = np.random.default_rng(9)
+    B = rng.standard_normal((E, n)).astype(np.float32)
+    G = rng.standard_normal((E, n)).astype(np.float32)
+    S = (rng.random((E, n)) * 0.05).astype(np.float32)
+    perm = np.stack([rng.permutation(n) for _ in range(E)]).astype(np.int32)
+    x = workloads.normal(batch, d, seed=1)
+    dphi = workloads.grad_features(batch, 2 * n * E)
+    t = lambda a: to_dev(torch, a)
+    phi = mk.forward_p(t(x), t(B), t(perm), t(G), t(S)).cpu().numpy()
+    z = orc.project(x, n, E, B, perm, G, S)
+    assert rowwise_rel(phi, orc.features(z, n, E)).max() <= FEAT_TOL
+    dx, dB, dG, dS = mk.backward_p(t(x), t(dphi), t(B), t(perm), t(G), t(S))
+    rx, rB, rG, rS = orc.backward(x, dphi, n, E, B, perm, G, S)
+    assert rowwise_rel(dx.cpu().numpy(), rx).max() <= FEAT_TOL
+    for got, ref in ((dB, rB), (dG, rG), (dS, rS)):
+        assert tensor_rel(got.cpu().numpy(), ref) <= FEAT_TOL
+
+
+def test_special_case_identity_parameters(mk, torch_mod):
+    # B = 1, Pi = id, G = 1  =>  z = n S xhat, so phi = c [cos(n S x), sin(n S x)]
+    torch = torch_mod
+    d, n, E = 64, 64, 1
+    x = workloads.normal(4, d, seed=2)
+    S = (np.random.default_rng(2).random((E, n)) * 0.01).astype(np.float32)
+    t = lambda a: to_dev(torch, a)
+    phi = mk.forward_p(t(x), t(np.ones((E, n), np.float32)), t(np.arange(n, dtype=np.int32)[None]),
+                       t(np.ones((E, n), np.float32)), t(S)).cpu().numpy()
+    z = n * S[0].astype(np.float64) * x.astype(np.float64)
+    ref = np.concatenate([np.cos(z), np.sin(z)], axis=1) / math.sqrt(n * E)
+    assert rowwise_rel(phi, ref).max() <= FEAT_TOL
+
+
+def test_autograd_function(mk, torch_mod, orc):
+    torch = torch_mod
+    x = to_dev(torch, workloads.mnist_uniform(8)[:, :100]).requires_grad_()
+    phi = mk.fastfood(x, 2, 21, 1.5)
+    w = to_dev(torch, workloads.grad_features(8, phi.shape[1]))
+    (phi * w).sum().backward()
+    rx, _, _, _ = _oracle_grads(orc, x.detach().cpu().numpy(), w.cpu().numpy(), 2, 21, 1.5)
+    assert rowwise_rel(x.grad.cpu().numpy(), rx).max() <= FEAT_TOL
