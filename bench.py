@@ -42,6 +42,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--only", choices=["fwd", "bwd", "all"], default="all",
+                    help="time only one pass (for profiling); the JSON line then lacks the other")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also time a plain 1 GiB device copy and fill (bandwidth calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -95,29 +99,35 @@ def main():
         else:
             fwd()
 
-    for _ in range(args.warmup):
-        run_fwd()
-    torch.cuda.synchronize()
-    log("forward warmup done")
     t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0.record(stream)
-    for _ in range(args.steps):
-        run_fwd()
-    t1.record(stream)
-    torch.cuda.synchronize()
-    fwd_ms = t0.elapsed_time(t1) / args.steps
-    log("forward %.3f ms/step" % fwd_ms)
 
-    for _ in range(max(1, args.warmup // 2)):
-        bwd()
-    torch.cuda.synchronize()
-    t0.record(stream)
-    for _ in range(args.steps):
-        bwd()
-    t1.record(stream)
-    torch.cuda.synchronize()
-    bwd_ms = t0.elapsed_time(t1) / args.steps
-    log("backward %.3f ms/step" % bwd_ms)
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0.record(stream)
+        for _ in range(steps):
+            fn()
+        t1.record(stream)
+        torch.cuda.synchronize()
+        return t0.elapsed_time(t1) / steps
+
+    if args.copy_probe:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        cp_ms = timed(lambda: b.copy_(a), 20, 3)
+        fill_ms = timed(lambda: b.fill_(2.0), 20, 3)
+        log("copy 1 GiB: %.3f ms (%.0f GB/s read+write); fill 1 GiB: %.3f ms (%.0f GB/s)"
+            % (cp_ms, 2 * (1 << 30) / cp_ms / 1e6, fill_ms, (1 << 30) / fill_ms / 1e6))
+        del a, b
+
+    fwd_ms = bwd_ms = float("nan")
+    if args.only in ("fwd", "all"):
+        fwd_ms = timed(run_fwd, args.steps, args.warmup)
+        log("forward %.3f ms/step" % fwd_ms)
+    if args.only in ("bwd", "all"):
+        bwd_ms = timed(bwd, args.steps, max(1, args.warmup // 2))
+        log("backward %.3f ms/step" % bwd_ms)
 
     fwd_vps = BATCH / (fwd_ms * 1e-3)
     fb_ms = fwd_ms + bwd_ms
@@ -128,7 +138,7 @@ def main():
 
     cpu = None
     err = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.only != "bwd":
         import oracle
 
         oracle.build(force=False)
@@ -177,7 +187,14 @@ def main():
                      "frac": fwd_gbs / HBM_PEAK_GBS, "traffic": None},
         "cpu_baseline": cpu,
     }
-    print(json.dumps(line), flush=True)
+    def clean(o):
+        if isinstance(o, dict):
+            return {k: clean(v) for k, v in o.items()}
+        if isinstance(o, float) and not math.isfinite(o):
+            return None
+        return o
+
+    print(json.dumps(clean(line)), flush=True)
 
 
 if __name__ == "__main__":

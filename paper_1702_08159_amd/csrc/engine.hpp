@@ -13,6 +13,10 @@ namespace mck {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 
+// a lane's register array in a (M, P) geometry
+template <typename TT, int M, int P>
+using LaneArr = TT[Geo<M, P>::EPL];
+
 // Orders LDS traffic of one wave: LDS instructions of a wave execute in issue
 // order, so only the compiler must be kept from moving accesses across.
 __device__ __forceinline__ void wave_fence()
@@ -22,36 +26,36 @@ __device__ __forceinline__ void wave_fence()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int M>
+template <int M, int P>
 __device__ __forceinline__ void lds_sync()
 {
-    if constexpr (Geo<M>::kMulti)
+    if constexpr (Geo<M, P>::kMulti)
         __syncthreads();
     else
         wave_fence();
 }
 
 // index bits owned by lane t in layout ID
-template <int M, int ID>
+template <int M, int P, int ID>
 __device__ __forceinline__ uint32_t tpart(uint32_t t)
 {
     uint32_t i = 0;
 #pragma unroll
-    for (int b = 0; b < Geo<M>::T; ++b)
-        i |= ((t >> b) & 1u) << thr_bit(M, ID, b);
+    for (int b = 0; b < Geo<M, P>::T; ++b)
+        i |= ((t >> b) & 1u) << thr_bit(M, P, ID, b);
     return i;
 }
 
 // Radix-2 butterflies (a, b) -> (a + b, a - b) on every register bit of
 // layout ID whose index bit is in MASK: pairs (i, i + 2^k), bit k of i clear,
 // natural (Sylvester) order.
-template <int M, int ID, uint32_t MASK>
-__device__ __forceinline__ void stages(float (&v)[Geo<M>::EPL])
+template <int M, int P, int ID, uint32_t MASK>
+__device__ __forceinline__ void stages(LaneArr<float, M, P>& v)
 {
-    constexpr int P = Geo<M>::P, EPL = Geo<M>::EPL;
+    constexpr int Q = Geo<M, P>::Q, EPL = Geo<M, P>::EPL;
 #pragma unroll
-    for (int b = 0; b < P; ++b) {
-        if (((MASK >> reg_bit(M, ID, b)) & 1u) == 0)
+    for (int b = 0; b < Q; ++b) {
+        if (((MASK >> reg_bit(M, P, ID, b)) & 1u) == 0)
             continue;
 #pragma unroll
         for (int r = 0; r < EPL; ++r) {
@@ -66,36 +70,36 @@ __device__ __forceinline__ void stages(float (&v)[Geo<M>::EPL])
 
 // float4 LDS access is used for the coalesced layout when row regions are
 // 16-byte aligned.
-template <int M, int ID>
-constexpr bool lds_vec() { return ID == 0 && M >= 6; }
+template <int M, int P, int ID>
+constexpr bool lds_vec() { return ID == 0 && M > P; }
 
-template <int M, int ID>
-__device__ __forceinline__ void lds_put(float* buf, uint32_t t, const float (&v)[Geo<M>::EPL])
+template <int M, int P, int ID>
+__device__ __forceinline__ void lds_put(float* buf, uint32_t t, const LaneArr<float, M, P>& v)
 {
-    constexpr int EPL = Geo<M>::EPL;
-    const uint32_t tb = phys(tpart<M, ID>(t));
-    if constexpr (lds_vec<M, ID>()) {
+    constexpr int EPL = Geo<M, P>::EPL;
+    float* base = buf + phys<P>(tpart<M, P, ID>(t));
+    if constexpr (lds_vec<M, P, ID>()) {
 #pragma unroll
         for (int j = 0; j < EPL / 4; ++j) {
             float4 q = make_float4(v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]);
-            *reinterpret_cast<float4*>(buf + (tb ^ phys(rpart(M, ID, 4 * j)))) = q;
+            *reinterpret_cast<float4*>(base + phys<P>(rpart(M, P, ID, 4 * j))) = q;
         }
     } else {
 #pragma unroll
         for (int r = 0; r < EPL; ++r)
-            buf[tb ^ phys(rpart(M, ID, r))] = v[r];
+            base[phys<P>(rpart(M, P, ID, r))] = v[r];
     }
 }
 
-template <int M, int ID>
-__device__ __forceinline__ void lds_get(const float* buf, uint32_t t, float (&v)[Geo<M>::EPL])
+template <int M, int P, int ID>
+__device__ __forceinline__ void lds_get(const float* buf, uint32_t t, LaneArr<float, M, P>& v)
 {
-    constexpr int EPL = Geo<M>::EPL;
-    const uint32_t tb = phys(tpart<M, ID>(t));
-    if constexpr (lds_vec<M, ID>()) {
+    constexpr int EPL = Geo<M, P>::EPL;
+    const float* base = buf + phys<P>(tpart<M, P, ID>(t));
+    if constexpr (lds_vec<M, P, ID>()) {
 #pragma unroll
         for (int j = 0; j < EPL / 4; ++j) {
-            const float4 q = *reinterpret_cast<const float4*>(buf + (tb ^ phys(rpart(M, ID, 4 * j))));
+            const float4 q = *reinterpret_cast<const float4*>(base + phys<P>(rpart(M, P, ID, 4 * j)));
             v[4 * j] = q.x;
             v[4 * j + 1] = q.y;
             v[4 * j + 2] = q.z;
@@ -104,156 +108,185 @@ __device__ __forceinline__ void lds_get(const float* buf, uint32_t t, float (&v)
     } else {
 #pragma unroll
         for (int r = 0; r < EPL; ++r)
-            v[r] = buf[tb ^ phys(rpart(M, ID, r))];
+            v[r] = base[phys<P>(rpart(M, P, ID, r))];
     }
 }
 
 // Move a vector from layout X to layout Y through the row's LDS region.
-template <int M, int X, int Y>
-__device__ __forceinline__ void relayout(float (&v)[Geo<M>::EPL], float* buf, uint32_t t)
+template <int M, int P, int X, int Y>
+__device__ __forceinline__ void relayout(LaneArr<float, M, P>& v, float* buf, uint32_t t)
 {
-    lds_put<M, X>(buf, t, v);
-    lds_sync<M>();
-    lds_get<M, Y>(buf, t, v);
-    lds_sync<M>();
+    lds_put<M, P, X>(buf, t, v);
+    lds_sync<M, P>();
+    lds_get<M, P, Y>(buf, t, v);
+    lds_sync<M, P>();
 }
 
 // H v, starting in layout 0 and ending in the last chunk layout.
-template <int M>
-__device__ __forceinline__ void fwht_up(float (&v)[Geo<M>::EPL], float* buf, uint32_t t)
+template <int M, int P>
+__device__ __forceinline__ void fwht_up(LaneArr<float, M, P>& v, float* buf, uint32_t t)
 {
-    constexpr int K = Geo<M>::K;
-    stages<M, 0, fwd1_new_bits(M, 0)>(v);
+    constexpr int K = Geo<M, P>::K;
+    stages<M, P, 0, up_new_bits(M, P, 0)>(v);
     if constexpr (K >= 1) {
-        relayout<M, 0, 1>(v, buf, t);
-        stages<M, 1, fwd1_new_bits(M, 1)>(v);
+        relayout<M, P, 0, 1>(v, buf, t);
+        stages<M, P, 1, up_new_bits(M, P, 1)>(v);
     }
     if constexpr (K >= 2) {
-        relayout<M, 1, 2>(v, buf, t);
-        stages<M, 2, fwd1_new_bits(M, 2)>(v);
+        relayout<M, P, 1, 2>(v, buf, t);
+        stages<M, P, 2, up_new_bits(M, P, 2)>(v);
     }
+    if constexpr (K >= 3) {
+        relayout<M, P, 2, 3>(v, buf, t);
+        stages<M, P, 3, up_new_bits(M, P, 3)>(v);
+    }
+    static_assert(K <= 3, "at most three chunk layouts");
 }
 
 // H v, starting in the last chunk layout and ending in layout 0.
-template <int M>
-__device__ __forceinline__ void fwht_down(float (&v)[Geo<M>::EPL], float* buf, uint32_t t)
+template <int M, int P>
+__device__ __forceinline__ void fwht_down(LaneArr<float, M, P>& v, float* buf, uint32_t t)
 {
-    constexpr int K = Geo<M>::K;
-    if constexpr (K == 0) {
-        stages<M, 0, fwd2_new_bits(M, 0, 0)>(v);
-    } else if constexpr (K == 1) {
-        stages<M, 1, fwd2_new_bits(M, 1, 1)>(v);
-        relayout<M, 1, 0>(v, buf, t);
-        stages<M, 0, fwd2_new_bits(M, 1, 0)>(v);
-    } else {
-        stages<M, 2, fwd2_new_bits(M, 2, 2)>(v);
-        relayout<M, 2, 1>(v, buf, t);
-        stages<M, 1, fwd2_new_bits(M, 2, 1)>(v);
-        relayout<M, 1, 0>(v, buf, t);
-        stages<M, 0, fwd2_new_bits(M, 2, 0)>(v);
+    constexpr int K = Geo<M, P>::K;
+    if constexpr (K >= 3) {
+        stages<M, P, 3, down_new_bits(M, P, K, 3)>(v);
+        relayout<M, P, 3, 2>(v, buf, t);
     }
+    if constexpr (K >= 2) {
+        stages<M, P, 2, down_new_bits(M, P, K, 2)>(v);
+        relayout<M, P, 2, 1>(v, buf, t);
+    }
+    if constexpr (K >= 1) {
+        stages<M, P, 1, down_new_bits(M, P, K, 1)>(v);
+        relayout<M, P, 1, 0>(v, buf, t);
+    }
+    stages<M, P, 0, down_new_bits(M, P, K, 0)>(v);
 }
 
-// ------------------------------------------------------------------ HBM access
-// Coalesced layout: register r of lane t holds index tpart(t) | rpart(0, r);
-// registers 4j..4j+3 are consecutive indices (M >= 2).
+// ------------------------------------------------------------------ buffer access
+// HBM traffic of the hot kernels goes through buffer instructions: one
+// uniform resource (base, byte range) per array lives in SGPRs, each lane
+// keeps a 32-bit byte offset that is reused across expansions (the
+// expansion's offset rides in the scalar offset), chunk offsets are
+// immediates, and offsets past the range read as zero (hardware range
+// check), which pads rows to n without branches.  Every array a launch
+// touches is kept below 2^31 bytes by the host.
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
 
-template <int M>
-__device__ __forceinline__ uint32_t coal_index(uint32_t t, int r)
+constexpr uint32_t kOutOfRange = 0x7ffffff0u;  // any offset >= every range
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void* p, uint32_t bytes)
 {
-    return tpart<M, 0>(t) | rpart(M, 0, r);
+    // word 3 of the descriptor for gfx9-family raw (untyped) buffers
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
 }
 
-// Load one row of length d (zero-padded to n) into the coalesced layout.
-template <int M, bool VEC>
-__device__ __forceinline__ void load_row(float (&v)[Geo<M>::EPL], const float* __restrict__ src, int d,
-                                         uint32_t t, bool valid)
+__device__ __forceinline__ void bload4(float* dst, rsrc_t r, uint32_t voff, uint32_t soff)
 {
-    constexpr int EPL = Geo<M>::EPL;
-    const uint32_t tb = tpart<M, 0>(t);
+    const v4i q = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0);
+    dst[0] = __int_as_float(q.x);
+    dst[1] = __int_as_float(q.y);
+    dst[2] = __int_as_float(q.z);
+    dst[3] = __int_as_float(q.w);
+}
+
+__device__ __forceinline__ void bload4u(uint32_t* dst, rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    const v4i q = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0);
+    dst[0] = (uint32_t)q.x;
+    dst[1] = (uint32_t)q.y;
+    dst[2] = (uint32_t)q.z;
+    dst[3] = (uint32_t)q.w;
+}
+
+__device__ __forceinline__ float bload1(rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+
+// 128-bit stores take the whole byte offset in the VGPR (constant parts go
+// to the instruction's immediate field) and a literal zero scalar offset.
+// A store wider than 64 bits reads its data VGPRs after issue; the compiler
+// separates it from a VALU write of those VGPRs only when the scalar offset
+// is not a register, and on gfx950 we observed the overwritten value reach
+// memory when it was one.
+__device__ __forceinline__ void bstore4_nt(rsrc_t r, uint32_t voff, float a, float b, float c, float d)
+{
+    const v4i q = {__float_as_int(a), __float_as_int(b), __float_as_int(c), __float_as_int(d)};
+    __builtin_amdgcn_raw_buffer_store_b128(q, r, (int)voff, 0, 2);  // streaming (non-temporal)
+}
+
+__device__ __forceinline__ void bstore4(rsrc_t r, uint32_t voff, float a, float b, float c, float d)
+{
+    const v4i q = {__float_as_int(a), __float_as_int(b), __float_as_int(c), __float_as_int(d)};
+    __builtin_amdgcn_raw_buffer_store_b128(q, r, (int)voff, 0, 0);
+}
+
+__device__ __forceinline__ void bstore1(rsrc_t r, uint32_t voff, uint32_t soff, float a)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(a), r, (int)voff, (int)soff, 0);
+}
+
+// Row of length d at byte offset rowoff (zero-padded to n) into the
+// coalesced layout; invalid rows read as zero.
+template <int M, int P, bool VEC>
+__device__ __forceinline__ void bload_row(LaneArr<float, M, P>& v, rsrc_t r, uint32_t rowoff, int d, uint32_t t,
+                                          bool valid)
+{
+    constexpr int EPL = Geo<M, P>::EPL;
+    const uint32_t tb = tpart<M, P, 0>(t);
     if constexpr (VEC) {
 #pragma unroll
         for (int j = 0; j < EPL / 4; ++j) {
-            const uint32_t i0 = tb | rpart(M, 0, 4 * j);
-            float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (valid && (int)i0 < d)
-                q = *reinterpret_cast<const float4*>(src + i0);
-            v[4 * j] = q.x;
-            v[4 * j + 1] = q.y;
-            v[4 * j + 2] = q.z;
-            v[4 * j + 3] = q.w;
+            const uint32_t i0 = tb | rpart(M, P, 0, 4 * j);
+            const uint32_t off = (valid && (int)i0 < d) ? rowoff + 4u * i0 : kOutOfRange;
+            bload4(&v[4 * j], r, off, 0);
         }
     } else {
 #pragma unroll
-        for (int r = 0; r < EPL; ++r) {
-            const uint32_t i = tb | rpart(M, 0, r);
-            v[r] = (valid && (int)i < d) ? src[i] : 0.f;
+        for (int k = 0; k < EPL; ++k) {
+            const uint32_t i = tb | rpart(M, P, 0, k);
+            v[k] = bload1(r, (valid && (int)i < d) ? rowoff + 4u * i : kOutOfRange, 0);
         }
     }
 }
 
-// Load n parameter values (natural order, n % 4 == 0 when M >= 2) into the
-// coalesced layout.
-template <int M>
-__device__ __forceinline__ void load_param_coal(float (&v)[Geo<M>::EPL], const float* __restrict__ src, uint32_t t)
+// n values in natural order at scalar byte offset soff, coalesced layout.
+template <int M, int P>
+__device__ __forceinline__ void bload_coal(LaneArr<float, M, P>& v, rsrc_t r, uint32_t soff, uint32_t t)
 {
-    constexpr int EPL = Geo<M>::EPL;
-    const uint32_t tb = tpart<M, 0>(t);
+    constexpr int EPL = Geo<M, P>::EPL;
+    const uint32_t tb = 4u * tpart<M, P, 0>(t);
     if constexpr (M >= 2) {
 #pragma unroll
-        for (int j = 0; j < EPL / 4; ++j) {
-            const float4 q = *reinterpret_cast<const float4*>(src + (tb | rpart(M, 0, 4 * j)));
-            v[4 * j] = q.x;
-            v[4 * j + 1] = q.y;
-            v[4 * j + 2] = q.z;
-            v[4 * j + 3] = q.w;
-        }
+        for (int j = 0; j < EPL / 4; ++j)
+            bload4(&v[4 * j], r, tb, soff + 4u * rpart(M, P, 0, 4 * j));
     } else {
 #pragma unroll
-        for (int r = 0; r < EPL; ++r)
-            v[r] = src[tb | rpart(M, 0, r)];
+        for (int k = 0; k < EPL; ++k)
+            v[k] = bload1(r, tb, soff + 4u * rpart(M, P, 0, k));
     }
 }
 
-// Load EPL consecutive values owned by lane t from a lane-major array
-// (element r of lane t at src[t * EPL + r]).
-template <int M, typename TT>
-__device__ __forceinline__ void load_lane_major(TT (&v)[Geo<M>::EPL], const TT* __restrict__ src, uint32_t t)
+// EPL consecutive 32-bit values of lane q (element k at q * EPL + k).
+template <int M, int P, typename TT>
+__device__ __forceinline__ void bload_lane(LaneArr<TT, M, P>& v, rsrc_t r, uint32_t soff, uint32_t q)
 {
-    constexpr int EPL = Geo<M>::EPL;
-    const TT* p = src + (size_t)t * EPL;
-    if constexpr (EPL % 4 == 0 && sizeof(TT) == 4) {
+    constexpr int EPL = Geo<M, P>::EPL;
+    const uint32_t base = 4u * q * EPL;
+    if constexpr (EPL % 4 == 0) {
 #pragma unroll
         for (int j = 0; j < EPL / 4; ++j) {
-            const uint4 q = *reinterpret_cast<const uint4*>(p + 4 * j);
-            v[4 * j] = __builtin_bit_cast(TT, q.x);
-            v[4 * j + 1] = __builtin_bit_cast(TT, q.y);
-            v[4 * j + 2] = __builtin_bit_cast(TT, q.z);
-            v[4 * j + 3] = __builtin_bit_cast(TT, q.w);
+            if constexpr (sizeof(TT) == 4 && TT(0.5f) == TT(0))  // integer
+                bload4u(reinterpret_cast<uint32_t*>(&v[4 * j]), r, base, soff + 16u * j);
+            else
+                bload4(reinterpret_cast<float*>(&v[4 * j]), r, base, soff + 16u * j);
         }
     } else {
 #pragma unroll
-        for (int r = 0; r < EPL; ++r)
-            v[r] = p[r];
-    }
-}
-
-// Store the coalesced layout to dst[i] for all n indices (VEC: float4).
-template <int M, bool VEC>
-__device__ __forceinline__ void store_coal(float* __restrict__ dst, uint32_t t, const float (&v)[Geo<M>::EPL])
-{
-    constexpr int EPL = Geo<M>::EPL;
-    const uint32_t tb = tpart<M, 0>(t);
-    if constexpr (VEC) {
-#pragma unroll
-        for (int j = 0; j < EPL / 4; ++j) {
-            const v4f q = {v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]};
-            __builtin_nontemporal_store(q, reinterpret_cast<v4f*>(dst + (tb | rpart(M, 0, 4 * j))));
-        }
-    } else {
-#pragma unroll
-        for (int r = 0; r < EPL; ++r)
-            dst[tb | rpart(M, 0, r)] = v[r];
+        for (int k = 0; k < EPL; ++k)
+            v[k] = __builtin_bit_cast(TT, bload1(r, base, soff + 4u * k));
     }
 }
 

@@ -3,16 +3,16 @@
 //   k_fwht      in-place batched H v (section "Fast Walsh Hadamard")
 //   k_forward   phi = c [cos z, sin z], z = S H G Pi H B xhat for every
 //               expansion (equations mckernel and mcfeatures), fused: one HBM
-//               read of x per row, one HBM write of phi, everything else in
-//               registers and LDS
+//               read of x per row and expansion chunk, one HBM write of phi,
+//               everything else in registers and LDS
 //   k_backward  adjoint of the same chain (H is symmetric, Pi^T a scatter),
 //               recomputing the forward instead of storing it
 //   k_reduce    fixed-order sum of the backward's per-block partials
-//   k_derive    parameter copies in the kernels' register layout
+//   k_derive    parameter copies in the kernels' register layouts
 //
 // Vectors are spread over lanes as described in layout.hpp; each lane keeps
-// 32 elements in VGPRs and butterflies on register bits are lane-local, so
-// the transform costs 5 add/sub per element per layout and one LDS round trip
+// 2^P elements in VGPRs, butterflies on register bits are lane-local, and a
+// transform costs P add/sub per element per layout plus one LDS round trip
 // per change of layout.
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -24,12 +24,28 @@
 namespace mck {
 namespace {
 
+constexpr int kXcds = 8;
+
+// Register bits per layout.  The forward keeps four arrays of the next
+// expansion in flight while it stores the current one, which fits the
+// 128-VGPR budget of 4 waves per SIMD only at 16 elements per lane; the
+// transform kernel has no such pipeline and uses 32.  n = 2^15 needs 32 so
+// that one row fits in a 1024-thread workgroup.
+constexpr int fwd_p(int M) { return M >= 15 ? 5 : 4; }
+constexpr int bwd_p(int M) { return M >= 15 ? 5 : 4; }
+constexpr int kFwhtP = 5;
+
+// Every buffer range a launch uses stays below 2^31 bytes.
+constexpr int64_t kRangeLimit = (int64_t(1) << 31) - 4096;
+
 // ------------------------------------------------------------------ H v
 template <int M, bool VEC>
-__global__ void __launch_bounds__(Geo<M>::BLOCK) k_fwht(float* __restrict__ data, int64_t batch)
+__global__ void __launch_bounds__((Geo<M, kFwhtP>::BLOCK))
+    k_fwht(float* __restrict__ data, uint32_t bytes, int64_t batch)
 {
-    using g = Geo<M>;
-    constexpr int K = g::K;
+    constexpr int P = kFwhtP;
+    using g = Geo<M, P>;
+    constexpr int K = g::K, EPL = g::EPL;
     __shared__ float lds[g::LDS_FLOATS];
     const uint32_t lane = threadIdx.x;
     const uint32_t grp = g::kMulti ? 0u : lane >> g::T;
@@ -37,123 +53,226 @@ __global__ void __launch_bounds__(Geo<M>::BLOCK) k_fwht(float* __restrict__ data
     const int64_t row = (int64_t)blockIdx.x * g::RPB + grp;
     const bool valid = row < batch;
     float* buf = lds + grp * g::STRIDE;
-    float* src = data + (valid ? row : 0) * (int64_t)g::n;
-    float v[g::EPL];
-    load_row<M, VEC>(v, src, g::n, t, valid);
-    fwht_up<M>(v, buf, t);
+    const rsrc_t r = make_rsrc(data, bytes);
+    const uint32_t rowoff = valid ? (uint32_t)(row * g::n) * 4u : kOutOfRange;
+    float v[EPL];
+    bload_row<M, P, VEC>(v, r, rowoff, g::n, t, valid);
+    fwht_up<M, P>(v, buf, t);
     if constexpr (K >= 1)
-        relayout<M, K, 0>(v, buf, t);
-    if (valid)
-        store_coal<M, VEC>(src, t, v);
+        relayout<M, P, K, 0>(v, buf, t);
+    const uint32_t tb4 = 4u * tpart<M, P, 0>(t);
+    if constexpr (VEC) {
+#pragma unroll
+        for (int j = 0; j < EPL / 4; ++j)
+            bstore4(r, rowoff + tb4 + 4u * rpart(M, P, 0, 4 * j), v[4 * j], v[4 * j + 1], v[4 * j + 2],
+                    v[4 * j + 3]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < EPL; ++k)
+            bstore1(r, rowoff + tb4, 4u * rpart(M, P, 0, k), v[k]);
+    }
 }
 
 // ------------------------------------------------------------------ forward
-// One block holds RPB rows (one wave) or one row (n >= 4096, several waves).
-// For each expansion e: v = B_e xhat; H; Pi gather through LDS fused with the
-// G_e product; H; z = S_e v; phi blocks written with float4 stores.
-template <int M, bool VEC, bool TRIG>
-__global__ void __launch_bounds__(Geo<M>::BLOCK)
-    k_forward(const float* __restrict__ x, int64_t batch, int d, int E, const float* __restrict__ B,
-              const uint32_t* __restrict__ goff, const float* __restrict__ Gk, const float* __restrict__ Sx,
-              FeatCoef coef, float* __restrict__ out)
+// A block holds RPB rows (one wave) or one row (several waves) and a chunk of
+// `echunk` expansions.  Blocks are numbered so that all chunks of one row
+// group land on the same XCD (blocks are dealt to the 8 XCDs round robin),
+// which keeps the row's x in that XCD's L2 for the later chunks.
+struct ChunkMap {
+    int64_t group;  // row group
+    int chunk;      // expansion chunk
+};
+
+__device__ __forceinline__ ChunkMap chunk_map(int nchunks)
 {
-    using g = Geo<M>;
+    const int64_t b = blockIdx.x;
+    const int64_t q = b / kXcds;
+    ChunkMap m;
+    m.chunk = (int)(q % nchunks);
+    m.group = (q / nchunks) * kXcds + (b % kXcds);
+    return m;
+}
+
+// Per expansion e: v = B_e xhat; H; scale by G_e in source order and write to
+// LDS; gather v[perm[i]]; H; z = S_e v; phi blocks written with float4
+// streaming stores.  On gfx9-family GPUs the vector-memory counter counts
+// stores as well as loads, so a load issued after an expansion's 2n-float
+// feature stores cannot complete (be waited for) before those stores do.
+// With PIPE, all loads of expansion e+1 are therefore issued before the
+// stores of e; the stores then drain while e+1 computes.
+template <int M, int P, bool VEC, bool TRIG>
+__global__ void __launch_bounds__((Geo<M, P>::BLOCK), (Geo<M, P>::kMulti ? 1 : 4))
+    k_forward(const float* __restrict__ x, uint32_t x_bytes, int64_t batch, int d, int E, int echunk, int nchunks,
+              const float* __restrict__ B, const uint32_t* __restrict__ goff, const float* __restrict__ Gs,
+              const float* __restrict__ Sx, uint32_t par_bytes, uint32_t goff_bytes, FeatCoef coef,
+              float* __restrict__ out, uint32_t out_bytes)
+{
+    using g = Geo<M, P>;
     constexpr int EPL = g::EPL, n = g::n, K = g::K;
+    constexpr bool PIPE = (P == 4);
     __shared__ float lds[g::LDS_FLOATS];
+    const ChunkMap cm = chunk_map(nchunks);
+    if (cm.group * g::RPB >= batch)
+        return;  // whole block past the end (uniform)
     const uint32_t lane = threadIdx.x;
     const uint32_t grp = g::kMulti ? 0u : lane >> g::T;
     const uint32_t t = g::kMulti ? lane : (lane & (g::LPR - 1));
-    const int64_t row = (int64_t)blockIdx.x * g::RPB + grp;
+    const int64_t row = cm.group * g::RPB + grp;
     const bool valid = row < batch;
+    const int e0 = cm.chunk * echunk;
+    const int e1 = e0 + echunk < E ? e0 + echunk : E;
     float* buf = lds + grp * g::STRIDE;
-    const char* lbytes = reinterpret_cast<const char*>(buf);
+    const char* lbytes = reinterpret_cast<const char*>(lds);  // gather offsets include the row region
+    constexpr uint32_t kGoffE = (uint32_t)g::RPB * n;
 
-    float xh[EPL];
-    load_row<M, VEC>(xh, x + (valid ? row : 0) * (int64_t)d, d, t, valid);
-    const int64_t nE = (int64_t)n * E;
-    float* orow = out + (valid ? row : 0) * (TRIG ? 2 * nE : nE);
+    const rsrc_t rx = make_rsrc(x, x_bytes), rB = make_rsrc(B, par_bytes), rG = make_rsrc(Gs, par_bytes);
+    const rsrc_t rS = make_rsrc(Sx, par_bytes), rO = make_rsrc(goff, goff_bytes), rY = make_rsrc(out, out_bytes);
+    const uint32_t nE = (uint32_t)n * (uint32_t)E;
+    const uint32_t xoff = valid ? (uint32_t)(row * d) * 4u : 0u;
+    const uint32_t ooff = valid ? (uint32_t)(row * (TRIG ? 2 * (int64_t)nE : (int64_t)nE)) * 4u : kOutOfRange;
+    const uint32_t yoff = ooff + 4u * tpart<M, P, 0>(t);  // this lane's output base
 
-    for (int e = 0; e < E; ++e) {
-        const int64_t eo = (int64_t)e * n;
+    // PIPE: x stays in VGPRs; B, G' and the gather offsets of expansion e+1
+    // are loaded before the stores of e.  S is loaded after those stores: it
+    // is first needed after the second transform, by when they have drained.
+    float xh[EPL], bn[EPL], gs[EPL], sx[EPL];
+    uint32_t off[EPL];
+    if constexpr (PIPE) {
+        bload_row<M, P, VEC>(xh, rx, xoff, d, t, valid);
+        bload_coal<M, P>(bn, rB, 4u * (uint32_t)e0 * n, t);
+        bload_lane<M, P, float>(gs, rG, 4u * (uint32_t)e0 * n, t);
+        bload_lane<M, P, uint32_t>(off, rO, 4u * (uint32_t)e0 * kGoffE, lane);
+    }
+
+    for (int e = e0; e < e1; ++e) {
+        const uint32_t eo4 = 4u * (uint32_t)e * n;
         float v[EPL];
-        load_param_coal<M>(v, B + eo, t);
-#pragma unroll
-        for (int r = 0; r < EPL; ++r)
-            v[r] *= xh[r];
-        fwht_up<M>(v, buf, t);
-
-        // Pi: v1 to LDS in natural order, then gather v1[perm[i]] * G[i]
-        lds_put<M, K>(buf, t, v);
-        lds_sync<M>();
-        uint32_t off[EPL];
-        load_lane_major<M, uint32_t>(off, goff + eo, t);
-        float gk[EPL];
-        load_lane_major<M, float>(gk, Gk + eo, t);
-#pragma unroll
-        for (int r = 0; r < EPL; ++r)
-            v[r] = *reinterpret_cast<const float*>(lbytes + off[r]) * gk[r];
-        lds_sync<M>();
-
-        fwht_down<M>(v, buf, t);
-
-        float sx[EPL];
-        load_param_coal<M>(sx, Sx + eo, t);
-        if constexpr (TRIG) {
-            float co[EPL], si[EPL];
+        if constexpr (PIPE) {
 #pragma unroll
             for (int r = 0; r < EPL; ++r)
-                cossin_hturn(v[r] * sx[r], coef, co[r], si[r]);
-            if (valid) {
-                store_coal<M, VEC>(orow + eo, t, co);
-                store_coal<M, VEC>(orow + nE + eo, t, si);
+                v[r] = xh[r] * bn[r];
+            bload_coal<M, P>(sx, rS, eo4, t);
+        } else {
+            float xn[EPL];
+            bload_row<M, P, VEC>(xn, rx, xoff, d, t, valid);
+            bload_coal<M, P>(v, rB, eo4, t);
+            bload_lane<M, P, float>(gs, rG, eo4, t);
+            bload_lane<M, P, uint32_t>(off, rO, 4u * (uint32_t)e * kGoffE, lane);
+#pragma unroll
+            for (int r = 0; r < EPL; ++r)
+                v[r] *= xn[r];
+        }
+
+        fwht_up<M, P>(v, buf, t);
+
+        // G Pi v1 = Pi (G' v1) with G' = G in source order: scale, write v1 to
+        // LDS in natural order, gather v1[perm[i]]
+#pragma unroll
+        for (int r = 0; r < EPL; ++r)
+            v[r] *= gs[r];
+        lds_put<M, P, K>(buf, t, v);
+        lds_sync<M, P>();
+#pragma unroll
+        for (int r = 0; r < EPL; ++r)
+            v[r] = *reinterpret_cast<const float*>(lbytes + off[r]);
+        lds_sync<M, P>();
+        if constexpr (!PIPE)
+            bload_coal<M, P>(sx, rS, eo4, t);
+
+        fwht_down<M, P>(v, buf, t);
+#pragma unroll
+        for (int r = 0; r < EPL; ++r)
+            v[r] *= sx[r];
+
+        if constexpr (PIPE) {
+            if (e + 1 < e1) {
+                const uint32_t en4 = eo4 + 4u * n;
+                bload_coal<M, P>(bn, rB, en4, t);
+                bload_lane<M, P, float>(gs, rG, en4, t);
+                bload_lane<M, P, uint32_t>(off, rO, 4u * (uint32_t)(e + 1) * kGoffE, lane);
+            }
+        }
+        if constexpr (TRIG) {
+            if constexpr (M >= 2) {
+                // four features at a time, straight to HBM (cos block, sin block)
+                const uint32_t yc = yoff + eo4, ys = yc + 4u * nE;
+#pragma unroll
+                for (int j = 0; j < EPL / 4; ++j) {
+                    float c4[4], s4[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        cossin_hturn(v[4 * j + k], coef, c4[k], s4[k]);
+                    const uint32_t so = 4u * rpart(M, P, 0, 4 * j);
+                    bstore4_nt(rY, yc + so, c4[0], c4[1], c4[2], c4[3]);
+                    bstore4_nt(rY, ys + so, s4[0], s4[1], s4[2], s4[3]);
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < EPL; ++k) {
+                    float c1, s1;
+                    cossin_hturn(v[k], coef, c1, s1);
+                    const uint32_t so = eo4 + 4u * rpart(M, P, 0, k);
+                    bstore1(rY, yoff, so, c1);
+                    bstore1(rY, yoff, 4u * nE + so, s1);
+                }
             }
         } else {
 #pragma unroll
-            for (int r = 0; r < EPL; ++r)
-                v[r] *= sx[r];
-            if (valid)
-                store_coal<M, VEC>(orow + eo, t, v);
+            for (int k = 0; k < EPL; ++k)
+                bstore1(rY, yoff, eo4 + 4u * rpart(M, P, 0, k), v[k]);
         }
     }
 }
 
 // ------------------------------------------------------------------ backward
-// Block = NW waves (or one multi-wave row group for n >= 4096).  The loop runs
-// over expansions outermost so that the dS, dG, dB contributions of all rows
-// a block owns accumulate in VGPRs; at the end of each expansion they are
-// summed across the block in a fixed order and written as the block's
-// partial.  dx accumulates over expansions in place (each row has one owner).
+// Block = NW waves, one row per wave and pass (or one multi-wave row for
+// large n).  Expansions are the outer loop so that the dS, dG, dB
+// contributions of all rows a block owns accumulate in VGPRs; at the end of
+// each expansion they are summed across the block in a fixed order and
+// written as the block's partial.  dx accumulates over expansions in place
+// (every row has one owner, so the read-modify-write is ordered).
 constexpr int kBwdWaves = 8;
 
 template <int M>
 struct BwdGeo {
-    static constexpr int NW = Geo<M>::kMulti ? 1 : kBwdWaves;
-    static constexpr int THREADS = Geo<M>::BLOCK * NW;
-    static constexpr int ROWS = NW * Geo<M>::RPB;  // rows per block per pass
+    static constexpr int P = bwd_p(M);
+    using g = Geo<M, P>;
+    static constexpr int NW = g::kMulti ? 1 : kBwdWaves;
+    static constexpr int THREADS = g::BLOCK * NW;
+    static constexpr int ROWS = NW * g::RPB;  // rows per block per pass
 };
 
 template <int M, bool VEC, bool PARAMS>
 __global__ void __launch_bounds__(BwdGeo<M>::THREADS)
-    k_backward(const float* __restrict__ x, const float* __restrict__ dphi, int64_t batch, int d, int E,
-               const float* __restrict__ B, const uint32_t* __restrict__ goff, const float* __restrict__ Gk,
-               const float* __restrict__ S32, const float* __restrict__ Sh, FeatCoef coef, float* __restrict__ dx,
+    k_backward(const float* __restrict__ x, uint32_t x_bytes, const float* __restrict__ dphi, uint32_t dphi_bytes,
+               int64_t batch, int d, int E, const float* __restrict__ B, const uint32_t* __restrict__ goff,
+               const float* __restrict__ Gk, const float* __restrict__ S32, const float* __restrict__ Sh,
+               uint32_t par_bytes, uint32_t goff_bytes, FeatCoef coef, float* __restrict__ dx,
                float* __restrict__ partial, int passes)
 {
-    using g = Geo<M>;
     using bg = BwdGeo<M>;
+    constexpr int P = bg::P;
+    using g = Geo<M, P>;
     constexpr int EPL = g::EPL, n = g::n, K = g::K;
+    constexpr uint32_t kGoffE = (uint32_t)g::RPB * n;
     __shared__ float lds[bg::NW * g::LDS_FLOATS];
     const uint32_t wave = g::kMulti ? 0u : threadIdx.x / 64u;
     const uint32_t lane = g::kMulti ? threadIdx.x : threadIdx.x % 64u;
     const uint32_t grp = g::kMulti ? 0u : lane >> g::T;
     const uint32_t t = g::kMulti ? lane : (lane & (g::LPR - 1));
-    float* buf = lds + wave * g::LDS_FLOATS + grp * g::STRIDE;
-    const char* lbytes = reinterpret_cast<const char*>(buf);
-    const int64_t nE = (int64_t)n * E;
-    const uint32_t ct = tpart<M, 0>(t);
+    float* wbuf = lds + wave * g::LDS_FLOATS;
+    float* buf = wbuf + grp * g::STRIDE;
+    char* lbytes = reinterpret_cast<char*>(wbuf);  // gather offsets include the row region
+    const uint32_t nE = (uint32_t)n * (uint32_t)E;
+    const uint32_t ct = tpart<M, P, 0>(t);
+
+    const rsrc_t rx = make_rsrc(x, x_bytes), rD = make_rsrc(dphi, dphi_bytes), rB = make_rsrc(B, par_bytes);
+    const rsrc_t rG = make_rsrc(Gk, par_bytes), rS = make_rsrc(S32, par_bytes), rH = make_rsrc(Sh, par_bytes);
+    const rsrc_t rO = make_rsrc(goff, goff_bytes), rX = make_rsrc(dx, x_bytes);
 
     for (int e = 0; e < E; ++e) {
-        const int64_t eo = (int64_t)e * n;
+        const uint32_t eo4 = 4u * (uint32_t)e * n;
+        const uint32_t go4 = 4u * (uint32_t)e * kGoffE;
         float aS[EPL], aG[EPL], aB[EPL];
         if constexpr (PARAMS) {
 #pragma unroll
@@ -163,60 +282,65 @@ __global__ void __launch_bounds__(BwdGeo<M>::THREADS)
         for (int p = 0; p < passes; ++p) {
             const int64_t row = ((int64_t)blockIdx.x * passes + p) * bg::ROWS + wave * g::RPB + grp;
             const bool valid = row < batch;
-            const float* xr = x + (valid ? row : 0) * (int64_t)d;
-            const float* gr = dphi + (valid ? row : 0) * 2 * nE;
+            const uint32_t xoff = valid ? (uint32_t)(row * d) * 4u : 0u;
+            const uint32_t goffr = valid ? (uint32_t)(row * 2 * (int64_t)nE) * 4u : 0u;
 
             // forward recompute: v1 = H B xhat, w = Pi v1, v3 = H G w
             float v[EPL];
             {
                 float xh[EPL];
-                load_row<M, VEC>(xh, xr, d, t, valid);
-                load_param_coal<M>(v, B + eo, t);
+                bload_row<M, P, VEC>(xh, rx, xoff, d, t, valid);
+                bload_coal<M, P>(v, rB, eo4, t);
 #pragma unroll
                 for (int r = 0; r < EPL; ++r)
                     v[r] *= xh[r];
             }
-            fwht_up<M>(v, buf, t);
-            lds_put<M, K>(buf, t, v);
-            lds_sync<M>();
             uint32_t off[EPL];
-            load_lane_major<M, uint32_t>(off, goff + eo, t);
+            bload_lane<M, P, uint32_t>(off, rO, go4, lane);
+            fwht_up<M, P>(v, buf, t);
+            lds_put<M, P, K>(buf, t, v);
+            lds_sync<M, P>();
             float w[EPL];
 #pragma unroll
             for (int r = 0; r < EPL; ++r)
                 w[r] = *reinterpret_cast<const float*>(lbytes + off[r]);
-            lds_sync<M>();
+            lds_sync<M, P>();
             {
                 float gk[EPL];
-                load_lane_major<M, float>(gk, Gk + eo, t);
+                bload_lane<M, P, float>(gk, rG, eo4, t);
 #pragma unroll
                 for (int r = 0; r < EPL; ++r)
                     v[r] = w[r] * gk[r];
             }
-            fwht_down<M>(v, buf, t);
+            fwht_down<M, P>(v, buf, t);
 
             // dz = c (-sin z dphi_cos + cos z dphi_sin); dS += dz v3; g3 = S dz
             {
-                float sh[EPL], s32[EPL], gc[EPL], gs[EPL];
-                load_param_coal<M>(sh, Sh + eo, t);
-                load_param_coal<M>(s32, S32 + eo, t);
-                load_row<M, VEC>(gc, gr + eo, n, t, valid);
-                load_row<M, VEC>(gs, gr + nE + eo, n, t, valid);
+                float gc[EPL], gsn[EPL];
+                bload_row<M, P, VEC>(gc, rD, goffr + eo4, n, t, valid);
+                bload_row<M, P, VEC>(gsn, rD, goffr + 4u * nE + eo4, n, t, valid);
+                float sh[EPL];
+                bload_coal<M, P>(sh, rH, eo4, t);
 #pragma unroll
                 for (int r = 0; r < EPL; ++r) {
                     float co, si;
                     cossin_hturn(v[r] * sh[r], coef, co, si);
-                    const float dz = co * gs[r] - si * gc[r];
+                    const float dz = co * gsn[r] - si * gc[r];
                     if constexpr (PARAMS)
                         aS[r] += dz * v[r];
-                    v[r] = s32[r] * dz;
+                    v[r] = dz;
                 }
+                float s32[EPL];
+                bload_coal<M, P>(s32, rS, eo4, t);
+#pragma unroll
+                for (int r = 0; r < EPL; ++r)
+                    v[r] *= s32[r];
             }
             // g2 = H g3 (ends in the gather layout); dG += g2 w; Pi^T scatter of G g2
-            fwht_up<M>(v, buf, t);
+            fwht_up<M, P>(v, buf, t);
             {
                 float gk[EPL];
-                load_lane_major<M, float>(gk, Gk + eo, t);
+                bload_lane<M, P, float>(gk, rG, eo4, t);
 #pragma unroll
                 for (int r = 0; r < EPL; ++r) {
                     if constexpr (PARAMS)
@@ -226,16 +350,16 @@ __global__ void __launch_bounds__(BwdGeo<M>::THREADS)
             }
 #pragma unroll
             for (int r = 0; r < EPL; ++r)
-                *reinterpret_cast<float*>(reinterpret_cast<char*>(buf) + off[r]) = v[r];
-            lds_sync<M>();
-            lds_get<M, K>(buf, t, v);
-            lds_sync<M>();
+                *reinterpret_cast<float*>(lbytes + off[r]) = v[r];
+            lds_sync<M, P>();
+            lds_get<M, P, K>(buf, t, v);
+            lds_sync<M, P>();
             // g0 = H g1 (ends in the coalesced layout); dB += g0 xhat; dx += B g0
-            fwht_down<M>(v, buf, t);
+            fwht_down<M, P>(v, buf, t);
             {
                 float xh[EPL], bb[EPL];
-                load_row<M, VEC>(xh, xr, d, t, valid);
-                load_param_coal<M>(bb, B + eo, t);
+                bload_row<M, P, VEC>(xh, rx, xoff, d, t, valid);
+                bload_coal<M, P>(bb, rB, eo4, t);
 #pragma unroll
                 for (int r = 0; r < EPL; ++r) {
                     if constexpr (PARAMS)
@@ -243,27 +367,27 @@ __global__ void __launch_bounds__(BwdGeo<M>::THREADS)
                     v[r] *= bb[r];
                 }
             }
-            if (dx != nullptr && valid) {
-                float* dr = dx + row * (int64_t)d;
+            if (dx != nullptr) {
+                // padded coordinates and invalid rows map out of range: dropped
+                if (e > 0) {
+                    float o[EPL];
+                    bload_row<M, P, VEC>(o, rX, xoff, d, t, valid);
+#pragma unroll
+                    for (int r = 0; r < EPL; ++r)
+                        v[r] += o[r];
+                }
                 if constexpr (VEC) {
 #pragma unroll
                     for (int j = 0; j < EPL / 4; ++j) {
-                        const uint32_t i0 = ct | rpart(M, 0, 4 * j);
-                        if ((int)i0 < d) {
-                            float4 q = make_float4(v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]);
-                            if (e > 0) {
-                                const float4 o = *reinterpret_cast<const float4*>(dr + i0);
-                                q.x += o.x; q.y += o.y; q.z += o.z; q.w += o.w;
-                            }
-                            *reinterpret_cast<float4*>(dr + i0) = q;
-                        }
+                        const uint32_t i0 = ct | rpart(M, P, 0, 4 * j);
+                        const uint32_t o = (valid && (int)i0 < d) ? xoff + 4u * i0 : kOutOfRange;
+                        bstore4(rX, o, v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]);
                     }
                 } else {
 #pragma unroll
-                    for (int r = 0; r < EPL; ++r) {
-                        const uint32_t i = ct | rpart(M, 0, r);
-                        if ((int)i < d)
-                            dr[i] = (e > 0) ? dr[i] + v[r] : v[r];
+                    for (int k = 0; k < EPL; ++k) {
+                        const uint32_t i = ct | rpart(M, P, 0, k);
+                        bstore1(rX, (valid && (int)i < d) ? xoff + 4u * i : kOutOfRange, 0, v[k]);
                     }
                 }
             }
@@ -278,15 +402,15 @@ __global__ void __launch_bounds__(BwdGeo<M>::THREADS)
             for (int a = 0; a < 3; ++a) {
                 __syncthreads();
                 if (a == 1) {
-                    const uint32_t tk = tpart<M, K>(t);
+                    const uint32_t tk = tpart<M, P, K>(t);
 #pragma unroll
                     for (int r = 0; r < EPL; ++r)
-                        slot[tk | rpart(M, K, r)] = aG[r];
+                        slot[tk | rpart(M, P, K, r)] = aG[r];
                 } else {
                     const float* acc = a == 0 ? aS : aB;
 #pragma unroll
                     for (int r = 0; r < EPL; ++r)
-                        slot[ct | rpart(M, 0, r)] = acc[r];
+                        slot[ct | rpart(M, P, 0, r)] = acc[r];
                 }
                 __syncthreads();
                 for (int i = threadIdx.x; i < n; i += bg::THREADS) {
@@ -321,27 +445,61 @@ __global__ void k_reduce(const float* __restrict__ partial, int64_t blocks, int6
 }
 
 // ------------------------------------------------------------------ derive
-template <int M>
+// For the gather layout of the given P:
+//   goff[e][lane][r] = byte offset in the block's LDS of the gather source of
+//     register r of lane `lane` (row region included);
+//   Gk[e][t][r] = G[e][i] for the element i held there (destination order);
+//   Gs[e][q] = G[e][j] for the destination j whose gather source perm[j]
+//     sits at lane-major slot q (G moved to source order);
+// and Sh = S / pi (S in half turns) in natural order.
+template <int M, int P>
+__device__ __forceinline__ uint32_t lane_major_slot(uint32_t i)
+{
+    using g = Geo<M, P>;
+    constexpr int K = g::K;
+    uint32_t r = 0, t = 0;
+    for (int b = 0; b < g::Q; ++b)
+        r |= ((i >> reg_bit(M, P, K, b)) & 1u) << b;
+    for (int b = 0; b < g::T; ++b)
+        t |= ((i >> thr_bit(M, P, K, b)) & 1u) << b;
+    return t * g::EPL + r;
+}
+
+template <int M, int P>
 __global__ void k_derive(int64_t E, const int32_t* __restrict__ perm, const float* __restrict__ G,
                          const double* __restrict__ S64, const float* __restrict__ S32, uint32_t* __restrict__ goff,
-                         float* __restrict__ Gk, float* __restrict__ Sh)
+                         float* __restrict__ Gk, float* __restrict__ Gs, float* __restrict__ Sh)
 {
-    using g = Geo<M>;
+    using g = Geo<M, P>;
     constexpr int K = g::K, EPL = g::EPL, n = g::n;
+    constexpr int64_t kGoffE = (int64_t)g::RPB * n;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= E * n)
+    if (idx >= E * kGoffE)
         return;
-    const int64_t e = idx / n;
-    const uint32_t q = (uint32_t)(idx % n);  // lane-major slot: t * EPL + r
-    const uint32_t t = q / EPL;
+    const int64_t e = idx / kGoffE;
+    const uint32_t q = (uint32_t)(idx % kGoffE);  // lane * EPL + r
+    const uint32_t lane = q / EPL;
     const int r = (int)(q % EPL);
-    const uint32_t i = tpart<M, K>(t) | rpart(M, K, r);
+    const uint32_t grp = g::kMulti ? 0u : lane / g::LPR;
+    const uint32_t t = g::kMulti ? lane : lane % g::LPR;
+    const uint32_t i = tpart<M, P, K>(t) | rpart(M, P, K, r);
     const uint32_t src = (uint32_t)perm[e * n + i] & (uint32_t)(n - 1);
-    goff[idx] = 4u * phys(src);
-    Gk[idx] = G[e * n + i];
-    // S in half turns for the feature map, from the FP64 value when present
-    const double s = S64 ? S64[idx] : (double)S32[idx];
-    Sh[idx] = (float)(s * 0.31830988618379067154);
+    goff[idx] = 4u * (grp * (uint32_t)g::STRIDE + phys<P>(src));
+    if (q < (uint32_t)n) {
+        const uint32_t tq = q / EPL;
+        const uint32_t iq = tpart<M, P, K>(tq) | rpart(M, P, K, (int)(q % EPL));
+        if (Gk)
+            Gk[e * n + q] = G[e * n + iq];
+        if (Gs) {
+            const uint32_t srcq = (uint32_t)perm[e * n + q] & (uint32_t)(n - 1);
+            Gs[e * n + lane_major_slot<M, P>(srcq)] = G[e * n + q];
+        }
+        if (Sh) {
+            // S in half turns for the feature map, from the FP64 value when present
+            const double sv = S64 ? S64[e * n + q] : (double)S32[e * n + q];
+            Sh[e * n + q] = (float)(sv * 0.31830988618379067154);
+        }
+    }
 }
 
 // ------------------------------------------------------------------ dispatch
@@ -382,38 +540,73 @@ template <int M>
 struct RunFwht {
     static hipError_t run(float* data, int64_t batch, bool vec, hipStream_t s)
     {
-        using g = Geo<M>;
-        const int64_t blocks = (batch + g::RPB - 1) / g::RPB;
-        if (vec && M >= 2)
-            k_fwht<M, true><<<dim3((unsigned)blocks), dim3(g::BLOCK), 0, s>>>(data, batch);
-        else
-            k_fwht<M, false><<<dim3((unsigned)blocks), dim3(g::BLOCK), 0, s>>>(data, batch);
-        return hipGetLastError();
+        using g = Geo<M, kFwhtP>;
+        const int64_t rows_per = kRangeLimit / (4 * g::n);
+        for (int64_t r0 = 0; r0 < batch; r0 += rows_per) {
+            const int64_t rows = batch - r0 < rows_per ? batch - r0 : rows_per;
+            const int64_t blocks = (rows + g::RPB - 1) / g::RPB;
+            float* p = data + r0 * g::n;
+            const uint32_t bytes = (uint32_t)(4 * rows * g::n);
+            if (vec && M >= 2)
+                k_fwht<M, true><<<dim3((unsigned)blocks), dim3(g::BLOCK), 0, s>>>(p, bytes, rows);
+            else
+                k_fwht<M, false><<<dim3((unsigned)blocks), dim3(g::BLOCK), 0, s>>>(p, bytes, rows);
+            const hipError_t err = hipGetLastError();
+            if (err != hipSuccess)
+                return err;
+        }
+        return hipSuccess;
     }
 };
 
 template <int M>
 struct RunForward {
     static hipError_t run(bool vec, bool trig, const float* x, int64_t batch, int d, int64_t E, const float* B,
-                          const uint32_t* goff, const float* Gk, const float* Sx, const FeatCoef& coef, float* out,
+                          const uint32_t* goff, const float* Gs, const float* Sx, const FeatCoef& coef, float* out,
                           hipStream_t s)
     {
-        using g = Geo<M>;
-        const int64_t blocks = (batch + g::RPB - 1) / g::RPB;
-        const dim3 grid((unsigned)blocks), blk(g::BLOCK);
-        const int Ei = (int)E;
-        if (vec && M >= 2) {
-            if (trig)
-                k_forward<M, true, true><<<grid, blk, 0, s>>>(x, batch, d, Ei, B, goff, Gk, Sx, coef, out);
-            else
-                k_forward<M, true, false><<<grid, blk, 0, s>>>(x, batch, d, Ei, B, goff, Gk, Sx, coef, out);
-        } else {
-            if (trig)
-                k_forward<M, false, true><<<grid, blk, 0, s>>>(x, batch, d, Ei, B, goff, Gk, Sx, coef, out);
-            else
-                k_forward<M, false, false><<<grid, blk, 0, s>>>(x, batch, d, Ei, B, goff, Gk, Sx, coef, out);
+        constexpr int P = fwd_p(M);
+        using g = Geo<M, P>;
+        const int64_t n = g::n;
+        const int64_t out_row = (trig ? 2 : 1) * n * E;
+        // rows per launch: keep every buffer range of a launch below 2^31 bytes
+        int64_t rows_per = kRangeLimit / (4 * (out_row > d ? out_row : d));
+        rows_per = rows_per < 1 ? 1 : rows_per;
+        const uint32_t par_bytes = (uint32_t)(4 * n * E);
+        const uint32_t goff_bytes = (uint32_t)(4 * g::RPB * n * E);
+        for (int64_t r0 = 0; r0 < batch; r0 += rows_per) {
+            const int64_t rows = batch - r0 < rows_per ? batch - r0 : rows_per;
+            const int64_t groups = (rows + g::RPB - 1) / g::RPB;
+            // split the expansions so that the grid holds >= ~16k waves
+            const int64_t waves_per_group = g::BLOCK / 64;
+            int64_t nchunks = (16384 + groups * waves_per_group - 1) / (groups * waves_per_group);
+            nchunks = nchunks > E ? E : (nchunks < 1 ? 1 : nchunks);
+            const int64_t echunk = (E + nchunks - 1) / nchunks;
+            nchunks = (E + echunk - 1) / echunk;
+            const int64_t blocks = ((groups + kXcds - 1) / kXcds) * kXcds * nchunks;
+            const dim3 grid((unsigned)blocks), blk(g::BLOCK);
+            const float* xs = x + r0 * d;
+            float* os = out + r0 * out_row;
+            const uint32_t xb = (uint32_t)(4 * rows * d), ob = (uint32_t)(4 * rows * out_row);
+            const int Ei = (int)E, ec = (int)echunk, nc = (int)nchunks;
+#define MCK_FWD_ARGS xs, xb, rows, d, Ei, ec, nc, B, goff, Gs, Sx, par_bytes, goff_bytes, coef, os, ob
+            if (vec && M >= 2) {
+                if (trig)
+                    k_forward<M, P, true, true><<<grid, blk, 0, s>>>(MCK_FWD_ARGS);
+                else
+                    k_forward<M, P, true, false><<<grid, blk, 0, s>>>(MCK_FWD_ARGS);
+            } else {
+                if (trig)
+                    k_forward<M, P, false, true><<<grid, blk, 0, s>>>(MCK_FWD_ARGS);
+                else
+                    k_forward<M, P, false, false><<<grid, blk, 0, s>>>(MCK_FWD_ARGS);
+            }
+#undef MCK_FWD_ARGS
+            const hipError_t err = hipGetLastError();
+            if (err != hipSuccess)
+                return err;
         }
-        return hipGetLastError();
+        return hipSuccess;
     }
 };
 
@@ -424,23 +617,26 @@ struct RunBackward {
                           const FeatCoef& coef, float* dx, float* partial, const BwdGeometry& geo, hipStream_t s)
     {
         using bg = BwdGeo<M>;
+        using g = typename bg::g;
         const dim3 grid((unsigned)geo.blocks), blk(bg::THREADS);
         const int Ei = (int)E;
+        const uint32_t xb = (uint32_t)(4 * batch * d), db = (uint32_t)(4 * batch * 2 * g::n * E);
+        const uint32_t par_bytes = (uint32_t)(4 * g::n * E);
+        const uint32_t goff_bytes = (uint32_t)(4 * g::RPB * g::n * E);
+#define MCK_BWD_ARGS x, xb, dphi, db, batch, d, Ei, B, goff, Gk, S32, Sh, par_bytes, goff_bytes, coef, dx, partial, \
+                     geo.passes
         if (vec && M >= 2) {
             if (partial)
-                k_backward<M, true, true><<<grid, blk, 0, s>>>(x, dphi, batch, d, Ei, B, goff, Gk, S32, Sh, coef,
-                                                                dx, partial, geo.passes);
+                k_backward<M, true, true><<<grid, blk, 0, s>>>(MCK_BWD_ARGS);
             else
-                k_backward<M, true, false><<<grid, blk, 0, s>>>(x, dphi, batch, d, Ei, B, goff, Gk, S32, Sh, coef,
-                                                                 dx, partial, geo.passes);
+                k_backward<M, true, false><<<grid, blk, 0, s>>>(MCK_BWD_ARGS);
         } else {
             if (partial)
-                k_backward<M, false, true><<<grid, blk, 0, s>>>(x, dphi, batch, d, Ei, B, goff, Gk, S32, Sh, coef,
-                                                                 dx, partial, geo.passes);
+                k_backward<M, false, true><<<grid, blk, 0, s>>>(MCK_BWD_ARGS);
             else
-                k_backward<M, false, false><<<grid, blk, 0, s>>>(x, dphi, batch, d, Ei, B, goff, Gk, S32, Sh, coef,
-                                                                  dx, partial, geo.passes);
+                k_backward<M, false, false><<<grid, blk, 0, s>>>(MCK_BWD_ARGS);
         }
+#undef MCK_BWD_ARGS
         return hipGetLastError();
     }
 };
@@ -450,9 +646,9 @@ struct RunGeometry {
     static hipError_t run(int64_t batch, BwdGeometry* out)
     {
         using bg = BwdGeo<M>;
-        // about 256 blocks, each owning a contiguous run of rows
+        // about 512 blocks, each owning a contiguous run of rows
         const int64_t units = (batch + bg::ROWS - 1) / bg::ROWS;
-        const int64_t target = 256;
+        const int64_t target = 512;
         int64_t passes = (units + target - 1) / target;
         if (passes < 1)
             passes = 1;
@@ -466,12 +662,27 @@ struct RunGeometry {
 };
 
 template <int M>
+struct RunPlanElems {
+    static hipError_t run(int64_t* fwd_goff, int64_t* bwd_goff)
+    {
+        *fwd_goff = (int64_t)Geo<M, fwd_p(M)>::RPB * Geo<M, fwd_p(M)>::n;
+        *bwd_goff = (int64_t)Geo<M, bwd_p(M)>::RPB * Geo<M, bwd_p(M)>::n;
+        return hipSuccess;
+    }
+};
+
+template <int M>
 struct RunDerive {
     static hipError_t run(int64_t E, const int32_t* perm, const float* G, const double* S64, const float* S32,
-                          uint32_t* goff, float* Gk, float* Sh, hipStream_t s)
+                          uint32_t* goff_f, float* Gs_f, uint32_t* goff_b, float* Gk_b, float* Sh, hipStream_t s)
     {
-        const int64_t total = E * Geo<M>::n;
-        k_derive<M><<<dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s>>>(E, perm, G, S64, S32, goff, Gk, Sh);
+        constexpr int PF = fwd_p(M), PB = bwd_p(M);
+        const int64_t tf = E * Geo<M, PF>::RPB * Geo<M, PF>::n;
+        k_derive<M, PF><<<dim3((unsigned)((tf + 255) / 256)), dim3(256), 0, s>>>(E, perm, G, S64, S32, goff_f,
+                                                                                  nullptr, Gs_f, Sh);
+        const int64_t tb = E * Geo<M, PB>::RPB * Geo<M, PB>::n;
+        k_derive<M, PB><<<dim3((unsigned)((tb + 255) / 256)), dim3(256), 0, s>>>(E, perm, G, S64, S32, goff_b,
+                                                                                  Gk_b, nullptr, nullptr);
         return hipGetLastError();
     }
 };
@@ -484,11 +695,11 @@ hipError_t launch_fwht(int M, float* data, int64_t batch, bool vec, hipStream_t 
 }
 
 hipError_t launch_forward(int M, bool vec, bool trig, const float* x, int64_t batch, int d, int64_t E,
-                          const float* B, const uint32_t* goff, const float* Gk, const float* Sx,
+                          const float* B, const uint32_t* goff, const float* Gs, const float* Sx,
                           const FeatCoefHost& coef, float* out, hipStream_t s)
 {
     const FeatCoef c = to_dev(coef);
-    return dispatch_m<RunForward>(M, vec, trig, x, batch, d, E, B, goff, Gk, Sx, c, out, s);
+    return dispatch_m<RunForward>(M, vec, trig, x, batch, d, E, B, goff, Gs, Sx, c, out, s);
 }
 
 BwdGeometry backward_geometry(int M, int64_t batch)
@@ -515,10 +726,16 @@ hipError_t launch_reduce(const float* partial, int64_t blocks, int64_t E, int64_
     return hipGetLastError();
 }
 
-hipError_t launch_derive(int M, int64_t E, const int32_t* perm, const float* G, const double* S64, const float* S32,
-                         uint32_t* goff, float* Gk, float* Sh, hipStream_t s)
+void plan_elems(int M, int64_t* fwd_goff, int64_t* bwd_goff)
 {
-    return dispatch_m<RunDerive>(M, E, perm, G, S64, S32, goff, Gk, Sh, s);
+    *fwd_goff = *bwd_goff = 0;
+    (void)dispatch_m<RunPlanElems>(M, fwd_goff, bwd_goff);
+}
+
+hipError_t launch_derive(int M, int64_t E, const int32_t* perm, const float* G, const double* S64, const float* S32,
+                         uint32_t* goff_f, float* Gs_f, uint32_t* goff_b, float* Gk_b, float* Sh, hipStream_t s)
+{
+    return dispatch_m<RunDerive>(M, E, perm, G, S64, S32, goff_f, Gs_f, goff_b, Gk_b, Sh, s);
 }
 
 }  // namespace mck

@@ -22,18 +22,21 @@ hipError_t launch_generate(uint32_t seed, int64_t n, int64_t E, double sigma, fl
 hipError_t launch_boxmuller(const uint32_t* a, const uint32_t* b, int64_t count, float* g0, float* g1,
                             hipStream_t s);
 
-// Kernel-layout copies of the parameters: gather offsets (4 * LDS position of
-// perm[i]), G in the gather layout, S in half turns (S / pi) and S as FP32.
-// S64 may be null (then S32 is used).
+// Kernel-layout copies of the parameters, for the forward (F) and the
+// backward (B) register layouts: gather offsets (byte offset in the block's
+// LDS of the source of each gathered element; plan_elems(M) of them per
+// expansion), G by source (Gs_f) and by destination (Gk_b), and S in half
+// turns (Sh, natural order).  S64 may be null (then S32 is used).
+void plan_elems(int M, int64_t* fwd_goff, int64_t* bwd_goff);
 hipError_t launch_derive(int M, int64_t E, const int32_t* perm, const float* G, const double* S64, const float* S32,
-                         uint32_t* goff, float* Gk, float* Sh, hipStream_t s);
+                         uint32_t* goff_f, float* Gs_f, uint32_t* goff_b, float* Gk_b, float* Sh, hipStream_t s);
 
 // In-place batched Walsh-Hadamard transform, n = 2^M, 1 <= M <= 15.
 hipError_t launch_fwht(int M, float* data, int64_t batch, bool vec, hipStream_t s);
 
 // Forward: phi (trig = true) or z = S H G Pi H B xhat (trig = false).
 hipError_t launch_forward(int M, bool vec, bool trig, const float* x, int64_t batch, int d, int64_t E,
-                          const float* B, const uint32_t* goff, const float* Gk, const float* Sx,
+                          const float* B, const uint32_t* goff, const float* Gs, const float* Sx,
                           const FeatCoefHost& coef, float* out, hipStream_t s);
 
 // Backward geometry: blocks, passes per block.

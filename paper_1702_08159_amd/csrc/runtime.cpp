@@ -11,7 +11,7 @@
 #include <mutex>
 #include <string>
 
-#include "../../include/mckernel.h"
+#include "mckernel.h"
 #include "launch.hpp"
 
 namespace {
@@ -86,6 +86,8 @@ mck_status check_common(int64_t batch, int64_t d, int64_t E, int64_t* n_out)
     const int64_t n = padded_dim(d);
     if (n == 0)
         return fail(MCK_ERR_UNSUPPORTED, "padded dimension exceeds MCK_MAX_N");
+    if (E * (n > 2048 ? n : 2048) > (int64_t(1) << 28))
+        return fail(MCK_ERR_UNSUPPORTED, "E * n too large (parameter arrays limited to 2^28 entries)");
     if (d > (int64_t(1) << 30) || batch > (int64_t(1) << 40))
         return fail(MCK_ERR_INVALID_ARG, "size out of range");
     *n_out = n;
@@ -107,9 +109,11 @@ struct Plan {
     double* S64 = nullptr;
     float* S32 = nullptr;
     double* norm2 = nullptr;
-    uint32_t* goff = nullptr;
-    float* Gk = nullptr;
-    float* Sh = nullptr;
+    uint32_t* goffF = nullptr;  // forward gather offsets
+    float* GsF = nullptr;       // G in source order, forward layout
+    uint32_t* goffB = nullptr;  // backward gather offsets
+    float* GkB = nullptr;       // G in destination order, backward layout
+    float* Sh = nullptr;        // S / pi
 };
 
 std::mutex g_mutex;
@@ -156,9 +160,12 @@ mck_status get_plan(uint32_t seed, int64_t n, int64_t E, double sigma, int calib
     p.sigma = sigma;
     p.calib = calib;
     const size_t en = (size_t)(n * E);
-    size_t off[10], total = 0;
-    const size_t sz[10] = {en * 4, en * 4, en * 4, en * 8, en * 4, (size_t)E * 8, en * 4, en * 4, en * 4, 0};
-    for (int i = 0; i < 9; ++i) {
+    int64_t gf = 0, gb = 0;
+    mck::plan_elems(log2i(n), &gf, &gb);
+    size_t off[11], total = 0;
+    const size_t sz[11] = {en * 4, en * 4, en * 4, en * 8, en * 4, (size_t)E * 8,
+                           (size_t)gf * E * 4, en * 4, (size_t)gb * E * 4, en * 4, en * 4};
+    for (int i = 0; i < 11; ++i) {
         off[i] = total;
         total += align_up(sz[i]);
     }
@@ -184,12 +191,15 @@ mck_status get_plan(uint32_t seed, int64_t n, int64_t E, double sigma, int calib
     p.S64 = reinterpret_cast<double*>(b + off[3]);
     p.S32 = reinterpret_cast<float*>(b + off[4]);
     p.norm2 = reinterpret_cast<double*>(b + off[5]);
-    p.goff = reinterpret_cast<uint32_t*>(b + off[6]);
-    p.Gk = reinterpret_cast<float*>(b + off[7]);
-    p.Sh = reinterpret_cast<float*>(b + off[8]);
+    p.goffF = reinterpret_cast<uint32_t*>(b + off[6]);
+    p.GsF = reinterpret_cast<float*>(b + off[7]);
+    p.goffB = reinterpret_cast<uint32_t*>(b + off[8]);
+    p.GkB = reinterpret_cast<float*>(b + off[9]);
+    p.Sh = reinterpret_cast<float*>(b + off[10]);
     err = mck::launch_generate(seed, n, E, sigma, p.B, p.perm, p.G, p.S64, p.S32, p.norm2, stream);
     if (err == hipSuccess)
-        err = mck::launch_derive(log2i(n), E, p.perm, p.G, p.S64, p.S32, p.goff, p.Gk, p.Sh, stream);
+        err = mck::launch_derive(log2i(n), E, p.perm, p.G, p.S64, p.S32, p.goffF, p.GsF, p.goffB, p.GkB, p.Sh,
+                                 stream);
     if (err == hipSuccess)
         err = hipStreamSynchronize(stream);  // the plan may be used from other streams next
     if (err != hipSuccess) {
@@ -203,8 +213,10 @@ mck_status get_plan(uint32_t seed, int64_t n, int64_t E, double sigma, int calib
 
 struct TempPlan {
     void* block = nullptr;
-    uint32_t* goff = nullptr;
-    float* Gk = nullptr;
+    uint32_t* goffF = nullptr;
+    float* GsF = nullptr;
+    uint32_t* goffB = nullptr;
+    float* GkB = nullptr;
     float* Sh = nullptr;
 };
 
@@ -212,17 +224,21 @@ mck_status make_temp_plan(int64_t n, int64_t E, const int32_t* perm, const float
                           hipStream_t s, TempPlan* tp)
 {
     const size_t en = (size_t)(n * E);
-    const size_t a = align_up(en * 4);
-    hipError_t err = hipMallocAsync(&tp->block, 3 * a, s);
+    int64_t gf = 0, gb = 0;
+    mck::plan_elems(log2i(n), &gf, &gb);
+    const size_t a = align_up(en * 4), af = align_up((size_t)gf * E * 4), ab = align_up((size_t)gb * E * 4);
+    hipError_t err = hipMallocAsync(&tp->block, af + ab + 3 * a, s);
     if (err != hipSuccess) {
         tp->block = nullptr;
         return fail(MCK_ERR_NO_MEMORY, std::string("temporary plan: ") + hipGetErrorString(err));
     }
     char* b = static_cast<char*>(tp->block);
-    tp->goff = reinterpret_cast<uint32_t*>(b);
-    tp->Gk = reinterpret_cast<float*>(b + a);
-    tp->Sh = reinterpret_cast<float*>(b + 2 * a);
-    err = mck::launch_derive(log2i(n), E, perm, G, nullptr, S, tp->goff, tp->Gk, tp->Sh, s);
+    tp->goffF = reinterpret_cast<uint32_t*>(b);
+    tp->goffB = reinterpret_cast<uint32_t*>(b + af);
+    tp->GsF = reinterpret_cast<float*>(b + af + ab);
+    tp->GkB = reinterpret_cast<float*>(b + af + ab + a);
+    tp->Sh = reinterpret_cast<float*>(b + af + ab + 2 * a);
+    err = mck::launch_derive(log2i(n), E, perm, G, nullptr, S, tp->goffF, tp->GsF, tp->goffB, tp->GkB, tp->Sh, s);
     if (err != hipSuccess) {
         (void)hipFreeAsync(tp->block, s);
         return hip_fail(err, "derive kernel");
@@ -241,19 +257,34 @@ mck_status run_backward(const float* x, const float* dphi, int64_t batch, int64_
 {
     const int M = log2i(n);
     const bool want_params = dB || dG || dS;
-    const mck::BwdGeometry geo = mck::backward_geometry(M, batch);
+    // rows per launch: keep the x, dx and dphi ranges of a launch below 2^31 bytes
+    const int64_t lim = (int64_t(1) << 31) - 4096;
+    const int64_t row_bytes = 4 * (2 * n * E > d ? 2 * n * E : d);
+    const int64_t rows_per = lim / row_bytes < 1 ? 1 : lim / row_bytes;
+    int64_t total_blocks = 0;
+    for (int64_t r0 = 0; r0 < batch; r0 += rows_per)
+        total_blocks += mck::backward_geometry(M, batch - r0 < rows_per ? batch - r0 : rows_per).blocks;
     float* partial = nullptr;
     hipError_t err;
     if (want_params) {
-        err = hipMallocAsync(reinterpret_cast<void**>(&partial), (size_t)geo.blocks * E * 3 * n * sizeof(float), s);
+        err = hipMallocAsync(reinterpret_cast<void**>(&partial), (size_t)total_blocks * E * 3 * n * sizeof(float), s);
         if (err != hipSuccess)
             return fail(MCK_ERR_NO_MEMORY, std::string("backward partials: ") + hipGetErrorString(err));
     }
     const bool vec = vec_ok(x, dphi, d, n) && (dx == nullptr || aligned16(dx));
-    err = mck::launch_backward(M, vec, x, dphi, batch, (int)d, E, B, goff, Gk, S32, Sh, feature_coefficients(n, E), dx,
-                               partial, geo, s);
+    const mck::FeatCoefHost coef = feature_coefficients(n, E);
+    err = hipSuccess;
+    int64_t done_blocks = 0;
+    for (int64_t r0 = 0; r0 < batch && err == hipSuccess; r0 += rows_per) {
+        const int64_t rows = batch - r0 < rows_per ? batch - r0 : rows_per;
+        const mck::BwdGeometry geo = mck::backward_geometry(M, rows);
+        float* part = partial ? partial + (size_t)done_blocks * E * 3 * n : nullptr;
+        err = mck::launch_backward(M, vec, x + r0 * d, dphi + r0 * 2 * n * E, rows, (int)d, E, B, goff, Gk, S32, Sh,
+                                   coef, dx ? dx + r0 * d : nullptr, part, geo, s);
+        done_blocks += geo.blocks;
+    }
     if (err == hipSuccess && want_params)
-        err = mck::launch_reduce(partial, geo.blocks, E, n, dS, dG, dB, s);
+        err = mck::launch_reduce(partial, total_blocks, E, n, dS, dG, dB, s);
     if (partial)
         (void)hipFreeAsync(partial, s);
     if (err != hipSuccess)
@@ -354,7 +385,7 @@ static mck_status forward_common(const float* x, int64_t batch, int64_t d, int64
     if (st != MCK_OK)
         return st;
     const hipError_t err = mck::launch_forward(log2i(n), vec_ok(x, out, d, n), trig, x, batch, (int)d, E, p->B,
-                                               p->goff, p->Gk, trig ? p->Sh : p->S32, feature_coefficients(n, E),
+                                               p->goffF, p->GsF, trig ? p->Sh : p->S32, feature_coefficients(n, E),
                                                out, s);
     return err == hipSuccess ? MCK_OK : hip_fail(err, "forward launch");
 }
@@ -403,7 +434,7 @@ mck_status mck_fastfood_backward(const float* x, const float* dphi, int64_t batc
     st = get_plan(seed, n, E, sigma, calib, s, &p);
     if (st != MCK_OK)
         return st;
-    return run_backward(x, dphi, batch, d, n, E, p->B, p->goff, p->Gk, p->S32, p->Sh, dx, dB, dG, dS, s);
+    return run_backward(x, dphi, batch, d, n, E, p->B, p->goffB, p->GkB, p->S32, p->Sh, dx, dB, dG, dS, s);
 }
 
 static mck_status check_explicit(int64_t batch, int64_t d, int64_t n, int64_t E, const float* B,
@@ -435,7 +466,7 @@ mck_status mck_fastfood_forward_p(const float* x, int64_t batch, int64_t d, int6
     st = make_temp_plan(n, E, perm, G, S, s, &tp);
     if (st != MCK_OK)
         return st;
-    hipError_t err = mck::launch_forward(log2i(n), vec_ok(x, phi, d, n), true, x, batch, (int)d, E, B, tp.goff, tp.Gk,
+    hipError_t err = mck::launch_forward(log2i(n), vec_ok(x, phi, d, n), true, x, batch, (int)d, E, B, tp.goffF, tp.GsF,
                                          tp.Sh, feature_coefficients(n, E), phi, s);
     (void)hipFreeAsync(tp.block, s);
     return err == hipSuccess ? MCK_OK : hip_fail(err, "forward launch");
@@ -464,7 +495,7 @@ mck_status mck_fastfood_backward_p(const float* x, const float* dphi, int64_t ba
     st = make_temp_plan(n, E, perm, G, S, s, &tp);
     if (st != MCK_OK)
         return st;
-    st = run_backward(x, dphi, batch, d, n, E, B, tp.goff, tp.Gk, S, tp.Sh, dx, dB, dG, dS, s);
+    st = run_backward(x, dphi, batch, d, n, E, B, tp.goffB, tp.GkB, S, tp.Sh, dx, dB, dG, dS, s);
     (void)hipFreeAsync(tp.block, s);
     return st;
 }
