@@ -4,15 +4,21 @@ Workload (MNIST-shaped synthetic input, the paper's data shape): 8192 rows of
 784 pixels (80 % zeros, else uniform [0, 1]) padded to n = 1024, E = 16
 expansions (32768 features per row), RBF sigma = 2, seed 1398239763.
 
-A step is one forward pass x -> phi over the batch (one kernel launch); the
-fwd+bwd step adds the adjoint (dx and the batch-summed dB, dG, dS).  Inputs
-are resident in HBM before timing.  Prints one JSON line.
+A step is one forward pass x -> phi over the whole batch (one kernel launch).
+Forward steps are replayed from a HIP graph that holds GRAPH_STEPS launches,
+so host launch gaps do not count; the fwd+bwd figure adds the adjoint (dx
+and the batch-summed dB, dG, dS), launched eagerly.  Inputs are resident in
+HBM before timing.  The defaults warm up for about 100 steps first: the
+card's power management lowers clocks a few milliseconds into a sustained
+run and settles after about 20 ms, and the steady state is what is reported.
+Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--cpu-seconds S]
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -27,29 +33,50 @@ BATCH, D, N, E, SIGMA = 8192, 784, 1024, 16, 2.0
 FWD_BYTES_PER_VECTOR = 4 * D + 8 * N * E          # read x, write phi
 BWD_BYTES_PER_VECTOR = 8 * D + 8 * N * E          # read x and dphi, write dx
 HBM_PEAK_GBS = 8000.0
+GRAPH_STEPS = 10
 METRIC = "Fastfood vectors/s + %HBM peak at n=1024 E=16, fwd and fwd+bwd vs oracle error"
+
+# HBM bytes per forward launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of
+# this workload, scaled by what the same counters read for a 1 GiB device
+# copy (FETCH_SIZE reads half the bytes copied, WRITE_SIZE all of them).
+# Keyed by a hash of the kernel sources; any change to them voids the entry.
+KERNEL_SOURCES = ("paper_1702_08159_amd/csrc/kernels.hip", "paper_1702_08159_amd/csrc/engine.hpp",
+                  "paper_1702_08159_amd/csrc/layout.hpp")
+FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
+TRAFFIC_KIB = {
+    # sha1 of the kernel sources: (FETCH_SIZE KiB, WRITE_SIZE KiB) per launch
+    "f7b33cb33f0e646e9ba92e6ec6ca6bd659443601": (13855.0, 1048610.0),
+}
 
 
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+def kernel_hash() -> str:
+    h = hashlib.sha1()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--bwd-steps", type=int, default=40)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--only", choices=["fwd", "bwd", "all"], default="all",
                     help="time only one pass (for profiling); the JSON line then lacks the other")
     ap.add_argument("--copy-probe", action="store_true",
-                    help="also time a plain 1 GiB device copy and fill (bandwidth calibration)")
+                    help="also time a plain 1 GiB device copy and fill (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(rows would shard with zero communication; see DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: the Fastfood map has no cross-GPU step "
+              "(rows shard with zero communication), and this build runs on a single GPU", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -64,70 +91,81 @@ def main():
     x_np = workloads.mnist_sparse(BATCH)
     x = torch.from_numpy(x_np).to(dev)
     phi = torch.empty((BATCH, 2 * N * E), dtype=torch.float32, device=dev)
-    dphi = torch.from_numpy(workloads.grad_features(BATCH, 2 * N * E)).to(dev)
-    dx = torch.empty_like(x)
     log("inputs resident; building plan")
     mk.forward(x, E, seed, SIGMA, out=phi)
     torch.cuda.synchronize()
-
     stream = torch.cuda.current_stream(dev)
 
-    def fwd():
-        mk.forward(x, E, seed, SIGMA, out=phi)
-
-    def bwd():
-        return mk.backward(x, dphi, E, seed, SIGMA, need_dx=True, need_params=True)
-
-    use_graph = not args.no_graph
-    graph = None
-    if use_graph:
-        # one hipGraph launch per forward step (the plan is already cached)
+    def capture(k):
+        # a graph of k forward launches on the current stream
         s = torch.cuda.Stream(dev)
         s.wait_stream(stream)
         with torch.cuda.stream(s):
-            for _ in range(2):
-                fwd()
+            mk.forward(x, E, seed, SIGMA, out=phi)
         stream.wait_stream(s)
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph):
-            fwd()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for _ in range(k):
+                mk.forward(x, E, seed, SIGMA, out=phi)
         torch.cuda.synchronize()
-
-    def run_fwd():
-        if graph is not None:
-            graph.replay()
-        else:
-            fwd()
+        return g
 
     t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
-    def timed(fn, steps, warmup):
-        for _ in range(warmup):
-            fn()
-        torch.cuda.synchronize()
-        t0.record(stream)
-        for _ in range(steps):
-            fn()
-        t1.record(stream)
-        torch.cuda.synchronize()
-        return t0.elapsed_time(t1) / steps
+    def run_steps(fn_block, fn_rest, k):
+        # k steps: full graphs of GRAPH_STEPS launches, then the remainder
+        for _ in range(k // GRAPH_STEPS):
+            fn_block()
+        for _ in range(k % GRAPH_STEPS):
+            fn_rest()
 
     if args.copy_probe:
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
         b = torch.empty_like(a)
-        cp_ms = timed(lambda: b.copy_(a), 20, 3)
-        fill_ms = timed(lambda: b.fill_(2.0), 20, 3)
-        log("copy 1 GiB: %.3f ms (%.0f GB/s read+write); fill 1 GiB: %.3f ms (%.0f GB/s)"
-            % (cp_ms, 2 * (1 << 30) / cp_ms / 1e6, fill_ms, (1 << 30) / fill_ms / 1e6))
+        for name, fn in (("copy", lambda: b.copy_(a)), ("fill", lambda: b.fill_(2.0))):
+            for _ in range(3):
+                fn()
+            torch.cuda.synchronize()
+            t0.record(stream)
+            for _ in range(20):
+                fn()
+            t1.record(stream)
+            torch.cuda.synchronize()
+            ms = t0.elapsed_time(t1) / 20
+            log("%s 1 GiB: %.3f ms" % (name, ms))
         del a, b
 
     fwd_ms = bwd_ms = float("nan")
     if args.only in ("fwd", "all"):
-        fwd_ms = timed(run_fwd, args.steps, args.warmup)
-        log("forward %.3f ms/step" % fwd_ms)
+        gblock = capture(GRAPH_STEPS)
+        one = capture(1)
+        run_steps(gblock.replay, one.replay, args.warmup)
+        torch.cuda.synchronize()
+        t0.record(stream)
+        run_steps(gblock.replay, one.replay, args.steps)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        fwd_ms = t0.elapsed_time(t1) / args.steps
+        log("forward %.4f ms/step over %d steps" % (fwd_ms, args.steps))
     if args.only in ("bwd", "all"):
-        bwd_ms = timed(bwd, args.steps, max(1, args.warmup // 2))
-        log("backward %.3f ms/step" % bwd_ms)
+        dphi = torch.from_numpy(workloads.grad_features(BATCH, 2 * N * E)).to(dev)
+        grads = (torch.empty_like(x),) + tuple(torch.empty((E, N), dtype=torch.float32, device=dev)
+                                                for _ in range(3))
+
+        def bwd():
+            mk.backward(x, dphi, E, seed, SIGMA, out=grads)
+
+        for _ in range(max(1, args.warmup // 10)):
+            bwd()
+        torch.cuda.synchronize()
+        t0.record(stream)
+        for _ in range(args.bwd_steps):
+            bwd()
+        t1.record(stream)
+        torch.cuda.synchronize()
+        bwd_ms = t0.elapsed_time(t1) / args.bwd_steps
+        log("backward %.4f ms/step over %d steps" % (bwd_ms, args.bwd_steps))
+        del dphi
 
     fwd_vps = BATCH / (fwd_ms * 1e-3)
     fb_ms = fwd_ms + bwd_ms
@@ -135,6 +173,12 @@ def main():
     fwd_gbs = FWD_BYTES_PER_VECTOR * BATCH / (fwd_ms * 1e-3) / 1e9
     fb_bytes = (FWD_BYTES_PER_VECTOR + BWD_BYTES_PER_VECTOR) * BATCH
     fb_gbs = fb_bytes / (fb_ms * 1e-3) / 1e9
+
+    khash = kernel_hash()
+    traffic = None
+    if khash in TRAFFIC_KIB:
+        fk, wk = TRAFFIC_KIB[khash]
+        traffic = int(round((fk * FETCH_SCALE + wk * WRITE_SCALE) * 1024))
 
     cpu = None
     err = None
@@ -176,17 +220,20 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "fastfood-forward mnist-shaped 8192x784 (80% zeros) n=1024 E=16 sigma=2",
-                   "batch": BATCH, "d": D, "n": N, "E": E, "sigma": SIGMA, "graph": use_graph},
+                   "batch": BATCH, "d": D, "n": N, "E": E, "sigma": SIGMA, "graph_steps": GRAPH_STEPS},
         "fwd_hbm_frac": fwd_gbs / HBM_PEAK_GBS,
         "fwd_bwd_vectors_per_s": fb_vps,
         "fwd_bwd_ms_per_step": fb_ms,
         "fwd_bwd_hbm_frac": fb_gbs / HBM_PEAK_GBS,
         "bwd_ms_per_step": bwd_ms,
+        "bwd_steps": args.bwd_steps,
         "max_row_rel_err_vs_oracle": err,
         "roofline": {"bound": "hbm", "achieved": fwd_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": fwd_gbs / HBM_PEAK_GBS, "traffic": None},
+                     "frac": fwd_gbs / HBM_PEAK_GBS, "traffic": traffic},
+        "kernel_sources_sha1": khash,
         "cpu_baseline": cpu,
     }
+
     def clean(o):
         if isinstance(o, dict):
             return {k: clean(v) for k, v in o.items()}

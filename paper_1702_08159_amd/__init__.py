@@ -112,18 +112,31 @@ def project(x: torch.Tensor, E: int, seed: int = PAPER_SEED, sigma: float = 1.0)
 
 
 def backward(x: torch.Tensor, dphi: torch.Tensor, E: int, seed: int = PAPER_SEED, sigma: float = 1.0,
-             need_dx: bool = True, need_params: bool = False):
-    """(dx, dB, dG, dS) of <dphi, phi(x)>; entries not requested are None."""
+             need_dx: bool = True, need_params: bool = False, out=None):
+    """(dx, dB, dG, dS) of <dphi, phi(x)>; entries not requested are None.
+    `out` may pass preallocated (dx, dB, dG, dS) (None entries are skipped)."""
     _check(x, "x")
     _check(dphi, "dphi")
     batch, d = _rows(x)
     n = padded_dim(d)
     if dphi.shape != (batch, 2 * n * E):
         raise ValueError("dphi must be batch x 2nE")
-    dx = torch.empty_like(x) if need_dx else None
-    dB = dG = dS = None
-    if need_params:
-        dB, dG, dS = (torch.empty((E, n), dtype=torch.float32, device=x.device) for _ in range(3))
+    if out is not None:
+        dx, dB, dG, dS = out
+        if dx is not None:
+            _check(dx, "dx")
+            if dx.shape != x.shape:
+                raise ValueError("dx must have the shape of x")
+        for t, nm in ((dB, "dB"), (dG, "dG"), (dS, "dS")):
+            if t is not None:
+                _check(t, nm)
+                if t.numel() != E * n:
+                    raise ValueError(nm + " must hold E x n values")
+    else:
+        dx = torch.empty_like(x) if need_dx else None
+        dB = dG = dS = None
+        if need_params:
+            dB, dG, dS = (torch.empty((E, n), dtype=torch.float32, device=x.device) for _ in range(3))
     with torch.cuda.device(x.device):
         _lib.call("mck_fastfood_backward", _ptr(x), _ptr(dphi), batch, d, E, seed & 0xFFFFFFFF, float(sigma),
                   MCK_CALIB_RBF, _ptr(dx), _ptr(dB), _ptr(dG), _ptr(dS), _stream(x))

@@ -291,32 +291,15 @@ __device__ __forceinline__ void bload_lane(LaneArr<TT, M, P>& v, rsrc_t r, uint3
 }
 
 // ------------------------------------------------------------------ feature map
-// cos and sin of pi*t (t in half turns), both scaled by c = 1/sqrt(nE).
-// t = k + f with k = rint(t), |f| <= 1/2; sin(pi f) = f P(f^2), cos(pi f) =
-// Q(f^2) with near-minimax polynomials (errors 3e-9 and 5e-8 on [-1/2, 1/2])
-// whose coefficients arrive pre-multiplied by c; (-1)^k fixes the sign.
-struct FeatCoef {
-    float s[5];
-    float c[5];
-};
-
-__device__ __forceinline__ void cossin_hturn(float t, const FeatCoef& q, float& co, float& si)
+// c cos(2 pi t) and c sin(2 pi t) for t in revolutions.  The argument is
+// reduced to [0, 1) exactly (fract), then the hardware sine and cosine
+// (inputs in revolutions, half rate on gfx950) give an absolute error of
+// about 1e-7, well inside the fp32 rounding already present in t.
+__device__ __forceinline__ void cossin_rev(float t, float c, float& co, float& si)
 {
-    const float k = __builtin_rintf(t);
-    const float f = t - k;
-    const float u = f * f;
-    float ps = __builtin_fmaf(q.s[4], u, q.s[3]);
-    ps = __builtin_fmaf(ps, u, q.s[2]);
-    ps = __builtin_fmaf(ps, u, q.s[1]);
-    ps = __builtin_fmaf(ps, u, q.s[0]);
-    float pc = __builtin_fmaf(q.c[4], u, q.c[3]);
-    pc = __builtin_fmaf(pc, u, q.c[2]);
-    pc = __builtin_fmaf(pc, u, q.c[1]);
-    pc = __builtin_fmaf(pc, u, q.c[0]);
-    const float s = ps * f;
-    const uint32_t sg = ((uint32_t)(int)k) << 31;
-    co = __uint_as_float(__float_as_uint(pc) ^ sg);
-    si = __uint_as_float(__float_as_uint(s) ^ sg);
+    const float r = __builtin_amdgcn_fractf(t);
+    co = c * __builtin_amdgcn_cosf(r);
+    si = c * __builtin_amdgcn_sinf(r);
 }
 
 }  // namespace mck

@@ -104,7 +104,7 @@ template <int M, int P, bool VEC, bool TRIG>
 __global__ void __launch_bounds__((Geo<M, P>::BLOCK), (Geo<M, P>::kMulti ? 1 : 4))
     k_forward(const float* __restrict__ x, uint32_t x_bytes, int64_t batch, int d, int E, int echunk, int nchunks,
               const float* __restrict__ B, const uint32_t* __restrict__ goff, const float* __restrict__ Gs,
-              const float* __restrict__ Sx, uint32_t par_bytes, uint32_t goff_bytes, FeatCoef coef,
+              const float* __restrict__ Sx, uint32_t par_bytes, uint32_t goff_bytes, float cs,
               float* __restrict__ out, uint32_t out_bytes)
 {
     using g = Geo<M, P>;
@@ -201,7 +201,7 @@ __global__ void __launch_bounds__((Geo<M, P>::BLOCK), (Geo<M, P>::kMulti ? 1 : 4
                     float c4[4], s4[4];
 #pragma unroll
                     for (int k = 0; k < 4; ++k)
-                        cossin_hturn(v[4 * j + k], coef, c4[k], s4[k]);
+                        cossin_rev(v[4 * j + k], cs, c4[k], s4[k]);
                     const uint32_t so = 4u * rpart(M, P, 0, 4 * j);
                     bstore4_nt(rY, yc + so, c4[0], c4[1], c4[2], c4[3]);
                     bstore4_nt(rY, ys + so, s4[0], s4[1], s4[2], s4[3]);
@@ -210,7 +210,7 @@ __global__ void __launch_bounds__((Geo<M, P>::BLOCK), (Geo<M, P>::kMulti ? 1 : 4
 #pragma unroll
                 for (int k = 0; k < EPL; ++k) {
                     float c1, s1;
-                    cossin_hturn(v[k], coef, c1, s1);
+                    cossin_rev(v[k], cs, c1, s1);
                     const uint32_t so = eo4 + 4u * rpart(M, P, 0, k);
                     bstore1(rY, yoff, so, c1);
                     bstore1(rY, yoff, 4u * nE + so, s1);
@@ -247,7 +247,7 @@ __global__ void __launch_bounds__(BwdGeo<M>::THREADS)
     k_backward(const float* __restrict__ x, uint32_t x_bytes, const float* __restrict__ dphi, uint32_t dphi_bytes,
                int64_t batch, int d, int E, const float* __restrict__ B, const uint32_t* __restrict__ goff,
                const float* __restrict__ Gk, const float* __restrict__ S32, const float* __restrict__ Sh,
-               uint32_t par_bytes, uint32_t goff_bytes, FeatCoef coef, float* __restrict__ dx,
+               uint32_t par_bytes, uint32_t goff_bytes, float cs, float* __restrict__ dx,
                float* __restrict__ partial, int passes)
 {
     using bg = BwdGeo<M>;
@@ -324,7 +324,7 @@ __global__ void __launch_bounds__(BwdGeo<M>::THREADS)
 #pragma unroll
                 for (int r = 0; r < EPL; ++r) {
                     float co, si;
-                    cossin_hturn(v[r] * sh[r], coef, co, si);
+                    cossin_rev(v[r] * sh[r], cs, co, si);
                     const float dz = co * gsn[r] - si * gc[r];
                     if constexpr (PARAMS)
                         aS[r] += dz * v[r];
@@ -426,22 +426,50 @@ __global__ void __launch_bounds__(BwdGeo<M>::THREADS)
 }
 
 // ------------------------------------------------------------------ reduce
-__global__ void k_reduce(const float* __restrict__ partial, int64_t blocks, int64_t E, int64_t n,
-                         float* __restrict__ dS, float* __restrict__ dG, float* __restrict__ dB)
+// out[a][e][i] = sum over b of partial[b][e][a][i], in a fixed order: wave w
+// of a block sums the blocks b = w, w + 4, w + 8, ... as 8 interleaved
+// running sums combined pairwise, then the 4 waves' sums are added in wave
+// order.  Each block covers 64 consecutive (a, e, i) outputs, so every load
+// instruction reads 256 contiguous bytes.
+constexpr int kRedSlices = 4;
+
+__global__ void __launch_bounds__(64 * kRedSlices)
+    k_reduce(const float* __restrict__ partial, int64_t blocks, int64_t E, int64_t n, float* __restrict__ dS,
+             float* __restrict__ dG, float* __restrict__ dB)
 {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= 3 * E * n)
-        return;
-    const int64_t a = idx / (E * n);
-    const int64_t rem = idx % (E * n);
+    __shared__ float part[kRedSlices][64];
+    const int64_t en = E * n;
+    const int64_t idx = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+    const int w = (int)(threadIdx.x >> 6);
+    const bool live = idx < 3 * en;
+    const int64_t a = live ? idx / en : 0;
+    const int64_t rem = live ? idx % en : 0;
     const int64_t e = rem / n, i = rem % n;
-    float* out = a == 0 ? dS : (a == 1 ? dG : dB);
-    if (out == nullptr)
-        return;
-    float s = 0.f;
-    for (int64_t b = 0; b < blocks; ++b)
-        s += partial[((b * E + e) * 3 + a) * n + i];
-    out[e * n + i] = s;
+    const float* src = partial + (e * 3 + a) * n + i;
+    const int64_t stride = 3 * en;
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (live) {
+        int64_t b = w;
+        for (; b + 7 * kRedSlices < blocks; b += 8 * kRedSlices) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                acc[k] += src[(b + k * kRedSlices) * stride];
+        }
+#pragma unroll
+        for (int k = 0; k < 7; ++k)
+            if (b + k * kRedSlices < blocks)
+                acc[k] += src[(b + k * kRedSlices) * stride];
+    }
+    part[w][threadIdx.x & 63] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+    __syncthreads();
+    if (w == 0 && live) {
+        float s = part[0][threadIdx.x];
+        for (int k = 1; k < kRedSlices; ++k)
+            s += part[k][threadIdx.x];
+        float* out = a == 0 ? dS : (a == 1 ? dG : dB);
+        if (out != nullptr)
+            out[e * n + i] = s;
+    }
 }
 
 // ------------------------------------------------------------------ derive
@@ -451,7 +479,7 @@ __global__ void k_reduce(const float* __restrict__ partial, int64_t blocks, int6
 //   Gk[e][t][r] = G[e][i] for the element i held there (destination order);
 //   Gs[e][q] = G[e][j] for the destination j whose gather source perm[j]
 //     sits at lane-major slot q (G moved to source order);
-// and Sh = S / pi (S in half turns) in natural order.
+// and Sh = S / (2 pi) (S in revolutions) in natural order.
 template <int M, int P>
 __device__ __forceinline__ uint32_t lane_major_slot(uint32_t i)
 {
@@ -495,9 +523,9 @@ __global__ void k_derive(int64_t E, const int32_t* __restrict__ perm, const floa
             Gs[e * n + lane_major_slot<M, P>(srcq)] = G[e * n + q];
         }
         if (Sh) {
-            // S in half turns for the feature map, from the FP64 value when present
+            // S in revolutions for the feature map, from the FP64 value when present
             const double sv = S64 ? S64[e * n + q] : (double)S32[e * n + q];
-            Sh[e * n + q] = (float)(sv * 0.31830988618379067154);
+            Sh[e * n + q] = (float)(sv * 0.15915494309189533577);
         }
     }
 }
@@ -526,16 +554,6 @@ hipError_t dispatch_m(int M, A&&... args)
     }
 }
 
-FeatCoef to_dev(const FeatCoefHost& h)
-{
-    FeatCoef c;
-    for (int i = 0; i < 5; ++i) {
-        c.s[i] = h.s[i];
-        c.c[i] = h.c[i];
-    }
-    return c;
-}
-
 template <int M>
 struct RunFwht {
     static hipError_t run(float* data, int64_t batch, bool vec, hipStream_t s)
@@ -562,7 +580,7 @@ struct RunFwht {
 template <int M>
 struct RunForward {
     static hipError_t run(bool vec, bool trig, const float* x, int64_t batch, int d, int64_t E, const float* B,
-                          const uint32_t* goff, const float* Gs, const float* Sx, const FeatCoef& coef, float* out,
+                          const uint32_t* goff, const float* Gs, const float* Sx, float cs, float* out,
                           hipStream_t s)
     {
         constexpr int P = fwd_p(M);
@@ -589,7 +607,7 @@ struct RunForward {
             float* os = out + r0 * out_row;
             const uint32_t xb = (uint32_t)(4 * rows * d), ob = (uint32_t)(4 * rows * out_row);
             const int Ei = (int)E, ec = (int)echunk, nc = (int)nchunks;
-#define MCK_FWD_ARGS xs, xb, rows, d, Ei, ec, nc, B, goff, Gs, Sx, par_bytes, goff_bytes, coef, os, ob
+#define MCK_FWD_ARGS xs, xb, rows, d, Ei, ec, nc, B, goff, Gs, Sx, par_bytes, goff_bytes, cs, os, ob
             if (vec && M >= 2) {
                 if (trig)
                     k_forward<M, P, true, true><<<grid, blk, 0, s>>>(MCK_FWD_ARGS);
@@ -614,7 +632,7 @@ template <int M>
 struct RunBackward {
     static hipError_t run(bool vec, const float* x, const float* dphi, int64_t batch, int d, int64_t E,
                           const float* B, const uint32_t* goff, const float* Gk, const float* S32, const float* Sh,
-                          const FeatCoef& coef, float* dx, float* partial, const BwdGeometry& geo, hipStream_t s)
+                          float cs, float* dx, float* partial, const BwdGeometry& geo, hipStream_t s)
     {
         using bg = BwdGeo<M>;
         using g = typename bg::g;
@@ -623,7 +641,7 @@ struct RunBackward {
         const uint32_t xb = (uint32_t)(4 * batch * d), db = (uint32_t)(4 * batch * 2 * g::n * E);
         const uint32_t par_bytes = (uint32_t)(4 * g::n * E);
         const uint32_t goff_bytes = (uint32_t)(4 * g::RPB * g::n * E);
-#define MCK_BWD_ARGS x, xb, dphi, db, batch, d, Ei, B, goff, Gk, S32, Sh, par_bytes, goff_bytes, coef, dx, partial, \
+#define MCK_BWD_ARGS x, xb, dphi, db, batch, d, Ei, B, goff, Gk, S32, Sh, par_bytes, goff_bytes, cs, dx, partial, \
                      geo.passes
         if (vec && M >= 2) {
             if (partial)
@@ -696,10 +714,9 @@ hipError_t launch_fwht(int M, float* data, int64_t batch, bool vec, hipStream_t 
 
 hipError_t launch_forward(int M, bool vec, bool trig, const float* x, int64_t batch, int d, int64_t E,
                           const float* B, const uint32_t* goff, const float* Gs, const float* Sx,
-                          const FeatCoefHost& coef, float* out, hipStream_t s)
+                          float cs, float* out, hipStream_t s)
 {
-    const FeatCoef c = to_dev(coef);
-    return dispatch_m<RunForward>(M, vec, trig, x, batch, d, E, B, goff, Gs, Sx, c, out, s);
+    return dispatch_m<RunForward>(M, vec, trig, x, batch, d, E, B, goff, Gs, Sx, cs, out, s);
 }
 
 BwdGeometry backward_geometry(int M, int64_t batch)
@@ -711,18 +728,18 @@ BwdGeometry backward_geometry(int M, int64_t batch)
 
 hipError_t launch_backward(int M, bool vec, const float* x, const float* dphi, int64_t batch, int d, int64_t E,
                            const float* B, const uint32_t* goff, const float* Gk, const float* S32,
-                           const float* Sh, const FeatCoefHost& coef, float* dx, float* partial,
+                           const float* Sh, float cs, float* dx, float* partial,
                            const BwdGeometry& geo, hipStream_t s)
 {
-    const FeatCoef c = to_dev(coef);
-    return dispatch_m<RunBackward>(M, vec, x, dphi, batch, d, E, B, goff, Gk, S32, Sh, c, dx, partial, geo, s);
+    return dispatch_m<RunBackward>(M, vec, x, dphi, batch, d, E, B, goff, Gk, S32, Sh, cs, dx, partial, geo, s);
 }
 
 hipError_t launch_reduce(const float* partial, int64_t blocks, int64_t E, int64_t n, float* dS, float* dG,
                          float* dB, hipStream_t s)
 {
     const int64_t total = 3 * E * n;
-    k_reduce<<<dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s>>>(partial, blocks, E, n, dS, dG, dB);
+    k_reduce<<<dim3((unsigned)((total + 63) / 64)), dim3(64 * kRedSlices), 0, s>>>(partial, blocks, E, n, dS, dG,
+                                                                                  dB);
     return hipGetLastError();
 }
 

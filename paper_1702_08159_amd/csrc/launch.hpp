@@ -7,12 +7,6 @@
 
 namespace mck {
 
-// c-scaled coefficients of the feature map (see engine.hpp)
-struct FeatCoefHost {
-    float s[5];
-    float c[5];
-};
-
 // Parameter generator: B, perm, G, S64, S32 (E x n each); norm2 is E doubles
 // of scratch.  Six kernels on stream s.
 hipError_t launch_generate(uint32_t seed, int64_t n, int64_t E, double sigma, float* B, int32_t* perm, float* G,
@@ -37,7 +31,7 @@ hipError_t launch_fwht(int M, float* data, int64_t batch, bool vec, hipStream_t 
 // Forward: phi (trig = true) or z = S H G Pi H B xhat (trig = false).
 hipError_t launch_forward(int M, bool vec, bool trig, const float* x, int64_t batch, int d, int64_t E,
                           const float* B, const uint32_t* goff, const float* Gs, const float* Sx,
-                          const FeatCoefHost& coef, float* out, hipStream_t s);
+                          float cs, float* out, hipStream_t s);
 
 // Backward geometry: blocks, passes per block.
 struct BwdGeometry {
@@ -51,7 +45,7 @@ BwdGeometry backward_geometry(int M, int64_t batch);
 // of dS, dG, dB (blocks x E x 3 x n) reduced afterwards by launch_reduce.
 hipError_t launch_backward(int M, bool vec, const float* x, const float* dphi, int64_t batch, int d, int64_t E,
                            const float* B, const uint32_t* goff, const float* Gk, const float* S32,
-                           const float* Sh, const FeatCoefHost& coef, float* dx, float* partial,
+                           const float* Sh, float cs, float* dx, float* partial,
                            const BwdGeometry& geo, hipStream_t s);
 
 // Fixed-order sum of the partials: out_a[e][i] = sum_b partial[b][e][a][i]

@@ -51,22 +51,8 @@ int64_t padded_dim(int64_t d)
 
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
-// Near-minimax coefficients of sin(pi f)/f and cos(pi f) in u = f^2 on
-// |f| <= 1/2 (max errors 3.3e-9 and 4.7e-8), scaled by c = 1/sqrt(nE).
-mck::FeatCoefHost feature_coefficients(int64_t n, int64_t E)
-{
-    static const double ks[5] = {3.141592580044727, -5.167706878926373, 2.5500313772798826, -0.5980451741176938,
-                                 0.07722012894382006};
-    static const double kc[5] = {0.9999999534666582, -4.934792858674183, 4.0584119141457276, -1.3318801611124893,
-                                 0.21969679833150207};
-    const double c = 1.0 / std::sqrt((double)n * (double)E);
-    mck::FeatCoefHost h;
-    for (int i = 0; i < 5; ++i) {
-        h.s[i] = (float)(ks[i] * c);
-        h.c[i] = (float)(kc[i] * c);
-    }
-    return h;
-}
+// Feature scale c = 1/sqrt(nE) of phi (equation mcfeatures).
+float feature_scale(int64_t n, int64_t E) { return (float)(1.0 / std::sqrt((double)n * (double)E)); }
 
 mck_status check_sigma(double sigma)
 {
@@ -113,7 +99,7 @@ struct Plan {
     float* GsF = nullptr;       // G in source order, forward layout
     uint32_t* goffB = nullptr;  // backward gather offsets
     float* GkB = nullptr;       // G in destination order, backward layout
-    float* Sh = nullptr;        // S / pi
+    float* Sh = nullptr;        // S / (2 pi)
 };
 
 std::mutex g_mutex;
@@ -272,7 +258,7 @@ mck_status run_backward(const float* x, const float* dphi, int64_t batch, int64_
             return fail(MCK_ERR_NO_MEMORY, std::string("backward partials: ") + hipGetErrorString(err));
     }
     const bool vec = vec_ok(x, dphi, d, n) && (dx == nullptr || aligned16(dx));
-    const mck::FeatCoefHost coef = feature_coefficients(n, E);
+    const float cs = feature_scale(n, E);
     err = hipSuccess;
     int64_t done_blocks = 0;
     for (int64_t r0 = 0; r0 < batch && err == hipSuccess; r0 += rows_per) {
@@ -280,7 +266,7 @@ mck_status run_backward(const float* x, const float* dphi, int64_t batch, int64_
         const mck::BwdGeometry geo = mck::backward_geometry(M, rows);
         float* part = partial ? partial + (size_t)done_blocks * E * 3 * n : nullptr;
         err = mck::launch_backward(M, vec, x + r0 * d, dphi + r0 * 2 * n * E, rows, (int)d, E, B, goff, Gk, S32, Sh,
-                                   coef, dx ? dx + r0 * d : nullptr, part, geo, s);
+                                   cs, dx ? dx + r0 * d : nullptr, part, geo, s);
         done_blocks += geo.blocks;
     }
     if (err == hipSuccess && want_params)
@@ -385,7 +371,7 @@ static mck_status forward_common(const float* x, int64_t batch, int64_t d, int64
     if (st != MCK_OK)
         return st;
     const hipError_t err = mck::launch_forward(log2i(n), vec_ok(x, out, d, n), trig, x, batch, (int)d, E, p->B,
-                                               p->goffF, p->GsF, trig ? p->Sh : p->S32, feature_coefficients(n, E),
+                                               p->goffF, p->GsF, trig ? p->Sh : p->S32, feature_scale(n, E),
                                                out, s);
     return err == hipSuccess ? MCK_OK : hip_fail(err, "forward launch");
 }
@@ -467,7 +453,7 @@ mck_status mck_fastfood_forward_p(const float* x, int64_t batch, int64_t d, int6
     if (st != MCK_OK)
         return st;
     hipError_t err = mck::launch_forward(log2i(n), vec_ok(x, phi, d, n), true, x, batch, (int)d, E, B, tp.goffF, tp.GsF,
-                                         tp.Sh, feature_coefficients(n, E), phi, s);
+                                         tp.Sh, feature_scale(n, E), phi, s);
     (void)hipFreeAsync(tp.block, s);
     return err == hipSuccess ? MCK_OK : hip_fail(err, "forward launch");
 }
