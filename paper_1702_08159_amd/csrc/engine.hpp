@@ -182,9 +182,11 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void* p, uint32_t bytes)
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
 }
 
+// AUX = cache policy bits of the instruction (2: streaming / non-temporal).
+template <int AUX = 0>
 __device__ __forceinline__ void bload4(float* dst, rsrc_t r, uint32_t voff, uint32_t soff)
 {
-    const v4i q = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0);
+    const v4i q = __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, AUX);
     dst[0] = __int_as_float(q.x);
     dst[1] = __int_as_float(q.y);
     dst[2] = __int_as_float(q.z);
@@ -200,9 +202,10 @@ __device__ __forceinline__ void bload4u(uint32_t* dst, rsrc_t r, uint32_t voff, 
     dst[3] = (uint32_t)q.w;
 }
 
+template <int AUX = 0>
 __device__ __forceinline__ float bload1(rsrc_t r, uint32_t voff, uint32_t soff)
 {
-    return __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+    return __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, AUX));
 }
 
 // 128-bit stores take the whole byte offset in the VGPR (constant parts go
@@ -230,7 +233,7 @@ __device__ __forceinline__ void bstore1(rsrc_t r, uint32_t voff, uint32_t soff, 
 
 // Row of length d at byte offset rowoff (zero-padded to n) into the
 // coalesced layout; invalid rows read as zero.
-template <int M, int P, bool VEC>
+template <int M, int P, bool VEC, int AUX = 0>
 __device__ __forceinline__ void bload_row(LaneArr<float, M, P>& v, rsrc_t r, uint32_t rowoff, int d, uint32_t t,
                                           bool valid)
 {
@@ -241,13 +244,13 @@ __device__ __forceinline__ void bload_row(LaneArr<float, M, P>& v, rsrc_t r, uin
         for (int j = 0; j < EPL / 4; ++j) {
             const uint32_t i0 = tb | rpart(M, P, 0, 4 * j);
             const uint32_t off = (valid && (int)i0 < d) ? rowoff + 4u * i0 : kOutOfRange;
-            bload4(&v[4 * j], r, off, 0);
+            bload4<AUX>(&v[4 * j], r, off, 0);
         }
     } else {
 #pragma unroll
         for (int k = 0; k < EPL; ++k) {
             const uint32_t i = tb | rpart(M, P, 0, k);
-            v[k] = bload1(r, (valid && (int)i < d) ? rowoff + 4u * i : kOutOfRange, 0);
+            v[k] = bload1<AUX>(r, (valid && (int)i < d) ? rowoff + 4u * i : kOutOfRange, 0);
         }
     }
 }

@@ -240,7 +240,56 @@ struct BwdGeo {
     static constexpr int NW = g::kMulti ? 1 : kBwdWaves;
     static constexpr int THREADS = g::BLOCK * NW;
     static constexpr int ROWS = NW * g::RPB;  // rows per block per pass
+    // Rows of one wave or less: the block's dx rows stay in LDS (dynamic
+    // shared memory, rows x d) across the expansion loop and are written
+    // once.  Longer rows read-modify-write dx in HBM per expansion.
+    static constexpr bool XRES = !g::kMulti;
+    static constexpr int STATIC_LDS = (NW * g::LDS_FLOATS + 3) / 4 * 16;
+    static constexpr int PARAM_LDS = XRES ? (4 * g::n + g::RPB * g::n) * 4 : 0;
 };
+
+constexpr int kLdsBytes = 160 * 1024;
+
+// Sum of the three per-lane accumulators (dS and dB in the coalesced
+// layout, dG in the gather layout) over the rows of a block, in slot order
+// (wave, row group), written as the block's partial dst[3][n].  Uses the
+// first NW * RPB * n floats of the transform scratch; all threads of the
+// block must call it.
+template <int M>
+__device__ __forceinline__ void block_partials(float* lds, const LaneArr<float, M, BwdGeo<M>::P>& aS,
+                                               const LaneArr<float, M, BwdGeo<M>::P>& aG,
+                                               const LaneArr<float, M, BwdGeo<M>::P>& aB, float* dst,
+                                               uint32_t wave, uint32_t grp, uint32_t t)
+{
+    using bg = BwdGeo<M>;
+    constexpr int P = bg::P;
+    using g = Geo<M, P>;
+    constexpr int EPL = g::EPL, n = g::n, K = g::K, SLOTS = bg::NW * g::RPB;
+    float* slot = lds + (wave * g::RPB + grp) * n;
+    const uint32_t ct = tpart<M, P, 0>(t), tk = tpart<M, P, K>(t);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        __syncthreads();
+        if (a == 1) {
+#pragma unroll
+            for (int r = 0; r < EPL; ++r)
+                slot[tk | rpart(M, P, K, r)] = aG[r];
+        } else {
+            const float* acc = a == 0 ? aS : aB;
+#pragma unroll
+            for (int r = 0; r < EPL; ++r)
+                slot[ct | rpart(M, P, 0, r)] = acc[r];
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += bg::THREADS) {
+            float s = 0.f;
+            for (int k = 0; k < SLOTS; ++k)
+                s += lds[k * n + i];
+            dst[(int64_t)a * n + i] = s;
+        }
+    }
+    __syncthreads();
+}
 
 template <int M, bool VEC, bool PARAMS>
 __global__ void __launch_bounds__(BwdGeo<M>::THREADS)
@@ -255,7 +304,7 @@ __global__ void __launch_bounds__(BwdGeo<M>::THREADS)
     using g = Geo<M, P>;
     constexpr int EPL = g::EPL, n = g::n, K = g::K;
     constexpr uint32_t kGoffE = (uint32_t)g::RPB * n;
-    __shared__ float lds[bg::NW * g::LDS_FLOATS];
+    __shared__ __align__(16) float lds[bg::STATIC_LDS / 4];
     const uint32_t wave = g::kMulti ? 0u : threadIdx.x / 64u;
     const uint32_t lane = g::kMulti ? threadIdx.x : threadIdx.x % 64u;
     const uint32_t grp = g::kMulti ? 0u : lane >> g::T;
@@ -317,8 +366,8 @@ __global__ void __launch_bounds__(BwdGeo<M>::THREADS)
             // dz = c (-sin z dphi_cos + cos z dphi_sin); dS += dz v3; g3 = S dz
             {
                 float gc[EPL], gsn[EPL];
-                bload_row<M, P, VEC>(gc, rD, goffr + eo4, n, t, valid);
-                bload_row<M, P, VEC>(gsn, rD, goffr + 4u * nE + eo4, n, t, valid);
+                bload_row<M, P, VEC, 2>(gc, rD, goffr + eo4, n, t, valid);
+                bload_row<M, P, VEC, 2>(gsn, rD, goffr + 4u * nE + eo4, n, t, valid);
                 float sh[EPL];
                 bload_coal<M, P>(sh, rH, eo4, t);
 #pragma unroll
@@ -393,35 +442,263 @@ __global__ void __launch_bounds__(BwdGeo<M>::THREADS)
             }
         }
 
-        if constexpr (PARAMS) {
-            // block sum of the three accumulators in slot order (wave, group)
-            constexpr int SLOTS = bg::NW * g::RPB;
-            float* slot = lds + (wave * g::RPB + grp) * n;
-            float* dst = partial + (((int64_t)blockIdx.x * E + e) * 3) * n;
+        if constexpr (PARAMS)
+            block_partials<M>(lds, aS, aG, aB, partial + (((int64_t)blockIdx.x * E + e) * 3) * n, wave, grp, t);
+    }
+}
+
+// Backward for rows of one wave or less (n <= 1024).  A block of NW waves
+// owns passes x ROWS consecutive rows for all expansions:
+//  - the block's dx rows accumulate in LDS (dynamic shared memory) and are
+//    written to HBM once at the end;
+//  - at the start of each expansion the block stages that expansion's B,
+//    S, S/(2 pi), G and gather offsets in LDS, so the pass loop issues no
+//    parameter loads to L2;
+//  - dphi of the next (row, expansion) is loaded into spare VGPRs right
+//    after the current dphi is consumed, so its HBM latency hides behind
+//    the adjoint half of the current one.  (Loads complete in issue order
+//    for the vector-memory counter, which is why the only other load in the
+//    loop, x of the row, is issued at the top of the next iteration.)
+// Rows owned by no block lane (past the batch) read as zero and are never
+// written.
+template <int M, bool VEC, bool PARAMS>
+__global__ void __launch_bounds__(BwdGeo<M>::THREADS)
+    k_backward_rows(const float* __restrict__ x, uint32_t x_bytes, const float* __restrict__ dphi,
+                    uint32_t dphi_bytes, int64_t batch, int d, int E, const float* __restrict__ B,
+                    const uint32_t* __restrict__ goff, const float* __restrict__ Gk, const float* __restrict__ S32,
+                    const float* __restrict__ Sh, float cs, float* __restrict__ dx, float* __restrict__ partial,
+                    int passes)
+{
+    using bg = BwdGeo<M>;
+    constexpr int P = bg::P;
+    using g = Geo<M, P>;
+    static_assert(!g::kMulti, "rows of one wave or less");
+    constexpr int EPL = g::EPL, n = g::n, K = g::K, NQ = EPL / 4 > 0 ? EPL / 4 : 1;
+    constexpr int GOFF_E = g::RPB * n;  // gather offsets per expansion (all row groups of a wave)
+    // parameter stage: B, S, S/(2 pi) in natural order; G and the gather
+    // offsets float4-major (chunk j of lane t at (j * lanes + t) * 4) so
+    // that a wave's float4 reads hit consecutive LDS addresses
+    constexpr int PB = 0, PS = n, PH = 2 * n, PG = 3 * n, PO = 4 * n, PRM = 4 * n + GOFF_E;
+    __shared__ __align__(16) float lds[bg::STATIC_LDS / 4];
+    __shared__ __align__(16) float prm[PRM];
+    extern __shared__ float4 dxl4[];  // passes x ROWS rows of d4 floats
+    float* dxl = reinterpret_cast<float*>(dxl4);
+    const int d4 = (d + 3) & ~3;
+
+    const uint32_t wave = threadIdx.x / 64u;
+    const uint32_t lane = threadIdx.x % 64u;
+    const uint32_t grp = lane >> g::T;
+    const uint32_t t = lane & (g::LPR - 1);
+    float* wbuf = lds + wave * g::LDS_FLOATS;
+    float* buf = wbuf + grp * g::STRIDE;
+    char* lbytes = reinterpret_cast<char*>(wbuf);
+    const uint32_t nE = (uint32_t)n * (uint32_t)E;
+    const uint32_t ct = tpart<M, P, 0>(t);
+    const rsrc_t rx = make_rsrc(x, x_bytes), rD = make_rsrc(dphi, dphi_bytes);
+    const int64_t row_base = (int64_t)blockIdx.x * passes * bg::ROWS + wave * g::RPB + grp;
+
+    // dphi of the next (row, expansion), prefetched
+    float cn[EPL], sn[EPL];
+    auto prefetch = [&](int e, int p) {
+        const int64_t row = row_base + (int64_t)p * bg::ROWS;
+        const bool valid = e < E && row < batch;
+        const uint32_t doff = valid ? (uint32_t)(row * 2 * (int64_t)nE) * 4u + 4u * (uint32_t)e * n : 0u;
+        bload_row<M, P, VEC, 2>(cn, rD, doff, n, t, valid);
+        bload_row<M, P, VEC, 2>(sn, rD, doff + 4u * nE, n, t, valid);
+    };
+    prefetch(0, 0);
+
+    auto ld_nat = [&](float (&v)[EPL], int base) {  // natural-order parameter, coalesced layout
+        const float* b0 = prm + base + ct;
+        if constexpr (M >= 2) {
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                __syncthreads();
-                if (a == 1) {
-                    const uint32_t tk = tpart<M, P, K>(t);
+            for (int j = 0; j < EPL / 4; ++j) {
+                const float4 q = *reinterpret_cast<const float4*>(b0 + rpart(M, P, 0, 4 * j));
+                v[4 * j] = q.x;
+                v[4 * j + 1] = q.y;
+                v[4 * j + 2] = q.z;
+                v[4 * j + 3] = q.w;
+            }
+        } else {
 #pragma unroll
-                    for (int r = 0; r < EPL; ++r)
-                        slot[tk | rpart(M, P, K, r)] = aG[r];
-                } else {
-                    const float* acc = a == 0 ? aS : aB;
+            for (int k = 0; k < EPL; ++k)
+                v[k] = b0[rpart(M, P, 0, k)];
+        }
+    };
+    auto ld_lane = [&](float (&v)[EPL], int base, uint32_t q, uint32_t lanes) {  // float4-major, lane q
+        if constexpr (EPL >= 4) {
 #pragma unroll
-                    for (int r = 0; r < EPL; ++r)
-                        slot[ct | rpart(M, P, 0, r)] = acc[r];
-                }
-                __syncthreads();
-                for (int i = threadIdx.x; i < n; i += bg::THREADS) {
-                    float s = 0.f;
-                    for (int k = 0; k < SLOTS; ++k)
-                        s += lds[k * n + i];
-                    dst[(int64_t)a * n + i] = s;
-                }
+            for (int j = 0; j < NQ; ++j) {
+                const float4 f = *reinterpret_cast<const float4*>(prm + base + (j * lanes + q) * 4);
+                v[4 * j] = f.x;
+                v[4 * j + 1] = f.y;
+                v[4 * j + 2] = f.z;
+                v[4 * j + 3] = f.w;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < EPL; ++k)
+                v[k] = prm[base + q * EPL + k];
+        }
+    };
+
+    for (int e = 0; e < E; ++e) {
+        // stage the expansion's parameters (all earlier readers are done:
+        // the previous expansion ended with a block barrier)
+        {
+            const float* srcB = B + (int64_t)e * n;
+            const float* srcS = S32 + (int64_t)e * n;
+            const float* srcH = Sh + (int64_t)e * n;
+            const float* srcG = Gk + (int64_t)e * n;
+            const uint32_t* srcO = goff + (int64_t)e * GOFF_E;
+            for (int i = threadIdx.x; i < n; i += bg::THREADS) {
+                prm[PB + i] = srcB[i];
+                prm[PS + i] = srcS[i];
+                prm[PH + i] = srcH[i];
+                // lane-major source (t * EPL + r) to float4-major
+                const int tq = i / EPL, r = i % EPL;
+                prm[PG + ((r / 4) * g::LPR + tq) * 4 + (r % 4)] = srcG[i];
+            }
+            for (int i = threadIdx.x; i < GOFF_E; i += bg::THREADS) {
+                const int lq = i / EPL, r = i % EPL;
+                prm[PO + ((r / 4) * 64 + lq) * 4 + (r % 4)] = __uint_as_float(srcO[i]);
             }
             __syncthreads();
         }
+        float aS[EPL], aG[EPL], aB[EPL];
+        if constexpr (PARAMS) {
+#pragma unroll
+            for (int r = 0; r < EPL; ++r)
+                aS[r] = aG[r] = aB[r] = 0.f;
+        }
+        for (int p = 0; p < passes; ++p) {
+            const int64_t row = row_base + (int64_t)p * bg::ROWS;
+            const bool valid = row < batch;
+            // x of this row (L2-resident after the first expansion); its wait
+            // also covers the dphi prefetch issued half an iteration ago
+            float xh[EPL];
+            bload_row<M, P, VEC>(xh, rx, valid ? (uint32_t)(row * d) * 4u : 0u, d, t, valid);
+
+            // forward recompute: v1 = H B xhat, w = Pi v1, v3 = H G w
+            float v[EPL], q[EPL];
+            ld_nat(q, PB);
+#pragma unroll
+            for (int r = 0; r < EPL; ++r)
+                v[r] = xh[r] * q[r];
+            fwht_up<M, P>(v, buf, t);
+            lds_put<M, P, K>(buf, t, v);
+            lds_sync<M, P>();
+            float w[EPL];
+            {
+                float of[EPL];
+                ld_lane(of, PO, lane, 64);
+#pragma unroll
+                for (int r = 0; r < EPL; ++r)
+                    w[r] = *reinterpret_cast<const float*>(lbytes + __float_as_uint(of[r]));
+            }
+            lds_sync<M, P>();
+            ld_lane(q, PG, t, g::LPR);
+#pragma unroll
+            for (int r = 0; r < EPL; ++r)
+                v[r] = w[r] * q[r];
+            fwht_down<M, P>(v, buf, t);
+
+            // dz = c (-sin z dphi_cos + cos z dphi_sin); dS += dz v3; g3 = S dz
+            ld_nat(q, PH);
+#pragma unroll
+            for (int r = 0; r < EPL; ++r) {
+                float co, si;
+                cossin_rev(v[r] * q[r], cs, co, si);
+                const float dz = co * sn[r] - si * cn[r];
+                if constexpr (PARAMS)
+                    aS[r] += dz * v[r];
+                v[r] = dz;
+            }
+            // dphi of the next (row, expansion) while the adjoint runs;
+            // the scheduling barrier keeps these loads after the last use of
+            // the registers they overwrite
+            __builtin_amdgcn_sched_barrier(0);
+            if (p + 1 < passes)
+                prefetch(e, p + 1);
+            else
+                prefetch(e + 1, 0);
+            __builtin_amdgcn_sched_barrier(0);
+            ld_nat(q, PS);
+#pragma unroll
+            for (int r = 0; r < EPL; ++r)
+                v[r] *= q[r];
+
+            // g2 = H g3 (gather layout); dG += g2 w; Pi^T scatter of G g2
+            fwht_up<M, P>(v, buf, t);
+            ld_lane(q, PG, t, g::LPR);
+#pragma unroll
+            for (int r = 0; r < EPL; ++r) {
+                if constexpr (PARAMS)
+                    aG[r] += v[r] * w[r];
+                v[r] *= q[r];
+            }
+            {
+                float of[EPL];
+                ld_lane(of, PO, lane, 64);
+#pragma unroll
+                for (int r = 0; r < EPL; ++r)
+                    *reinterpret_cast<float*>(lbytes + __float_as_uint(of[r])) = v[r];
+            }
+            lds_sync<M, P>();
+            lds_get<M, P, K>(buf, t, v);
+            lds_sync<M, P>();
+            // g0 = H g1 (coalesced layout); dB += g0 xhat; dx += B g0
+            fwht_down<M, P>(v, buf, t);
+            ld_nat(q, PB);
+#pragma unroll
+            for (int r = 0; r < EPL; ++r) {
+                if constexpr (PARAMS)
+                    aB[r] += v[r] * xh[r];
+                v[r] *= q[r];
+            }
+            if (dx != nullptr) {
+                float* drow = dxl + (uint32_t)(p * bg::ROWS + (int)(wave * g::RPB + grp)) * (uint32_t)d4;
+                if constexpr (VEC) {
+#pragma unroll
+                    for (int j = 0; j < EPL / 4; ++j) {
+                        const uint32_t i0 = ct | rpart(M, P, 0, 4 * j);
+                        if (valid && (int)i0 < d) {
+                            float4* dq = reinterpret_cast<float4*>(drow + i0);
+                            float4 a = make_float4(v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]);
+                            if (e > 0) {
+                                const float4 o = *dq;
+                                a.x += o.x;
+                                a.y += o.y;
+                                a.z += o.z;
+                                a.w += o.w;
+                            }
+                            *dq = a;
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < EPL; ++k) {
+                        const uint32_t i = ct | rpart(M, P, 0, k);
+                        if (valid && (int)i < d)
+                            drow[i] = e > 0 ? drow[i] + v[k] : v[k];
+                    }
+                }
+            }
+        }
+        if constexpr (PARAMS)
+            block_partials<M>(lds, aS, aG, aB, partial + (((int64_t)blockIdx.x * E + e) * 3) * n, wave, grp, t);
+        else
+            __syncthreads();  // the parameter stage is rewritten next
+    }
+    if (dx != nullptr) {
+        // every wave has added its last expansion: copy the rows out
+        __syncthreads();
+        const int64_t row0 = (int64_t)blockIdx.x * passes * bg::ROWS;
+        const int64_t left = batch - row0;
+        const int nrows = left < (int64_t)passes * bg::ROWS ? (int)left : passes * bg::ROWS;
+        for (int r = 0; r < nrows; ++r)
+            for (int i = threadIdx.x; i < d; i += bg::THREADS)
+                dx[(row0 + r) * d + i] = dxl[r * d4 + i];
     }
 }
 
@@ -638,36 +915,62 @@ struct RunBackward {
         using g = typename bg::g;
         const dim3 grid((unsigned)geo.blocks), blk(bg::THREADS);
         const int Ei = (int)E;
+        const size_t dyn = bg::XRES && dx ? (size_t)geo.passes * bg::ROWS * ((d + 3) & ~3) * 4 : 0;
         const uint32_t xb = (uint32_t)(4 * batch * d), db = (uint32_t)(4 * batch * 2 * g::n * E);
         const uint32_t par_bytes = (uint32_t)(4 * g::n * E);
         const uint32_t goff_bytes = (uint32_t)(4 * g::RPB * g::n * E);
+        auto launch = [&](auto kern, auto... args) -> hipError_t {
+            if (dyn > 0) {
+                const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+                if (e != hipSuccess)
+                    return e;
+            }
+            kern<<<grid, blk, dyn, s>>>(args...);
+            return hipGetLastError();
+        };
 #define MCK_BWD_ARGS x, xb, dphi, db, batch, d, Ei, B, goff, Gk, S32, Sh, par_bytes, goff_bytes, cs, dx, partial, \
                      geo.passes
-        if (vec && M >= 2) {
-            if (partial)
-                k_backward<M, true, true><<<grid, blk, 0, s>>>(MCK_BWD_ARGS);
+#define MCK_BWDR_ARGS x, xb, dphi, db, batch, d, Ei, B, goff, Gk, S32, Sh, cs, dx, partial, geo.passes
+        hipError_t err;
+        if constexpr (bg::XRES) {
+            if (vec && M >= 2)
+                err = partial ? launch(k_backward_rows<M, true, true>, MCK_BWDR_ARGS)
+                              : launch(k_backward_rows<M, true, false>, MCK_BWDR_ARGS);
             else
-                k_backward<M, true, false><<<grid, blk, 0, s>>>(MCK_BWD_ARGS);
+                err = partial ? launch(k_backward_rows<M, false, true>, MCK_BWDR_ARGS)
+                              : launch(k_backward_rows<M, false, false>, MCK_BWDR_ARGS);
         } else {
-            if (partial)
-                k_backward<M, false, true><<<grid, blk, 0, s>>>(MCK_BWD_ARGS);
+            if (vec && M >= 2)
+                err = partial ? launch(k_backward<M, true, true>, MCK_BWD_ARGS)
+                              : launch(k_backward<M, true, false>, MCK_BWD_ARGS);
             else
-                k_backward<M, false, false><<<grid, blk, 0, s>>>(MCK_BWD_ARGS);
+                err = partial ? launch(k_backward<M, false, true>, MCK_BWD_ARGS)
+                              : launch(k_backward<M, false, false>, MCK_BWD_ARGS);
         }
 #undef MCK_BWD_ARGS
-        return hipGetLastError();
+#undef MCK_BWDR_ARGS
+        return err;
     }
 };
 
 template <int M>
 struct RunGeometry {
-    static hipError_t run(int64_t batch, BwdGeometry* out)
+    static hipError_t run(int64_t batch, int d, BwdGeometry* out)
     {
         using bg = BwdGeo<M>;
-        // about 512 blocks, each owning a contiguous run of rows
+        // Blocks own contiguous runs of rows.  With the dx rows in LDS, one
+        // block fills a CU's LDS: aim for one block per CU (256), as many
+        // rows per block as the LDS holds; otherwise about 512 blocks.
         const int64_t units = (batch + bg::ROWS - 1) / bg::ROWS;
-        const int64_t target = 512;
+        const int64_t target = bg::XRES ? 256 : 512;
         int64_t passes = (units + target - 1) / target;
+        if (bg::XRES) {
+            const int64_t row_bytes = (int64_t)bg::ROWS * ((d + 3) & ~3) * 4;
+            int64_t pmax = (kLdsBytes - bg::STATIC_LDS - bg::PARAM_LDS) / row_bytes;
+            pmax = pmax < 1 ? 1 : pmax;
+            passes = passes > pmax ? pmax : passes;
+        }
         if (passes < 1)
             passes = 1;
         out->passes = (int)passes;
@@ -719,10 +1022,10 @@ hipError_t launch_forward(int M, bool vec, bool trig, const float* x, int64_t ba
     return dispatch_m<RunForward>(M, vec, trig, x, batch, d, E, B, goff, Gs, Sx, cs, out, s);
 }
 
-BwdGeometry backward_geometry(int M, int64_t batch)
+BwdGeometry backward_geometry(int M, int64_t batch, int d)
 {
     BwdGeometry g{1, 1, 64};
-    (void)dispatch_m<RunGeometry>(M, batch, &g);
+    (void)dispatch_m<RunGeometry>(M, batch, d, &g);
     return g;
 }
 

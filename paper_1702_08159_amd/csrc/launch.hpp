@@ -39,7 +39,7 @@ struct BwdGeometry {
     int passes;
     int block_threads;
 };
-BwdGeometry backward_geometry(int M, int64_t batch);
+BwdGeometry backward_geometry(int M, int64_t batch, int d);
 
 // Backward: dx (nullable) and, when partial != null, per-block partial sums
 // of dS, dG, dB (blocks x E x 3 x n) reduced afterwards by launch_reduce.

@@ -249,7 +249,7 @@ mck_status run_backward(const float* x, const float* dphi, int64_t batch, int64_
     const int64_t rows_per = lim / row_bytes < 1 ? 1 : lim / row_bytes;
     int64_t total_blocks = 0;
     for (int64_t r0 = 0; r0 < batch; r0 += rows_per)
-        total_blocks += mck::backward_geometry(M, batch - r0 < rows_per ? batch - r0 : rows_per).blocks;
+        total_blocks += mck::backward_geometry(M, batch - r0 < rows_per ? batch - r0 : rows_per, (int)d).blocks;
     float* partial = nullptr;
     hipError_t err;
     if (want_params) {
@@ -263,7 +263,7 @@ mck_status run_backward(const float* x, const float* dphi, int64_t batch, int64_
     int64_t done_blocks = 0;
     for (int64_t r0 = 0; r0 < batch && err == hipSuccess; r0 += rows_per) {
         const int64_t rows = batch - r0 < rows_per ? batch - r0 : rows_per;
-        const mck::BwdGeometry geo = mck::backward_geometry(M, rows);
+        const mck::BwdGeometry geo = mck::backward_geometry(M, rows, (int)d);
         float* part = partial ? partial + (size_t)done_blocks * E * 3 * n : nullptr;
         err = mck::launch_backward(M, vec, x + r0 * d, dphi + r0 * 2 * n * E, rows, (int)d, E, B, goff, Gk, S32, Sh,
                                    cs, dx ? dx + r0 * d : nullptr, part, geo, s);
