@@ -34,6 +34,7 @@ FWD_BYTES_PER_VECTOR = 4 * D + 8 * N * E          # read x, write phi
 BWD_BYTES_PER_VECTOR = 8 * D + 8 * N * E          # read x and dphi, write dx
 HBM_PEAK_GBS = 8000.0
 GRAPH_STEPS = 10
+TRAIN_BATCH, TRAIN_CLASSES = 1024, 10
 METRIC = "Fastfood vectors/s + %HBM peak at n=1024 E=16, fwd and fwd+bwd vs oracle error"
 
 # HBM bytes per forward launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of
@@ -67,9 +68,10 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--bwd-steps", type=int, default=40)
+    ap.add_argument("--train-steps", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", choices=["fwd", "bwd", "all"], default="all",
+    ap.add_argument("--only", choices=["fwd", "bwd", "train", "all"], default="all",
                     help="time only one pass (for profiling); the JSON line then lacks the other")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also time a plain 1 GiB device copy and fill (counter calibration)")
@@ -167,6 +169,33 @@ def main():
         log("backward %.4f ms/step over %d steps" % (bwd_ms, args.bwd_steps))
         del dphi
 
+    train_ms = float("nan")
+    if args.only in ("train", "all") and args.train_steps > 0:
+        # softmax(W phi + b) training step with learnable B, G, S: batch 1024,
+        # 10 classes, sigma = 1, SGD with the paper's learning rate 0.001
+        tb, C = TRAIN_BATCH, TRAIN_CLASSES
+        p = mk.params(seed, N, E, 1.0, device=dev)
+        B, perm, G, S = (t.contiguous() for t in (p["B"], p["perm"], p["G"], p["S"]))
+        xt = x[:tb].contiguous()
+        rng = np.random.default_rng(3)
+        W = torch.from_numpy((rng.standard_normal((C, 2 * N * E)) * 0.01).astype(np.float32)).to(dev)
+        bias = torch.zeros(C, dtype=torch.float32, device=dev)
+        labels = torch.from_numpy(rng.integers(0, C, tb).astype(np.int32)).to(dev)
+
+        def step():
+            mk.train_step(xt, labels, W, bias, B, perm, G, S, lr=0.001)
+
+        for _ in range(3):
+            step()
+        torch.cuda.synchronize()
+        t0.record(stream)
+        for _ in range(args.train_steps):
+            step()
+        t1.record(stream)
+        torch.cuda.synchronize()
+        train_ms = t0.elapsed_time(t1) / args.train_steps
+        log("train step %.4f ms over %d steps" % (train_ms, args.train_steps))
+
     fwd_vps = BATCH / (fwd_ms * 1e-3)
     fb_ms = fwd_ms + bwd_ms
     fb_vps = BATCH / (fb_ms * 1e-3)
@@ -227,6 +256,10 @@ def main():
         "fwd_bwd_hbm_frac": fb_gbs / HBM_PEAK_GBS,
         "bwd_ms_per_step": bwd_ms,
         "bwd_steps": args.bwd_steps,
+        "train_step_ms": train_ms,
+        "train_vectors_per_s": TRAIN_BATCH / (train_ms * 1e-3),
+        "train_config": {"batch": TRAIN_BATCH, "classes": TRAIN_CLASSES, "d": D, "n": N, "E": E, "sigma": 1.0,
+                         "lr": 0.001, "learnable": "W, b, B, G, S"},
         "max_row_rel_err_vs_oracle": err,
         "roofline": {"bound": "hbm", "achieved": fwd_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": fwd_gbs / HBM_PEAK_GBS, "traffic": traffic},

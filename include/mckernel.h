@@ -140,6 +140,27 @@ mck_status mck_fastfood_backward_p(const float* x, const float* dphi, int64_t ba
 mck_status mck_gen_boxmuller(const uint32_t* a, const uint32_t* b, int64_t count, float* g0, float* g1,
                              mck_stream stream);
 
+/*
+ * Classifier head of the training step (section "Empirical Analysis and
+ * Experiments": softmax(W phi + b) on the McKernel features, trained with
+ * cross-entropy).  logits: batch x C (row-major), labels: batch int32 in
+ * [0, C).  Writes dlogits (batch x C) = (softmax(logits) - onehot(labels)) /
+ * batch, the gradient of the mean loss; *loss = the mean cross-entropy and
+ * db (C floats) = the column sums of dlogits, both summed in a fixed order
+ * (loss and db may be NULL).  A label outside [0, C) makes that row's loss
+ * and gradient NaN.  C in [1, 1024].  Allocates batch floats of scratch on
+ * `stream` (stream-ordered).
+ */
+mck_status mck_softmax_xent(const float* logits, const int32_t* labels, int64_t batch, int64_t C, float* loss,
+                            float* dlogits, float* db, mck_stream stream);
+
+/*
+ * y += alpha x over `count` floats (the SGD update w <- w - gamma grad of
+ * section "Large-scale Machine Learning", with alpha = -gamma).  y and x
+ * must not overlap unless equal.
+ */
+mck_status mck_axpy(float* y, const float* x, int64_t count, float alpha, mck_stream stream);
+
 /* Frees every cached plan (waits for the device first). */
 void mck_shutdown(void);
 

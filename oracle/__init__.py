@@ -17,6 +17,9 @@ Functions (all FP64 unless the generator's definition fixes the precision):
   features(z, n, E)                    -- c [cos z, sin z]
   forward(x, E, seed, sigma)           -- phi in FP64 from the generated parameters
   backward(x, dphi, n, E, B, perm, G, S) -- dx, dB, dG, dS
+  softmax_xent(logits, labels)         -- mean cross-entropy and d/dlogits
+  train_step(x, labels, W, b, B, perm, G, S) -- loss and every gradient of the
+                                          softmax(W phi + b) classifier
 """
 from __future__ import annotations
 
@@ -232,3 +235,41 @@ def backward(x, dphi, n: int, E: int, B, perm, G, S):
                             _ptr(G), _ptr(S), _ptr(dx), _ptr(dB), _ptr(dG), _ptr(dS)) != 0:
         raise ValueError("orc_backward rejected its arguments")
     return dx, dB, dG, dS
+
+
+# ---------------------------------------------------------------- training step
+def softmax_xent(logits, labels):
+    """Mean cross-entropy of softmax(logits) against integer labels, and its
+    gradient with respect to the logits, FP64."""
+    lg = np.asarray(logits, np.float64)
+    y = np.asarray(labels, np.int64)
+    m = lg.max(axis=1, keepdims=True)
+    ex = np.exp(lg - m)
+    s = ex.sum(axis=1, keepdims=True)
+    logp = lg - m - np.log(s)
+    batch = lg.shape[0]
+    loss = -logp[np.arange(batch), y].mean()
+    dlog = ex / s
+    dlog[np.arange(batch), y] -= 1.0
+    return loss, dlog / batch
+
+
+def train_step(x, labels, W, b, B, perm, G, S):
+    """One softmax(W phi(x) + b) cross-entropy step with explicit diagonals
+    (section "Empirical Analysis and Experiments": the classifier on the
+    McKernel features; section "Large-scale Machine Learning": minimised by
+    SGD).  Returns the mean loss and the gradients with respect to W, b, x,
+    B, G, S, all FP64."""
+    x = np.atleast_2d(np.asarray(x, np.float64))
+    W = np.asarray(W, np.float64)
+    b = np.asarray(b, np.float64)
+    E, n = np.asarray(B).reshape(-1, np.asarray(B).shape[-1]).shape
+    z = project(x, n, E, B, perm, G, S)
+    phi = features(z, n, E)
+    logits = phi @ W.T + b
+    loss, dlog = softmax_xent(logits, labels)
+    dW = dlog.T @ phi
+    db = dlog.sum(axis=0)
+    dphi = dlog @ W
+    dx, dB, dG, dS = backward(x, dphi, n, E, B, perm, G, S)
+    return {"loss": loss, "dW": dW, "db": db, "dx": dx, "dB": dB, "dG": dG, "dS": dS, "logits": logits}

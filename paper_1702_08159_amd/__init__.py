@@ -224,5 +224,53 @@ def gen_boxmuller(a: torch.Tensor, b: torch.Tensor):
     return g0, g1
 
 
+def softmax_xent(logits: torch.Tensor, labels: torch.Tensor):
+    """(mean cross-entropy, dlogits, db) of softmax(logits) against int32 labels."""
+    _check(logits, "logits")
+    _check(labels, "labels", torch.int32)
+    batch, C = logits.shape
+    if labels.shape != (batch,):
+        raise ValueError("labels must have one entry per row")
+    loss = torch.empty((), dtype=torch.float32, device=logits.device)
+    dlogits = torch.empty_like(logits)
+    db = torch.empty((C,), dtype=torch.float32, device=logits.device)
+    with torch.cuda.device(logits.device):
+        _lib.call("mck_softmax_xent", _ptr(logits), _ptr(labels), batch, C, _ptr(loss), _ptr(dlogits), _ptr(db),
+                  _stream(logits))
+    return loss, dlogits, db
+
+
+def axpy_(y: torch.Tensor, x: torch.Tensor, alpha: float) -> torch.Tensor:
+    """y += alpha x in place (the SGD update with alpha = -learning rate)."""
+    _check(y, "y")
+    _check(x, "x")
+    if y.numel() != x.numel():
+        raise ValueError("y and x must have the same number of elements")
+    with torch.cuda.device(y.device):
+        _lib.call("mck_axpy", _ptr(y), _ptr(x), y.numel(), float(alpha), _stream(y))
+    return y
+
+
+def train_step(x, labels, W, b, B, perm, G, S, lr=None, need_dx=False):
+    """One step of the classifier softmax(W phi(x) + b) with cross-entropy on
+    the features of explicit diagonals B, G, S (perm fixed): the feature map
+    and its adjoint run in this library's kernels, the three dense products
+    (logits, dW, dphi) in the BLAS library.  Returns the loss and the
+    gradients with respect to W, b, B, G, S (and x if need_dx); with lr given,
+    applies the SGD update to W, b, B, G, S in place."""
+    for t, nm in ((W, "W"), (b, "b")):
+        _check(t, nm)
+    phi = forward_p(x, B, perm, G, S)
+    logits = torch.addmm(b, phi, W.t())
+    loss, dlogits, db = softmax_xent(logits, labels)
+    dW = torch.mm(dlogits.t(), phi)
+    dphi = torch.mm(dlogits, W)
+    dx, dB, dG, dS = backward_p(x, dphi, B, perm, G, S, need_dx=need_dx, need_params=True)
+    if lr is not None:
+        for prm, grd in ((W, dW), (b, db), (B, dB), (G, dG), (S, dS)):
+            axpy_(prm, grd, -float(lr))
+    return {"loss": loss, "dW": dW, "db": db, "dx": dx, "dB": dB, "dG": dG, "dS": dS, "logits": logits}
+
+
 def shutdown() -> None:
     _lib.lib().mck_shutdown()

@@ -26,6 +26,7 @@ COMMON = ["--offload-arch=" + ARCH, "-O3", "-fPIC", "-std=c++17",
           "-I" + os.path.join(ROOT, "include"), "-Wno-unused-command-line-argument"]
 SOURCES = {
     "kernels.hip": [],
+    "head.hip": [],
     "generator.hip": ["-ffp-contract=off"],
     "runtime.cpp": ["-x", "hip"],
 }

@@ -53,4 +53,14 @@ hipError_t launch_backward(int M, bool vec, const float* x, const float* dphi, i
 hipError_t launch_reduce(const float* partial, int64_t blocks, int64_t E, int64_t n, float* dS, float* dG,
                          float* dB, hipStream_t s);
 
+// Classifier head (head.hip): per-row softmax cross-entropy and its
+// gradient (dlogits = (softmax - onehot) / batch), then the mean loss and
+// db = column sums of dlogits in a fixed order.  row_loss is batch floats of
+// scratch.  loss and db may be null.
+hipError_t launch_softmax_xent(const float* logits, const int32_t* labels, int64_t batch, int C, float* row_loss,
+                               float* dlogits, float* loss, float* db, hipStream_t s);
+
+// y += alpha x over count floats.
+hipError_t launch_axpy(float* y, const float* x, int64_t count, float alpha, hipStream_t s);
+
 }  // namespace mck

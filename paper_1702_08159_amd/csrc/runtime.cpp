@@ -497,6 +497,43 @@ mck_status mck_gen_boxmuller(const uint32_t* a, const uint32_t* b, int64_t count
     return err == hipSuccess ? MCK_OK : hip_fail(err, "mck_gen_boxmuller");
 }
 
+mck_status mck_softmax_xent(const float* logits, const int32_t* labels, int64_t batch, int64_t C, float* loss,
+                            float* dlogits, float* db, mck_stream stream)
+{
+    if (batch < 0)
+        return fail(MCK_ERR_INVALID_ARG, "batch must be >= 0");
+    if (C < 1 || C > 1024)
+        return fail(MCK_ERR_INVALID_ARG, "C must be in [1, 1024]");
+    if (batch == 0)
+        return MCK_OK;
+    if (!logits || !labels || !dlogits)
+        return fail(MCK_ERR_INVALID_ARG, "logits, labels or dlogits is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    float* row_loss = nullptr;
+    hipError_t err = hipMallocAsync(reinterpret_cast<void**>(&row_loss), (size_t)batch * sizeof(float), s);
+    if (err != hipSuccess)
+        return fail(MCK_ERR_NO_MEMORY, std::string("softmax scratch: ") + hipGetErrorString(err));
+    err = mck::launch_softmax_xent(logits, labels, batch, (int)C, row_loss, dlogits, loss, db, s);
+    (void)hipFreeAsync(row_loss, s);
+    if (err != hipSuccess)
+        return hip_fail(err, "softmax cross-entropy launch");
+    return MCK_OK;
+}
+
+mck_status mck_axpy(float* y, const float* x, int64_t count, float alpha, mck_stream stream)
+{
+    if (count < 0)
+        return fail(MCK_ERR_INVALID_ARG, "count must be >= 0");
+    if (count == 0)
+        return MCK_OK;
+    if (!y || !x)
+        return fail(MCK_ERR_INVALID_ARG, "y or x is NULL");
+    const hipError_t err = mck::launch_axpy(y, x, count, alpha, static_cast<hipStream_t>(stream));
+    if (err != hipSuccess)
+        return hip_fail(err, "axpy launch");
+    return MCK_OK;
+}
+
 void mck_shutdown(void)
 {
     std::lock_guard<std::mutex> lock(g_mutex);

@@ -1,0 +1,113 @@
+"""GPU parity of the training step (softmax(W phi + b) with cross-entropy on
+the McKernel features, learnable B, G, S) against the FP64 oracle.
+
+Tolerance: 1e-5 normwise per tensor for the loss, logits and every gradient
+(FP32 products over up to 1024 rows and 32768 features stay near 1e-6)."""
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def mk():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1702_08159_amd as mk
+
+    mk._lib.lib()
+    return mk
+
+
+def rel(a, ref):
+    a = np.asarray(a, np.float64)
+    ref = np.asarray(ref, np.float64)
+    return float(np.linalg.norm(a - ref) / max(np.linalg.norm(ref), 1e-300))
+
+
+def _problem(orc, batch, E, C=10, sigma=1.0, seed=3):
+    x = workloads.mnist_sparse(batch)
+    n = orc.padded_dim(x.shape[1])
+    p = orc.params(workloads.FASTFOOD_SEED, n, E, sigma)
+    rng = np.random.default_rng(seed)
+    W = (rng.standard_normal((C, 2 * n * E)) * 0.3).astype(np.float32)
+    b = (rng.standard_normal(C) * 0.1).astype(np.float32)
+    y = rng.integers(0, C, batch).astype(np.int32)
+    return x, y, W, b, p
+
+
+def test_softmax_xent_matches_oracle(mk, orc):
+    import torch
+
+    rng = np.random.default_rng(0)
+    for batch, C in ((1, 1), (5, 3), (300, 10), (1024, 10), (2000, 37)):
+        lg = (rng.standard_normal((batch, C)) * 4).astype(np.float32)
+        y = rng.integers(0, C, batch).astype(np.int32)
+        loss, dl, db = mk.softmax_xent(torch.from_numpy(lg).cuda(), torch.from_numpy(y).cuda())
+        rl, rdl = orc.softmax_xent(lg.astype(np.float64), y)
+        assert abs(float(loss) - rl) <= 1e-6 * max(1.0, abs(rl))
+        assert rel(dl.cpu().numpy(), rdl) <= 1e-6
+        assert rel(db.cpu().numpy(), rdl.sum(axis=0)) <= 1e-5 or np.abs(db.cpu().numpy()).max() < 1e-6
+
+
+def test_softmax_xent_bad_label_is_nan(mk):
+    import torch
+
+    lg = torch.zeros((3, 4), device="cuda")
+    y = torch.tensor([0, 4, 1], dtype=torch.int32, device="cuda")
+    loss, dl, _ = mk.softmax_xent(lg, y)
+    assert np.isnan(float(loss))
+    d = dl.cpu().numpy()
+    assert np.isnan(d[1]).all() and np.isfinite(d[[0, 2]]).all()
+
+
+def test_axpy(mk):
+    import torch
+
+    rng = np.random.default_rng(1)
+    for count in (1, 255, 256, 257, 100000):
+        y = rng.standard_normal(count).astype(np.float32)
+        x = rng.standard_normal(count).astype(np.float32)
+        yt = torch.from_numpy(y).cuda()
+        mk.axpy_(yt, torch.from_numpy(x).cuda(), -0.125)
+        ref = y.astype(np.float64) - 0.125 * x.astype(np.float64)
+        np.testing.assert_allclose(yt.cpu().numpy(), ref, rtol=2e-7, atol=1e-7)
+
+
+@pytest.mark.parametrize("batch,E", [(64, 2), (1024, 16)])
+def test_train_step_matches_oracle(mk, orc, batch, E):
+    import torch
+
+    x, y, W, b, p = _problem(orc, batch, E)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    B, G, S = dev(p["B"]), dev(p["G"]), dev(p["S32"])
+    perm = dev(p["perm"])
+    out = mk.train_step(dev(x), dev(y), dev(W), dev(b), B, perm, G, S, need_dx=True)
+    ref = orc.train_step(x.astype(np.float64), y, W.astype(np.float64), b.astype(np.float64),
+                         p["B"].astype(np.float64), p["perm"], p["G"].astype(np.float64),
+                         p["S32"].astype(np.float64))
+    assert abs(float(out["loss"]) - ref["loss"]) <= TOL * abs(ref["loss"])
+    for k in ("logits", "dW", "db", "dx", "dB", "dG", "dS"):
+        assert rel(out[k].cpu().numpy(), ref[k]) <= TOL, k
+
+
+def test_sgd_steps_reduce_loss(mk, orc):
+    import torch
+
+    x, y, W, b, p = _problem(orc, 1024, 16, seed=9)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    xs, ys, Wt, bt = dev(x), dev(y), dev(W), dev(b)
+    B, G, S, perm = dev(p["B"]), dev(p["G"]), dev(p["S32"]), dev(p["perm"])
+    losses = [float(mk.train_step(xs, ys, Wt, bt, B, perm, G, S, lr=0.5)["loss"]) for _ in range(5)]
+    assert all(np.isfinite(losses))
+    assert losses[-1] < losses[0]
+    # the update is exactly w - lr * grad: check W after one more step
+    W0 = Wt.clone()
+    out = mk.train_step(xs, ys, Wt, bt, B, perm, G, S, lr=0.5)
+    np.testing.assert_allclose(Wt.cpu().numpy(), (W0 - 0.5 * out["dW"]).cpu().numpy(), rtol=0, atol=1e-6)
