@@ -69,6 +69,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--bwd-steps", type=int, default=40)
     ap.add_argument("--train-steps", type=int, default=20)
+    ap.add_argument("--lowp-steps", type=int, default=100)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["fwd", "bwd", "train", "all"], default="all",
@@ -149,6 +150,34 @@ def main():
         torch.cuda.synchronize()
         fwd_ms = t0.elapsed_time(t1) / args.steps
         log("forward %.4f ms/step over %d steps" % (fwd_ms, args.steps))
+    lowp = {}
+    if args.only in ("fwd", "all") and args.lowp_steps > 0:
+        # the same forward with phi stored in 16 bits (FP32 arithmetic)
+        for name, dt in (("bf16", torch.bfloat16), ("f16", torch.float16)):
+            phi16 = torch.empty((BATCH, 2 * N * E), dtype=dt, device=dev)
+            mk.forward(x, E, seed, SIGMA, out=phi16)
+            g16 = torch.cuda.CUDAGraph()
+            s16 = torch.cuda.Stream(dev)
+            s16.wait_stream(stream)
+            with torch.cuda.stream(s16):
+                mk.forward(x, E, seed, SIGMA, out=phi16)
+            stream.wait_stream(s16)
+            with torch.cuda.graph(g16):
+                for _ in range(GRAPH_STEPS):
+                    mk.forward(x, E, seed, SIGMA, out=phi16)
+            torch.cuda.synchronize()
+            for _ in range(max(1, args.warmup // GRAPH_STEPS)):
+                g16.replay()
+            torch.cuda.synchronize()
+            t0.record(stream)
+            for _ in range(max(1, args.lowp_steps // GRAPH_STEPS)):
+                g16.replay()
+            t1.record(stream)
+            torch.cuda.synchronize()
+            ms = t0.elapsed_time(t1) / (max(1, args.lowp_steps // GRAPH_STEPS) * GRAPH_STEPS)
+            lowp[name] = {"ms_per_step": ms, "vectors_per_s": BATCH / (ms * 1e-3),
+                          "bytes_per_vector": 4 * D + 4 * N * E, "phi": phi16}
+            log("forward, phi in %s: %.4f ms/step" % (name, ms))
     if args.only in ("bwd", "all"):
         dphi = torch.from_numpy(workloads.grad_features(BATCH, 2 * N * E)).to(dev)
         grads = (torch.empty_like(x),) + tuple(torch.empty((E, N), dtype=torch.float32, device=dev)
@@ -234,6 +263,15 @@ def main():
         cpu = {"value": rows / cpu_s, "unit": "vectors/s", "cores": 1, "kind": "oracle",
                "sample": "first %d of the %d rows, forward, FP64 C oracle, one thread" % (rows, BATCH)}
         err = worst
+        # 16-bit storage: error of the stored phi against the oracle, first 256 rows
+        ref, _, _ = oracle.forward(xs[:256], E, seed, SIGMA, p=p)
+        for name, rec in lowp.items():
+            ph = rec["phi"][:256].float().cpu().numpy().astype(np.float64)
+            rec["max_row_rel_err_vs_oracle"] = float(
+                (np.linalg.norm(ph - ref, axis=1) / np.linalg.norm(ref, axis=1)).max())
+    for rec in lowp.values():
+        rec.pop("phi", None)
+        rec["speedup_vs_f32"] = fwd_ms / rec["ms_per_step"] if math.isfinite(fwd_ms) else None
 
     line = {
         "metric": METRIC,
@@ -256,6 +294,7 @@ def main():
         "fwd_bwd_hbm_frac": fb_gbs / HBM_PEAK_GBS,
         "bwd_ms_per_step": bwd_ms,
         "bwd_steps": args.bwd_steps,
+        "fwd_16bit_phi": lowp,
         "train_step_ms": train_ms,
         "train_vectors_per_s": TRAIN_BATCH / (train_ms * 1e-3),
         "train_config": {"batch": TRAIN_BATCH, "classes": TRAIN_CLASSES, "d": D, "n": N, "E": E, "sigma": 1.0,

@@ -62,6 +62,13 @@ typedef enum mck_calibration {
 
 typedef void* mck_stream; /* hipStream_t */
 
+/* Storage type of x or phi in mck_fastfood_forward_t. */
+typedef enum mck_dtype {
+    MCK_DTYPE_F32 = 0,  /* IEEE binary32 */
+    MCK_DTYPE_BF16 = 1, /* bfloat16 (the upper half of a binary32) */
+    MCK_DTYPE_F16 = 2   /* IEEE binary16 */
+} mck_dtype;
+
 /* Largest n a single call accepts (single-pass transform held in LDS). */
 #define MCK_MAX_N 32768
 
@@ -100,6 +107,21 @@ mck_status mck_fastfood_params(uint32_t seed, int64_t n, int64_t E, double sigma
  */
 mck_status mck_fastfood_forward(const float* x, int64_t batch, int64_t d, int64_t E, uint32_t seed,
                                 double sigma, mck_calibration calib, float* phi, mck_stream stream);
+
+/*
+ * The feature map with 16-bit storage: x (batch x d) and phi (batch x 2nE,
+ * layout as in mck_fastfood_forward) of the given storage types, arithmetic
+ * in FP32 throughout; 16-bit x values widen exactly and phi is rounded to
+ * nearest even.  Supported (x_type, phi_type) pairs: (F32, F32), (F32, BF16),
+ * (F32, F16), (BF16, BF16), (F16, F16); others return MCK_ERR_UNSUPPORTED.
+ * |phi| <= 1/sqrt(nE), so half precision needs no scaling: its relative
+ * rounding error is 2^-11 down to 6.1e-5 and below that the absolute error
+ * is at most 3e-8.  Same argument rules and plan cache as
+ * mck_fastfood_forward.
+ */
+mck_status mck_fastfood_forward_t(const void* x, mck_dtype x_type, int64_t batch, int64_t d, int64_t E,
+                                  uint32_t seed, double sigma, mck_calibration calib, void* phi, mck_dtype phi_type,
+                                  mck_stream stream);
 
 /* z = Z xhat without the trigonometric map: batch x (n E), expansion-major. */
 mck_status mck_fastfood_project(const float* x, int64_t batch, int64_t d, int64_t E, uint32_t seed,

@@ -85,8 +85,17 @@ def _rows(x: torch.Tensor):
     return x.shape[0], x.shape[1]
 
 
-def forward(x: torch.Tensor, E: int, seed: int = PAPER_SEED, sigma: float = 1.0, out=None) -> torch.Tensor:
-    """phi(x): batch x 2nE features [cos blocks, sin blocks]."""
+_DTYPES = {torch.float32: 0, torch.bfloat16: 1, torch.float16: 2}
+
+
+def forward(x: torch.Tensor, E: int, seed: int = PAPER_SEED, sigma: float = 1.0, out=None,
+            out_dtype=None) -> torch.Tensor:
+    """phi(x): batch x 2nE features [cos blocks, sin blocks].  x may be
+    float32, bfloat16 or float16; phi is float32 unless out_dtype (or out)
+    says bfloat16 / float16 (16-bit storage, FP32 arithmetic)."""
+    if x.dtype != torch.float32 or (out_dtype not in (None, torch.float32)) or (
+            out is not None and out.dtype != torch.float32):
+        return _forward_t(x, E, seed, sigma, out, out_dtype)
     _check(x, "x")
     batch, d = _rows(x)
     n = padded_dim(d)
@@ -96,6 +105,23 @@ def forward(x: torch.Tensor, E: int, seed: int = PAPER_SEED, sigma: float = 1.0,
     with torch.cuda.device(x.device):
         _lib.call("mck_fastfood_forward", _ptr(x), batch, d, E, seed & 0xFFFFFFFF, float(sigma), MCK_CALIB_RBF,
                   _ptr(out), _stream(x))
+    return out
+
+
+def _forward_t(x, E, seed, sigma, out, out_dtype):
+    if x.dtype not in _DTYPES:
+        raise TypeError("x must be float32, bfloat16 or float16")
+    _check(x, "x", x.dtype)
+    batch, d = _rows(x)
+    n = padded_dim(d)
+    if out is None:
+        out = torch.empty((batch, 2 * n * E), dtype=out_dtype or x.dtype, device=x.device)
+    if out.dtype not in _DTYPES:
+        raise TypeError("phi must be float32, bfloat16 or float16")
+    _check(out, "out", out.dtype)
+    with torch.cuda.device(x.device):
+        _lib.call("mck_fastfood_forward_t", _ptr(x), _DTYPES[x.dtype], batch, d, E, seed & 0xFFFFFFFF,
+                  float(sigma), MCK_CALIB_RBF, _ptr(out), _DTYPES[out.dtype], _stream(x))
     return out
 
 

@@ -31,6 +31,7 @@ SIGNATURES = {
     "mck_fastfood_params": (_int, [_u32, _i64, _i64, _f64, _int, _vp, _vp, _vp, _vp, _vp, _vp]),
     "mck_fastfood_forward": (_int, [_vp, _i64, _i64, _i64, _u32, _f64, _int, _vp, _vp]),
     "mck_fastfood_project": (_int, [_vp, _i64, _i64, _i64, _u32, _f64, _int, _vp, _vp]),
+    "mck_fastfood_forward_t": (_int, [_vp, _int, _i64, _i64, _i64, _u32, _f64, _int, _vp, _int, _vp]),
     "mck_fastfood_backward": (_int, [_vp, _vp, _i64, _i64, _i64, _u32, _f64, _int, _vp, _vp, _vp, _vp, _vp]),
     "mck_fastfood_forward_p": (_int, [_vp, _i64, _i64, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
     "mck_fastfood_backward_p": (_int, [_vp, _vp, _i64, _i64, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp,

@@ -293,6 +293,103 @@ __device__ __forceinline__ void bload_lane(LaneArr<TT, M, P>& v, rsrc_t r, uint3
     }
 }
 
+// ------------------------------------------------------------------ storage types
+// x and phi may be stored as FP32, bfloat16 or IEEE half; arithmetic stays
+// FP32.  16-bit values widen exactly; FP32 results narrow with
+// round-to-nearest-even (v_cvt_pk_bf16_f32 / v_cvt_pk_f16_f32 on gfx950).
+enum : int { kF32 = 0, kBF16 = 1, kF16 = 2 };
+
+template <int T>
+constexpr uint32_t elem_bytes() { return T == kF32 ? 4u : 2u; }
+
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2_t __attribute__((ext_vector_type(2)));
+typedef unsigned u32x2_t __attribute__((ext_vector_type(2)));
+
+template <int T>
+__device__ __forceinline__ uint32_t pack2(float a, float b)
+{
+    const f32x2_t v = {a, b};
+    if constexpr (T == kBF16)
+        return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
+    else
+        return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, f16x2_t));
+}
+
+template <int T>
+__device__ __forceinline__ void unpack2(uint32_t w, float& a, float& b)
+{
+    f32x2_t v;
+    if constexpr (T == kBF16)
+        v = __builtin_convertvector(__builtin_bit_cast(bf16x2_t, w), f32x2_t);
+    else
+        v = __builtin_convertvector(__builtin_bit_cast(f16x2_t, w), f32x2_t);
+    a = v.x;
+    b = v.y;
+}
+
+template <int T>
+__device__ __forceinline__ float widen1(uint32_t h)
+{
+    float a, b;
+    unpack2<T>(h & 0xffffu, a, b);
+    return a;
+}
+
+// Row of length d (elements of type T) at byte offset rowoff, zero-padded to
+// n, into the coalesced layout; invalid rows read as zero.
+template <int M, int P, bool VEC, int T, int AUX = 0>
+__device__ __forceinline__ void bload_row_t(LaneArr<float, M, P>& v, rsrc_t r, uint32_t rowoff, int d, uint32_t t,
+                                            bool valid)
+{
+    if constexpr (T == kF32) {
+        bload_row<M, P, VEC, AUX>(v, r, rowoff, d, t, valid);
+    } else {
+        constexpr int EPL = Geo<M, P>::EPL;
+        const uint32_t tb = tpart<M, P, 0>(t);
+        if constexpr (VEC) {
+#pragma unroll
+            for (int j = 0; j < EPL / 4; ++j) {
+                const uint32_t i0 = tb | rpart(M, P, 0, 4 * j);
+                const uint32_t off = (valid && (int)i0 < d) ? rowoff + 2u * i0 : kOutOfRange;
+                const u32x2_t q = __builtin_bit_cast(u32x2_t, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, AUX));
+                unpack2<T>(q.x, v[4 * j], v[4 * j + 1]);
+                unpack2<T>(q.y, v[4 * j + 2], v[4 * j + 3]);
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < EPL; ++k) {
+                const uint32_t i = tb | rpart(M, P, 0, k);
+                const uint32_t off = (valid && (int)i < d) ? rowoff + 2u * i : kOutOfRange;
+                v[k] = widen1<T>((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, AUX));
+            }
+        }
+    }
+}
+
+// Four consecutive elements (streaming store): 16 bytes in FP32, 8 bytes
+// (two packed pairs) in 16-bit types.  The whole offset is in the VGPR.
+template <int T>
+__device__ __forceinline__ void bstore_quad(rsrc_t r, uint32_t voff, float a, float b, float c, float d)
+{
+    if constexpr (T == kF32) {
+        bstore4_nt(r, voff, a, b, c, d);
+    } else {
+        const u32x2_t q = {pack2<T>(a, b), pack2<T>(c, d)};
+        __builtin_amdgcn_raw_buffer_store_b64(q, r, (int)voff, 0, 2);
+    }
+}
+
+template <int T>
+__device__ __forceinline__ void bstore_elem(rsrc_t r, uint32_t voff, float a)
+{
+    if constexpr (T == kF32)
+        bstore1(r, voff, 0, a);
+    else
+        __builtin_amdgcn_raw_buffer_store_b16((unsigned short)(pack2<T>(a, 0.f) & 0xffffu), r, (int)voff, 0, 0);
+}
+
 // ------------------------------------------------------------------ feature map
 // c cos(2 pi t) and c sin(2 pi t) for t in revolutions.  The argument is
 // reduced to [0, 1) exactly (fract), then the hardware sine and cosine

@@ -33,6 +33,12 @@ hipError_t launch_forward(int M, bool vec, bool trig, const float* x, int64_t ba
                           const float* B, const uint32_t* goff, const float* Gs, const float* Sx,
                           float cs, float* out, hipStream_t s);
 
+// Forward with 16-bit storage (forward16.hip): xt, yt = 0 (FP32), 1 (bf16),
+// 2 (half); supported pairs (0,1), (0,2), (1,1), (2,2); the feature map only.
+hipError_t launch_forward_t(int M, bool vec, int xt, int yt, const void* x, int64_t batch, int d, int64_t E,
+                            const float* B, const uint32_t* goff, const float* Gs, const float* Sx, float cs,
+                            void* out, hipStream_t s);
+
 // Backward geometry: blocks, passes per block.
 struct BwdGeometry {
     int64_t blocks;

@@ -382,6 +382,46 @@ mck_status mck_fastfood_forward(const float* x, int64_t batch, int64_t d, int64_
     return forward_common(x, batch, d, E, seed, sigma, calib, phi, true, stream);
 }
 
+mck_status mck_fastfood_forward_t(const void* x, mck_dtype x_type, int64_t batch, int64_t d, int64_t E,
+                                  uint32_t seed, double sigma, mck_calibration calib, void* phi, mck_dtype phi_type,
+                                  mck_stream stream)
+{
+    const int xt = (int)x_type, yt = (int)phi_type;
+    if (xt < 0 || xt > 2 || yt < 0 || yt > 2)
+        return fail(MCK_ERR_INVALID_ARG, "unknown storage type");
+    if (xt == 0 && yt == 0)
+        return forward_common(static_cast<const float*>(x), batch, d, E, seed, sigma, calib,
+                              static_cast<float*>(phi), true, stream);
+    const bool supported = (xt == 0 && (yt == 1 || yt == 2)) || (xt == yt);
+    if (!supported)
+        return fail(MCK_ERR_UNSUPPORTED, "storage pair not supported (use F32 x, or the same 16-bit type)");
+    int64_t n = 0;
+    mck_status st = check_common(batch, d, E, &n);
+    if (st != MCK_OK)
+        return st;
+    st = check_sigma(sigma);
+    if (st != MCK_OK)
+        return st;
+    if (calib != MCK_CALIB_RBF)
+        return fail(MCK_ERR_UNSUPPORTED, "only MCK_CALIB_RBF is implemented");
+    if (batch > 0 && (x == nullptr || phi == nullptr))
+        return fail(MCK_ERR_INVALID_ARG, "x or phi is NULL");
+    if (batch == 0)
+        return MCK_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Plan* p = nullptr;
+    st = get_plan(seed, n, E, sigma, calib, s, &p);
+    if (st != MCK_OK)
+        return st;
+    // vector path: 4 elements per access, so 4-element alignment of both arrays
+    const uintptr_t xa = 4u * (xt == 0 ? 4u : 2u), ya = 4u * (yt == 0 ? 4u : 2u);
+    const bool vec = (reinterpret_cast<uintptr_t>(x) % xa == 0) && (reinterpret_cast<uintptr_t>(phi) % ya == 0) &&
+                     d % 4 == 0 && n >= 4;
+    const hipError_t err = mck::launch_forward_t(log2i(n), vec, xt, yt, x, batch, (int)d, E, p->B, p->goffF, p->GsF,
+                                                 p->Sh, feature_scale(n, E), phi, s);
+    return err == hipSuccess ? MCK_OK : hip_fail(err, "forward launch");
+}
+
 mck_status mck_fastfood_project(const float* x, int64_t batch, int64_t d, int64_t E, uint32_t seed, double sigma,
                                 mck_calibration calib, float* z, mck_stream stream)
 {
