@@ -11,7 +11,8 @@ Functions (all FP64 unless the generator's definition fixes the precision):
   ln32, sincos2pi32       -- FP32 elementary functions of the G generator
   ln64, cos2pi64          -- FP64 elementary functions of the S generator
   boxmuller32, normal64, chi
-  params(seed, n, E, sigma)           -- B, perm, G, S64, S32
+  params(seed, n, E, sigma, matern_t) -- B, perm, G, S64, S32 (RBF, or RBF-Matern)
+  ball_sample, matern                  -- the RBF-Matern calibration draws
   fwht(v)                              -- H v by the divide-and-conquer recursion
   project(x, n, E, B, perm, G, S)      -- z = S H G Pi H B xhat per expansion
   features(z, n, E)                    -- c [cos z, sin z]
@@ -79,6 +80,12 @@ def _load():
     lib.orc_padded_dim.argtypes = [i64]
     lib.orc_params.restype = ctypes.c_int
     lib.orc_params.argtypes = [u32, i64, i64, f64, vp, vp, vp, vp, vp, vp, vp]
+    lib.orc_params_c.restype = ctypes.c_int
+    lib.orc_params_c.argtypes = [u32, i64, i64, f64, i64, vp, vp, vp, vp, vp, vp, vp]
+    lib.orc_ball_sample.restype = None
+    lib.orc_ball_sample.argtypes = [u32, i64, u32, i64, vp]
+    lib.orc_matern.restype = f64
+    lib.orc_matern.argtypes = [u32, i64, i64, i64, i64]
     lib.orc_fwht.restype = ctypes.c_int
     lib.orc_fwht.argtypes = [vp, i64, i64]
     lib.orc_project.restype = ctypes.c_int
@@ -156,9 +163,22 @@ def padded_dim(d: int) -> int:
 
 
 # ---------------------------------------------------------------- parameters
-def params(seed: int, n: int, E: int, sigma: float, with_aux: bool = False):
+def ball_sample(seed: int, e: int, w: int, n: int) -> np.ndarray:
+    """One sample uniform in the unit n-ball (the RBF-Matern building block)."""
+    z = np.empty(n, np.float64)
+    _load().orc_ball_sample(seed & 0xFFFFFFFF, e, w & 0xFFFFFFFF, n, _ptr(z))
+    return z
+
+
+def matern(seed: int, e: int, j: int, n: int, t: int) -> float:
+    """RBF-Matern radius: the norm of the sum of t unit-ball samples."""
+    return _load().orc_matern(seed & 0xFFFFFFFF, e, j, n, t)
+
+
+def params(seed: int, n: int, E: int, sigma: float, with_aux: bool = False, matern_t: int = 0):
     """B, perm, G (E x n; float32, int32, float32), S64 (float64) and S32
-    (float32).  With ``with_aux`` also the chi radii s_j and ||G_e||^2."""
+    (float32).  With ``with_aux`` also the calibration radii s_j (chi(n), or
+    the RBF-Matern radii when matern_t > 0) and ||G_e||^2."""
     B = np.empty((E, n), np.float32)
     P = np.empty((E, n), np.int32)
     G = np.empty((E, n), np.float32)
@@ -166,8 +186,8 @@ def params(seed: int, n: int, E: int, sigma: float, with_aux: bool = False):
     S32 = np.empty((E, n), np.float32)
     chi_ = np.empty((E, n), np.float64) if with_aux else None
     nrm = np.empty((E,), np.float64) if with_aux else None
-    rc = _load().orc_params(seed & 0xFFFFFFFF, n, E, float(sigma), _ptr(B), _ptr(P),
-                            _ptr(G), _ptr(S64), _ptr(S32), _ptr(chi_), _ptr(nrm))
+    rc = _load().orc_params_c(seed & 0xFFFFFFFF, n, E, float(sigma), int(matern_t), _ptr(B), _ptr(P),
+                              _ptr(G), _ptr(S64), _ptr(S32), _ptr(chi_), _ptr(nrm))
     if rc != 0:
         raise ValueError("orc_params rejected (n=%d, E=%d, sigma=%r)" % (n, E, sigma))
     out = {"B": B, "perm": P, "G": G, "S64": S64, "S32": S32}
@@ -209,13 +229,13 @@ def features(z, n: int, E: int) -> np.ndarray:
     return phi
 
 
-def forward(x, E: int, seed: int, sigma: float, p=None):
+def forward(x, E: int, seed: int, sigma: float, p=None, matern_t: int = 0):
     """phi (batch x 2nE, FP64) with the generated parameters (FP32 G promoted,
     FP64 S).  Returns (phi, z, params)."""
     x = np.atleast_2d(x)
     n = padded_dim(x.shape[1])
     if p is None:
-        p = params(seed, n, E, sigma)
+        p = params(seed, n, E, sigma, matern_t=matern_t)
     z = project(x, n, E, p["B"], p["perm"], p["G"], p["S64"])
     return features(z, n, E), z, p
 

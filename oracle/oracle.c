@@ -26,6 +26,9 @@
  * Pins (tests/): FWHT vs scipy's Sylvester Hadamard and the popcount closed
  * form, H.H = nI; hash vs sklearn's murmurhash3_32; ln/sincos vs libm error
  * bounds; Box-Muller closed cases; distribution tests of B, Pi, G, s;
+ * RBF-Matern radii (unit-ball samples: radius law r^n, E||Z||^2 = n/(n+2),
+ * t = 1 reduces to U^(1/n), E C^2 = t n/(n+2), kernel against an independent
+ * Monte Carlo of the same spectral law);
  * row-norm identity of Z; dense n <= 64 product; ||phi|| = 1 and the
  * cos-difference identity; kernel unbiasedness; adjoint dot-product test and
  * finite differences.  No function here is parity-unpinned.
@@ -93,7 +96,7 @@ uint32_t orc_hash4(uint32_t seed, uint32_t w0, uint32_t w1, uint32_t w2, uint32_
     return orc_murmur3_x86_32(key, 16, seed);
 }
 
-enum { TAG_B = 0, TAG_PI = 1, TAG_G = 2, TAG_S = 3 };
+enum { TAG_B = 0, TAG_PI = 1, TAG_G = 2, TAG_S = 3, TAG_MX = 4, TAG_MU = 5 };
 
 /* ------------------------------------------------------------------ */
 /* Elementary functions of the generator, built from + - * / only.     */
@@ -358,14 +361,82 @@ static double pairwise_sumsq(const float *g, int64_t n)
     return r;
 }
 
+/* Canonical pairwise sum of squares of FP64 values (same tree as above). */
+static double pairwise_sumsq64(const double *v, int64_t n)
+{
+    double *y = (double *)malloc((size_t)n * sizeof(double));
+    for (int64_t k = 0; k < n; ++k)
+        y[k] = v[k] * v[k];
+    for (int64_t len = n; len > 1; len /= 2)
+        for (int64_t i = 0; i < len / 2; ++i)
+            y[i] = y[2 * i] + y[2 * i + 1];
+    double r = y[0];
+    free(y);
+    return r;
+}
+
+/* One sample uniform in the unit n-ball (section "Customizing McKernel"):
+ * Z = U^(1/n) X / ||X|| with X ~ N(0, I_n) and U ~ U(0, 1].  Sample `w` of
+ * expansion e draws X_k = normal64(h(4,e,w,2k), h(4,e,w,2k+1)) and
+ * U = (h(5,e,w,0) + 1) 2^-32; U^(1/n) is taken as log2(n) square roots
+ * (n = 2^m), ||X||^2 as the canonical pairwise sum.  Writes Z to z. */
+void orc_ball_sample(uint32_t seed, int64_t e, uint32_t w, int64_t n, double *z)
+{
+    for (int64_t k = 0; k < n; ++k)
+        z[k] = orc_normal64(orc_hash4(seed, TAG_MX, (uint32_t)e, w, (uint32_t)(2 * k)),
+                            orc_hash4(seed, TAG_MX, (uint32_t)e, w, (uint32_t)(2 * k + 1)));
+    double nx2 = pairwise_sumsq64(z, n);
+    double nx = sqrt(nx2);
+    uint32_t hu = orc_hash4(seed, TAG_MU, (uint32_t)e, w, 0u);
+    double r = (double)((uint64_t)hu + 1u) * 0x1p-32;
+    for (int64_t len = n; len > 1; len /= 2)
+        r = sqrt(r);
+    double f = r / nx;
+    for (int64_t k = 0; k < n; ++k)
+        z[k] = f * z[k];
+}
+
+/* RBF-Matern calibration C_jj (section "Customizing McKernel"): the
+ * Euclidean norm of the sum of t i.i.d. samples uniform in the unit n-ball;
+ * sample i of row j is orc_ball_sample with w = j t + i, summed in order
+ * i = 0..t-1, and the norm uses the canonical pairwise sum. */
+double orc_matern(uint32_t seed, int64_t e, int64_t j, int64_t n, int64_t t)
+{
+    double *z = (double *)malloc((size_t)n * sizeof(double));
+    double *acc = (double *)calloc((size_t)n, sizeof(double));
+    for (int64_t i = 0; i < t; ++i) {
+        orc_ball_sample(seed, e, (uint32_t)(j * t + i), n, z);
+        for (int64_t k = 0; k < n; ++k)
+            acc[k] = acc[k] + z[k];
+    }
+    double c2 = pairwise_sumsq64(acc, n);
+    free(z);
+    free(acc);
+    return sqrt(c2);
+}
+
 /* Every output is E x n, row-major by expansion.  S64 is the FP64 diagonal
  * S'_j = s_j / (sigma sqrt(n) ||G||_F); S32 its round-to-nearest FP32 value.
+ * s_j is the calibration radius: chi(n) for the RBF kernel (matern_t = 0),
+ * or the RBF-Matern norm of a sum of matern_t unit-ball samples.
  * chi (optional) receives s_j; norm2 (optional, length E) ||G_e||_F^2. */
+int orc_params_c(uint32_t seed, int64_t n, int64_t E, double sigma, int64_t matern_t,
+                 float *B, int32_t *perm, float *G, double *S64, float *S32,
+                 double *chi, double *norm2);
+
 int orc_params(uint32_t seed, int64_t n, int64_t E, double sigma,
                float *B, int32_t *perm, float *G, double *S64, float *S32,
                double *chi, double *norm2)
 {
-    if (!is_pow2(n) || n < 2 || E < 1 || !(sigma > 0.0) || !isfinite(sigma))
+    return orc_params_c(seed, n, E, sigma, 0, B, perm, G, S64, S32, chi, norm2);
+}
+
+int orc_params_c(uint32_t seed, int64_t n, int64_t E, double sigma, int64_t matern_t,
+                 float *B, int32_t *perm, float *G, double *S64, float *S32,
+                 double *chi, double *norm2)
+{
+    if (!is_pow2(n) || n < 2 || E < 1 || !(sigma > 0.0) || !isfinite(sigma) || matern_t < 0 ||
+        matern_t > 255)
         return 1;
     for (int64_t e = 0; e < E; ++e) {
         float *Be = B + e * n;
@@ -402,7 +473,7 @@ int orc_params(uint32_t seed, int64_t n, int64_t E, double sigma,
         double d2 = sqrt(nrm2);
         double den = d1 * d2;
         for (int64_t j = 0; j < n; ++j) {
-            double s = orc_chi(seed, e, j, n);
+            double s = matern_t > 0 ? orc_matern(seed, e, j, n, matern_t) : orc_chi(seed, e, j, n);
             if (chi)
                 chi[e * n + j] = s;
             double sp = s / den;
