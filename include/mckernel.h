@@ -55,10 +55,22 @@ typedef enum mck_status {
     MCK_ERR_NO_MEMORY = 4    /* device allocation failed */
 } mck_status;
 
+/*
+ * Calibration C of equation "mckernel": the radii s_j of S_j = s_j / (sigma
+ * sqrt(n) ||G||_F).
+ *  - MCK_CALIB_RBF: s_j ~ chi(n), the Gaussian RBF kernel exp(-|x-y|^2/2 sigma^2).
+ *  - MCK_CALIB_MATERN: RBF-Matern (section "Customizing McKernel"): s_j is the
+ *    Euclidean norm of the sum of t = 40 (the paper's value) i.i.d. samples
+ *    uniform in the unit n-ball, each U^(1/n) X/||X|| with X ~ N(0, I_n),
+ *    U ~ U(0,1], drawn from the same hash as B, Pi, G.  n <= 2048 (the draw
+ *    costs t n^2 normals per expansion); larger n returns MCK_ERR_UNSUPPORTED.
+ *  - MCK_CALIB_MATERN_T(t): RBF-Matern with t samples, 1 <= t <= 255.
+ */
 typedef enum mck_calibration {
-    MCK_CALIB_RBF = 0,   /* S from chi(n) radii: the Gaussian RBF kernel exp(-|x-y|^2 / 2 sigma^2) */
-    MCK_CALIB_MATERN = 1 /* RBF-Matern calibration (section "Customizing McKernel"); not implemented */
+    MCK_CALIB_RBF = 0,
+    MCK_CALIB_MATERN = 1
 } mck_calibration;
+#define MCK_CALIB_MATERN_T(t) ((mck_calibration)(0x100 + (t)))
 
 typedef void* mck_stream; /* hipStream_t */
 

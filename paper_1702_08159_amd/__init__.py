@@ -20,6 +20,15 @@ import torch
 from . import _lib
 from ._lib import MCK_CALIB_RBF, MckError
 
+
+def calibration(matern_t: int = 0) -> int:
+    """C-ABI calibration code: RBF (t = 0) or RBF-Matern with t unit-ball samples."""
+    if matern_t == 0:
+        return MCK_CALIB_RBF
+    if not 1 <= matern_t <= 255:
+        raise ValueError("matern_t must be in 1..255")
+    return 1 if matern_t == 40 else 0x100 + matern_t
+
 PAPER_SEED = 1398239763
 MAX_N = 32768
 
@@ -62,7 +71,7 @@ def fwht(v: torch.Tensor) -> torch.Tensor:
     return fwht_(v.contiguous().clone())
 
 
-def params(seed: int, n: int, E: int, sigma: float, device=None):
+def params(seed: int, n: int, E: int, sigma: float, device=None, matern_t: int = 0):
     """Generated B, perm, G, S (FP32) and S64 (FP64) of a seed-mode plan (E x n)."""
     dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
     out = {
@@ -73,7 +82,7 @@ def params(seed: int, n: int, E: int, sigma: float, device=None):
         "S64": torch.empty((E, n), dtype=torch.float64, device=dev),
     }
     with torch.cuda.device(dev):
-        _lib.call("mck_fastfood_params", seed & 0xFFFFFFFF, n, E, float(sigma), MCK_CALIB_RBF, _ptr(out["B"]),
+        _lib.call("mck_fastfood_params", seed & 0xFFFFFFFF, n, E, float(sigma), calibration(matern_t), _ptr(out["B"]),
                   _ptr(out["perm"]), _ptr(out["G"]), _ptr(out["S"]), _ptr(out["S64"]),
                   _stream(out["B"]))
     return out
@@ -89,13 +98,13 @@ _DTYPES = {torch.float32: 0, torch.bfloat16: 1, torch.float16: 2}
 
 
 def forward(x: torch.Tensor, E: int, seed: int = PAPER_SEED, sigma: float = 1.0, out=None,
-            out_dtype=None) -> torch.Tensor:
+            out_dtype=None, matern_t: int = 0) -> torch.Tensor:
     """phi(x): batch x 2nE features [cos blocks, sin blocks].  x may be
     float32, bfloat16 or float16; phi is float32 unless out_dtype (or out)
     says bfloat16 / float16 (16-bit storage, FP32 arithmetic)."""
     if x.dtype != torch.float32 or (out_dtype not in (None, torch.float32)) or (
             out is not None and out.dtype != torch.float32):
-        return _forward_t(x, E, seed, sigma, out, out_dtype)
+        return _forward_t(x, E, seed, sigma, out, out_dtype, matern_t)
     _check(x, "x")
     batch, d = _rows(x)
     n = padded_dim(d)
@@ -103,12 +112,12 @@ def forward(x: torch.Tensor, E: int, seed: int = PAPER_SEED, sigma: float = 1.0,
         out = torch.empty((batch, 2 * n * E), dtype=torch.float32, device=x.device)
     _check(out, "out")
     with torch.cuda.device(x.device):
-        _lib.call("mck_fastfood_forward", _ptr(x), batch, d, E, seed & 0xFFFFFFFF, float(sigma), MCK_CALIB_RBF,
+        _lib.call("mck_fastfood_forward", _ptr(x), batch, d, E, seed & 0xFFFFFFFF, float(sigma), calibration(matern_t),
                   _ptr(out), _stream(x))
     return out
 
 
-def _forward_t(x, E, seed, sigma, out, out_dtype):
+def _forward_t(x, E, seed, sigma, out, out_dtype, matern_t=0):
     if x.dtype not in _DTYPES:
         raise TypeError("x must be float32, bfloat16 or float16")
     _check(x, "x", x.dtype)
@@ -121,24 +130,24 @@ def _forward_t(x, E, seed, sigma, out, out_dtype):
     _check(out, "out", out.dtype)
     with torch.cuda.device(x.device):
         _lib.call("mck_fastfood_forward_t", _ptr(x), _DTYPES[x.dtype], batch, d, E, seed & 0xFFFFFFFF,
-                  float(sigma), MCK_CALIB_RBF, _ptr(out), _DTYPES[out.dtype], _stream(x))
+                  float(sigma), calibration(matern_t), _ptr(out), _DTYPES[out.dtype], _stream(x))
     return out
 
 
-def project(x: torch.Tensor, E: int, seed: int = PAPER_SEED, sigma: float = 1.0) -> torch.Tensor:
+def project(x: torch.Tensor, E: int, seed: int = PAPER_SEED, sigma: float = 1.0, matern_t: int = 0) -> torch.Tensor:
     """z = Z xhat: batch x nE (expansion-major)."""
     _check(x, "x")
     batch, d = _rows(x)
     n = padded_dim(d)
     out = torch.empty((batch, n * E), dtype=torch.float32, device=x.device)
     with torch.cuda.device(x.device):
-        _lib.call("mck_fastfood_project", _ptr(x), batch, d, E, seed & 0xFFFFFFFF, float(sigma), MCK_CALIB_RBF,
+        _lib.call("mck_fastfood_project", _ptr(x), batch, d, E, seed & 0xFFFFFFFF, float(sigma), calibration(matern_t),
                   _ptr(out), _stream(x))
     return out
 
 
 def backward(x: torch.Tensor, dphi: torch.Tensor, E: int, seed: int = PAPER_SEED, sigma: float = 1.0,
-             need_dx: bool = True, need_params: bool = False, out=None):
+             need_dx: bool = True, need_params: bool = False, out=None, matern_t: int = 0):
     """(dx, dB, dG, dS) of <dphi, phi(x)>; entries not requested are None.
     `out` may pass preallocated (dx, dB, dG, dS) (None entries are skipped)."""
     _check(x, "x")
@@ -165,7 +174,7 @@ def backward(x: torch.Tensor, dphi: torch.Tensor, E: int, seed: int = PAPER_SEED
             dB, dG, dS = (torch.empty((E, n), dtype=torch.float32, device=x.device) for _ in range(3))
     with torch.cuda.device(x.device):
         _lib.call("mck_fastfood_backward", _ptr(x), _ptr(dphi), batch, d, E, seed & 0xFFFFFFFF, float(sigma),
-                  MCK_CALIB_RBF, _ptr(dx), _ptr(dB), _ptr(dG), _ptr(dS), _stream(x))
+                  calibration(matern_t), _ptr(dx), _ptr(dB), _ptr(dG), _ptr(dS), _stream(x))
     return dx, dB, dG, dS
 
 

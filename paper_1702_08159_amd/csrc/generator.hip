@@ -18,7 +18,7 @@
 namespace mck {
 namespace {
 
-constexpr uint32_t kTagB = 0, kTagPi = 1, kTagG = 2, kTagS = 3;
+constexpr uint32_t kTagB = 0, kTagPi = 1, kTagG = 2, kTagS = 3, kTagMX = 4, kTagMU = 5;
 
 __device__ __forceinline__ uint32_t rotl(uint32_t x, int r) { return (x << r) | (x >> (32 - r)); }
 
@@ -353,16 +353,91 @@ __global__ void __launch_bounds__(kNormThreads) k_gen_norm2(int64_t n, const flo
         norm2[blockIdx.x] = part[0];
 }
 
-// S'_j = s_j / ((sigma sqrt n) sqrt ||G_e||^2): one thread per (e, j).
+// RBF-Matern radii (section "Customizing McKernel"): C_jj = the norm of the
+// sum of t samples uniform in the unit n-ball, sample i of row j being
+// U^(1/n) X/||X|| with X_k = normal64(h(4,e,w,2k), h(4,e,w,2k+1)),
+// U = (h(5,e,w,0)+1) 2^-32, w = j t + i; U^(1/n) by log2(n) square roots.
+// One block per (e, j); thread k owns the contiguous elements
+// [k cnt, (k+1) cnt), so a pairwise sum inside each thread followed by a
+// pairwise tree over the threads is the canonical pairwise sum of all n.
+constexpr int kMaternThreads = 256;
+constexpr int kMaternMaxCnt = 8;  // n <= 2048
+
+__device__ double block_pairwise(double* part, const double* y2, int cnt, int lanes)
+{
+    double loc[kMaternMaxCnt];
+    for (int k = 0; k < cnt; ++k)
+        loc[k] = y2[k];
+    for (int len = cnt; len > 1; len /= 2)
+        for (int i = 0; i < len / 2; ++i)
+            loc[i] = loc[2 * i] + loc[2 * i + 1];
+    if ((int)threadIdx.x < lanes)
+        part[threadIdx.x] = loc[0];
+    __syncthreads();
+    for (int len = lanes; len > 1; len /= 2) {
+        double s = 0.0;
+        if ((int)threadIdx.x < len / 2)
+            s = part[2 * threadIdx.x] + part[2 * threadIdx.x + 1];
+        __syncthreads();
+        if ((int)threadIdx.x < len / 2)
+            part[threadIdx.x] = s;
+        __syncthreads();
+    }
+    const double r = part[0];
+    __syncthreads();  // part is reused by the next call
+    return r;
+}
+
+__global__ void __launch_bounds__(kMaternThreads)
+    k_gen_matern(uint32_t seed, int64_t n, int64_t E, int t, double* __restrict__ radius)
+{
+    __shared__ double part[kMaternThreads];
+    const int64_t e = (int64_t)blockIdx.x / n;
+    const int64_t j = (int64_t)blockIdx.x % n;
+    const int lanes = n < kMaternThreads ? (int)n : kMaternThreads;
+    const int cnt = (int)(n / lanes);
+    const bool own = (int)threadIdx.x < lanes;
+    const int64_t k0 = (int64_t)threadIdx.x * cnt;
+    double x[kMaternMaxCnt], acc[kMaternMaxCnt], y2[kMaternMaxCnt];
+    for (int k = 0; k < kMaternMaxCnt; ++k)
+        acc[k] = 0.0;
+    for (int i = 0; i < t; ++i) {
+        const uint32_t w = (uint32_t)(j * t + i);
+        for (int k = 0; k < cnt; ++k) {
+            const uint32_t kk = own ? (uint32_t)(k0 + k) : 0u;
+            x[k] = normal64(hash4(seed, kTagMX, (uint32_t)e, w, 2u * kk), hash4(seed, kTagMX, (uint32_t)e, w, 2u * kk + 1u));
+            y2[k] = x[k] * x[k];
+        }
+        const double nx2 = block_pairwise(part, y2, cnt, lanes);
+        const double nx = __builtin_sqrt(nx2);
+        double r = (double)((uint64_t)hash4(seed, kTagMU, (uint32_t)e, w, 0u) + 1u) * 0x1p-32;
+        for (int64_t len = n; len > 1; len /= 2)
+            r = __builtin_sqrt(r);
+        const double f = r / nx;
+        for (int k = 0; k < cnt; ++k) {
+            const double z = f * x[k];
+            acc[k] = acc[k] + z;
+        }
+    }
+    for (int k = 0; k < cnt; ++k)
+        y2[k] = acc[k] * acc[k];
+    const double c2 = block_pairwise(part, y2, cnt, lanes);
+    if (threadIdx.x == 0)
+        radius[blockIdx.x] = __builtin_sqrt(c2);
+}
+
+// S'_j = s_j / ((sigma sqrt n) sqrt ||G_e||^2): one thread per (e, j).  s_j is
+// the chi(n) radius, or (radius != null) the precomputed calibration radius,
+// which may alias S64 (each thread reads its own entry before writing it).
 __global__ void k_gen_s(uint32_t seed, int64_t n, int64_t E, double sigma, const double* __restrict__ norm2,
-                        double* __restrict__ S64, float* __restrict__ S32)
+                        const double* radius, double* S64, float* __restrict__ S32)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= n * E)
         return;
     const uint32_t e = (uint32_t)(idx / n);
     const uint32_t j = (uint32_t)(idx % n);
-    const double s = chi_radius(seed, e, j, n);
+    const double s = radius ? radius[idx] : chi_radius(seed, e, j, n);
     double d1 = __builtin_sqrt((double)n);
     d1 = sigma * d1;
     const double d2 = __builtin_sqrt(norm2[e]);
@@ -387,9 +462,11 @@ __global__ void k_boxmuller(const uint32_t* __restrict__ a, const uint32_t* __re
 
 }  // namespace
 
-hipError_t launch_generate(uint32_t seed, int64_t n, int64_t E, double sigma, float* B, int32_t* perm, float* G,
-                           double* S64, float* S32, double* norm2, hipStream_t s)
+hipError_t launch_generate(uint32_t seed, int64_t n, int64_t E, double sigma, int matern_t, float* B, int32_t* perm,
+                           float* G, double* S64, float* S32, double* norm2, hipStream_t s)
 {
+    if (matern_t > 0 && n > kMaternThreads * kMaternMaxCnt)
+        return hipErrorInvalidValue;
     const int64_t pairs = (n / 2) * E;
     k_gen_bg<<<dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, s>>>(seed, n, E, B, G);
     const int use_lds = n * 4 <= 128 * 1024 ? 1 : 0;
@@ -402,7 +479,14 @@ hipError_t launch_generate(uint32_t seed, int64_t n, int64_t E, double sigma, fl
     k_gen_perm<<<dim3((unsigned)E), dim3(kPermChunk), use_lds ? (size_t)n * 4 : 0, s>>>(seed, n, perm, use_lds);
     k_gen_norm2<<<dim3((unsigned)E), dim3(kNormThreads), 0, s>>>(n, G, norm2);
     const int64_t total = n * E;
-    k_gen_s<<<dim3((unsigned)((total + 127) / 128)), dim3(128), 0, s>>>(seed, n, E, sigma, norm2, S64, S32);
+    const double* radius = nullptr;
+    if (matern_t > 0) {
+        // radii into S64, rescaled in place by k_gen_s
+        k_gen_matern<<<dim3((unsigned)total), dim3(kMaternThreads), 0, s>>>(seed, n, E, matern_t, S64);
+        radius = S64;
+    }
+    k_gen_s<<<dim3((unsigned)((total + 127) / 128)), dim3(128), 0, s>>>(seed, n, E, sigma, norm2, radius, S64,
+                                                                       S32);
     return hipGetLastError();
 }
 

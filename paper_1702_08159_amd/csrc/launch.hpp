@@ -9,8 +9,10 @@ namespace mck {
 
 // Parameter generator: B, perm, G, S64, S32 (E x n each); norm2 is E doubles
 // of scratch.  Six kernels on stream s.
-hipError_t launch_generate(uint32_t seed, int64_t n, int64_t E, double sigma, float* B, int32_t* perm, float* G,
-                           double* S64, float* S32, double* norm2, hipStream_t s);
+// matern_t = 0: RBF (chi(n) radii); 1..255: RBF-Matern radii from matern_t
+// unit-ball samples (n <= 2048).
+hipError_t launch_generate(uint32_t seed, int64_t n, int64_t E, double sigma, int matern_t, float* B, int32_t* perm,
+                           float* G, double* S64, float* S32, double* norm2, hipStream_t s);
 
 // Box-Muller pairs for given hash words (generator self-check).
 hipError_t launch_boxmuller(const uint32_t* a, const uint32_t* b, int64_t count, float* g0, float* g1,

@@ -54,6 +54,27 @@ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) ==
 // Feature scale c = 1/sqrt(nE) of phi (equation mcfeatures).
 float feature_scale(int64_t n, int64_t E) { return (float)(1.0 / std::sqrt((double)n * (double)E)); }
 
+// Calibration code -> RBF-Matern sample count t (0 = RBF).  MCK_CALIB_MATERN
+// is the paper's t = 40; MCK_CALIB_MATERN_T(t) = 0x100 + t for t in 1..255.
+constexpr int64_t kMaternMaxN = 2048;
+
+mck_status check_calib(int calib, int64_t n, int* t)
+{
+    if (calib == MCK_CALIB_RBF) {
+        *t = 0;
+        return MCK_OK;
+    }
+    if (calib == MCK_CALIB_MATERN)
+        *t = 40;
+    else if (calib > 0x100 && calib <= 0x1ff)
+        *t = calib - 0x100;
+    else
+        return fail(MCK_ERR_INVALID_ARG, "unknown calibration");
+    if (n > kMaternMaxN)
+        return fail(MCK_ERR_UNSUPPORTED, "RBF-Matern calibration supports n <= 2048");
+    return MCK_OK;
+}
+
 mck_status check_sigma(double sigma)
 {
     if (!(sigma > 0.0) || !std::isfinite(sigma))
@@ -182,7 +203,15 @@ mck_status get_plan(uint32_t seed, int64_t n, int64_t E, double sigma, int calib
     p.goffB = reinterpret_cast<uint32_t*>(b + off[8]);
     p.GkB = reinterpret_cast<float*>(b + off[9]);
     p.Sh = reinterpret_cast<float*>(b + off[10]);
-    err = mck::launch_generate(seed, n, E, sigma, p.B, p.perm, p.G, p.S64, p.S32, p.norm2, stream);
+    int matern_t = 0;
+    {
+        const mck_status cst = check_calib(calib, n, &matern_t);
+        if (cst != MCK_OK) {
+            free_plan(p);
+            return cst;
+        }
+    }
+    err = mck::launch_generate(seed, n, E, sigma, matern_t, p.B, p.perm, p.G, p.S64, p.S32, p.norm2, stream);
     if (err == hipSuccess)
         err = mck::launch_derive(log2i(n), E, p.perm, p.G, p.S64, p.S32, p.goffF, p.GsF, p.goffB, p.GkB, p.Sh,
                                  stream);
@@ -327,8 +356,12 @@ mck_status mck_fastfood_params(uint32_t seed, int64_t n, int64_t E, double sigma
     mck_status st = check_sigma(sigma);
     if (st != MCK_OK)
         return st;
-    if (calib != MCK_CALIB_RBF)
-        return fail(MCK_ERR_UNSUPPORTED, "only MCK_CALIB_RBF is implemented");
+    {
+        int mt = 0;
+        st = check_calib((int)calib, n, &mt);
+        if (st != MCK_OK)
+            return st;
+    }
     hipStream_t s = static_cast<hipStream_t>(stream);
     Plan* p = nullptr;
     st = get_plan(seed, n, E, sigma, calib, s, &p);
@@ -359,8 +392,12 @@ static mck_status forward_common(const float* x, int64_t batch, int64_t d, int64
     st = check_sigma(sigma);
     if (st != MCK_OK)
         return st;
-    if (calib != MCK_CALIB_RBF)
-        return fail(MCK_ERR_UNSUPPORTED, "only MCK_CALIB_RBF is implemented");
+    {
+        int mt = 0;
+        st = check_calib((int)calib, n, &mt);
+        if (st != MCK_OK)
+            return st;
+    }
     if (batch > 0 && (x == nullptr || out == nullptr))
         return fail(MCK_ERR_INVALID_ARG, "x or output is NULL");
     if (batch == 0)
@@ -402,8 +439,12 @@ mck_status mck_fastfood_forward_t(const void* x, mck_dtype x_type, int64_t batch
     st = check_sigma(sigma);
     if (st != MCK_OK)
         return st;
-    if (calib != MCK_CALIB_RBF)
-        return fail(MCK_ERR_UNSUPPORTED, "only MCK_CALIB_RBF is implemented");
+    {
+        int mt = 0;
+        st = check_calib((int)calib, n, &mt);
+        if (st != MCK_OK)
+            return st;
+    }
     if (batch > 0 && (x == nullptr || phi == nullptr))
         return fail(MCK_ERR_INVALID_ARG, "x or phi is NULL");
     if (batch == 0)
@@ -439,8 +480,12 @@ mck_status mck_fastfood_backward(const float* x, const float* dphi, int64_t batc
     st = check_sigma(sigma);
     if (st != MCK_OK)
         return st;
-    if (calib != MCK_CALIB_RBF)
-        return fail(MCK_ERR_UNSUPPORTED, "only MCK_CALIB_RBF is implemented");
+    {
+        int mt = 0;
+        st = check_calib((int)calib, n, &mt);
+        if (st != MCK_OK)
+            return st;
+    }
     if (batch > 0 && (x == nullptr || dphi == nullptr))
         return fail(MCK_ERR_INVALID_ARG, "x or dphi is NULL");
     hipStream_t s = static_cast<hipStream_t>(stream);

@@ -61,13 +61,18 @@ def test_validation_without_gpu(lib):
     assert _st(lib, "mck_fwht", null, 2, 8, null) == 1
     assert b"NULL" in lib.mck_last_error()
     assert _st(lib, "mck_fwht", null, 0, 8, null) == 0       # empty batch
-    # forward: d < 1, E < 1, bad sigma, unsupported calibration, NULL x, too long
+    # forward: d < 1, E < 1, bad sigma, calibration codes, NULL x, too long
     fwd = "mck_fastfood_forward"
     assert _st(lib, fwd, null, 4, 0, 1, 1, 1.0, 0, null, null) == 1
     assert _st(lib, fwd, null, 4, 8, 0, 1, 1.0, 0, null, null) == 1
     for sig in (0.0, -1.0, float("nan"), float("inf")):
         assert _st(lib, fwd, null, 4, 8, 1, 1, sig, 0, null, null) == 1
-    assert _st(lib, fwd, null, 4, 8, 1, 1, 1.0, 1, null, null) == 2
+    # calibrations: unknown codes are invalid; RBF-Matern (1, or 0x100 + t)
+    # is accepted up to n = 2048 and unsupported beyond
+    for code in (2, 7, 0x100, 0x200, -1):
+        assert _st(lib, fwd, null, 4, 8, 1, 1, 1.0, code, null, null) == 1
+    assert _st(lib, fwd, null, 4, 3000, 1, 1, 1.0, 1, null, null) == 2
+    assert _st(lib, fwd, null, 4, 3000, 1, 1, 1.0, 0x105, null, null) == 2
     assert _st(lib, fwd, null, 4, 8, 1, 1, 1.0, 0, null, null) == 1
     assert _st(lib, fwd, null, 4, 40000, 1, 1, 1.0, 0, null, null) == 2
     assert _st(lib, fwd, null, 0, 8, 2, 1, 1.0, 0, null, null) == 0  # empty batch
@@ -81,12 +86,13 @@ def test_validation_without_gpu(lib):
     p = ctypes.c_void_p(16)
     assert _st(lib, "mck_fastfood_forward_p", null, 1, 8, 16, 1, p, p, p, p, null, null) == 1
     assert _st(lib, "mck_fastfood_forward_p", null, 1, 8, 8, 1, p, p, p, p, null, null) == 1
-    # params: n not a power of two, n = 1, bad sigma, unsupported calibration
+    # params: n not a power of two, n = 1, bad sigma, unknown / unsupported calibration
     prm = "mck_fastfood_params"
     assert _st(lib, prm, 1, 12, 1, 1.0, 0, null, null, null, null, null, null) == 1
     assert _st(lib, prm, 1, 1, 1, 1.0, 0, null, null, null, null, null, null) == 1
     assert _st(lib, prm, 1, 8, 1, 0.0, 0, null, null, null, null, null, null) == 1
-    assert _st(lib, prm, 1, 8, 1, 1.0, 1, null, null, null, null, null, null) == 2
+    assert _st(lib, prm, 1, 8, 1, 1.0, 9, null, null, null, null, null, null) == 1
+    assert _st(lib, prm, 1, 4096, 1, 1.0, 1, null, null, null, null, null, null) == 2
     # generator self-check: negative count, NULL pointers
     assert _st(lib, "mck_gen_boxmuller", null, null, -1, null, null, null) == 1
     assert _st(lib, "mck_gen_boxmuller", null, null, 5, null, null, null) == 1
