@@ -81,10 +81,21 @@ typedef enum mck_dtype {
     MCK_DTYPE_F16 = 2   /* IEEE binary16 */
 } mck_dtype;
 
-/* Largest n a single call accepts (single-pass transform held in LDS). */
+/*
+ * Largest n of the single-pass kernels (the transform held in LDS): the
+ * backward, the projection and the explicit-parameter calls.
+ */
 #define MCK_MAX_N 32768
 
-/* n = max(2, smallest power of two >= d); 0 when d < 1 or n > MCK_MAX_N. */
+/*
+ * Largest n of mck_fwht and of the seed-mode feature map
+ * (mck_fastfood_forward, mck_fastfood_forward_t): beyond MCK_MAX_N they run
+ * as a row pass over 2^15-element chunks plus column passes over the high
+ * index bits, through FP32 scratch rows allocated on the stream.
+ */
+#define MCK_MAX_N_LONG 16777216
+
+/* n = max(2, smallest power of two >= d); 0 when d < 1 or n > MCK_MAX_N_LONG. */
 int64_t mck_padded_dim(int64_t d);
 
 /* Static description of a status code. */
@@ -98,7 +109,8 @@ const char* mck_last_error(void);
  * `data` (batch x n) is replaced by H_n row, unnormalised, natural Sylvester
  * order: (H v)_i = sum_k (-1)^popcount(i & k) v_k (section "Fast Walsh
  * Hadamard": H_0 = [1], H_k = [[H, H], [H, -H]]).
- * n must be a power of two, 1 <= n <= MCK_MAX_N (n = 1 is the identity).
+ * n must be a power of two, 1 <= n <= MCK_MAX_N_LONG (n = 1 is the
+ * identity); for n > MCK_MAX_N, data must be 16-byte aligned.
  */
 mck_status mck_fwht(float* data, int64_t batch, int64_t n, mck_stream stream);
 
@@ -113,9 +125,12 @@ mck_status mck_fastfood_params(uint32_t seed, int64_t n, int64_t E, double sigma
                                float* B, int32_t* perm, float* G, float* S, double* S64, mck_stream stream);
 
 /*
- * Feature map.  x: batch x d (d >= 1, n = mck_padded_dim(d) <= MCK_MAX_N),
+ * Feature map.  x: batch x d (d >= 1, n = mck_padded_dim(d) <= MCK_MAX_N_LONG),
  * E >= 1, sigma finite > 0.  phi: batch x (2 n E), per row the E cosine
- * blocks of length n (expansion-major) followed by the E sine blocks.
+ * blocks of length n (expansion-major) followed by the E sine blocks.  For
+ * n > MCK_MAX_N the call allocates two FP32 scratch buffers of up to
+ * 2^27 floats each on `stream` (stream-ordered) and one row of phi must stay
+ * below 2^31 bytes.
  */
 mck_status mck_fastfood_forward(const float* x, int64_t batch, int64_t d, int64_t E, uint32_t seed,
                                 double sigma, mck_calibration calib, float* phi, mck_stream stream);

@@ -28,6 +28,7 @@ SOURCES = {
     "kernels.hip": [],
     "head.hip": [],
     "forward16.hip": [],
+    "longn.hip": [],
     "generator.hip": ["-ffp-contract=off"],
     "runtime.cpp": ["-x", "hip"],
 }

@@ -41,6 +41,15 @@ hipError_t launch_forward_t(int M, bool vec, int xt, int yt, const void* x, int6
                             const float* B, const uint32_t* goff, const float* Gs, const float* Sx, float cs,
                             void* out, hipStream_t s);
 
+// n = 2^M > 2^15 (longn.hip): in-place H on 16-byte aligned rows, and the
+// feature map through FP32 scratch rows u, w (batch x n each).  Sh for such
+// plans comes from launch_sh (S / 2 pi from the FP64 S).
+hipError_t launch_fwht_long(int M, float* data, int64_t batch, bool vec, hipStream_t s);
+hipError_t launch_forward_long(int M, bool vec, int xt, int yt, const void* x, int64_t batch, int d, int64_t E,
+                               const float* B, const int32_t* perm, const float* G, const float* Sh, float cs,
+                               void* phi, float* u, float* w, hipStream_t s);
+hipError_t launch_sh(const double* S64, float* Sh, int64_t count, hipStream_t s);
+
 // Backward geometry: blocks, passes per block.
 struct BwdGeometry {
     int64_t blocks;

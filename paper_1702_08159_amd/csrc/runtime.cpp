@@ -46,7 +46,15 @@ int64_t padded_dim(int64_t d)
     int64_t n = 2;
     while (n < d)
         n *= 2;
-    return n > MCK_MAX_N ? 0 : n;
+    return n > MCK_MAX_N_LONG ? 0 : n;
+}
+
+// Single-pass kernels only (backward, projection, explicit parameters).
+mck_status check_single_pass(int64_t n)
+{
+    if (n > MCK_MAX_N)
+        return fail(MCK_ERR_UNSUPPORTED, "n > MCK_MAX_N is supported by mck_fwht and the forward feature map only");
+    return MCK_OK;
 }
 
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
@@ -92,7 +100,7 @@ mck_status check_common(int64_t batch, int64_t d, int64_t E, int64_t* n_out)
         return fail(MCK_ERR_INVALID_ARG, "E must be in [1, 2^20]");
     const int64_t n = padded_dim(d);
     if (n == 0)
-        return fail(MCK_ERR_UNSUPPORTED, "padded dimension exceeds MCK_MAX_N");
+        return fail(MCK_ERR_UNSUPPORTED, "padded dimension exceeds MCK_MAX_N_LONG");
     if (E * (n > 2048 ? n : 2048) > (int64_t(1) << 28))
         return fail(MCK_ERR_UNSUPPORTED, "E * n too large (parameter arrays limited to 2^28 entries)");
     if (d > (int64_t(1) << 30) || batch > (int64_t(1) << 40))
@@ -213,8 +221,9 @@ mck_status get_plan(uint32_t seed, int64_t n, int64_t E, double sigma, int calib
     }
     err = mck::launch_generate(seed, n, E, sigma, matern_t, p.B, p.perm, p.G, p.S64, p.S32, p.norm2, stream);
     if (err == hipSuccess)
-        err = mck::launch_derive(log2i(n), E, p.perm, p.G, p.S64, p.S32, p.goffF, p.GsF, p.goffB, p.GkB, p.Sh,
-                                 stream);
+        err = n > MCK_MAX_N ? mck::launch_sh(p.S64, p.Sh, n * E, stream)
+                            : mck::launch_derive(log2i(n), E, p.perm, p.G, p.S64, p.S32, p.goffF, p.GsF, p.goffB,
+                                                 p.GkB, p.Sh, stream);
     if (err == hipSuccess)
         err = hipStreamSynchronize(stream);  // the plan may be used from other streams next
     if (err != hipSuccess) {
@@ -333,14 +342,20 @@ mck_status mck_fwht(float* data, int64_t batch, int64_t n, mck_stream stream)
         return fail(MCK_ERR_INVALID_ARG, "batch must be >= 0");
     if (!is_pow2(n))
         return fail(MCK_ERR_INVALID_ARG, "n must be a power of two >= 1");
-    if (n > MCK_MAX_N)
-        return fail(MCK_ERR_UNSUPPORTED, "n exceeds MCK_MAX_N");
+    if (n > MCK_MAX_N_LONG)
+        return fail(MCK_ERR_UNSUPPORTED, "n exceeds MCK_MAX_N_LONG");
     if (batch > 0 && data == nullptr)
         return fail(MCK_ERR_INVALID_ARG, "data is NULL");
     if (batch == 0 || n == 1)
         return MCK_OK;
-    const hipError_t err = mck::launch_fwht(log2i(n), data, batch, aligned16(data) && n >= 4,
-                                            static_cast<hipStream_t>(stream));
+    if (n > MCK_MAX_N && !aligned16(data))
+        return fail(MCK_ERR_INVALID_ARG, "data must be 16-byte aligned for n > MCK_MAX_N");
+    if (batch > (int64_t(1) << 40) / n)
+        return fail(MCK_ERR_INVALID_ARG, "batch * n out of range");
+    const hipError_t err = n > MCK_MAX_N
+                               ? mck::launch_fwht_long(log2i(n), data, batch, true, static_cast<hipStream_t>(stream))
+                               : mck::launch_fwht(log2i(n), data, batch, aligned16(data) && n >= 4,
+                                                  static_cast<hipStream_t>(stream));
     return err == hipSuccess ? MCK_OK : hip_fail(err, "mck_fwht");
 }
 
@@ -349,8 +364,8 @@ mck_status mck_fastfood_params(uint32_t seed, int64_t n, int64_t E, double sigma
 {
     if (!is_pow2(n) || n < 2)
         return fail(MCK_ERR_INVALID_ARG, "n must be a power of two >= 2");
-    if (n > MCK_MAX_N)
-        return fail(MCK_ERR_UNSUPPORTED, "n exceeds MCK_MAX_N");
+    if (n > MCK_MAX_N_LONG)
+        return fail(MCK_ERR_UNSUPPORTED, "n exceeds MCK_MAX_N_LONG");
     if (E < 1 || E > (int64_t(1) << 20))
         return fail(MCK_ERR_INVALID_ARG, "E must be in [1, 2^20]");
     mck_status st = check_sigma(sigma);
@@ -382,6 +397,38 @@ mck_status mck_fastfood_params(uint32_t seed, int64_t n, int64_t E, double sigma
     return err == hipSuccess ? MCK_OK : hip_fail(err, "mck_fastfood_params copy");
 }
 
+// Feature map for n > MCK_MAX_N: row chunks sized so that one chunk's phi
+// range stays below 2^31 bytes and each FP32 scratch buffer below 2^27
+// floats; the scratch is stream-ordered.
+static mck_status forward_long(const Plan* p, const void* x, int xt, int64_t batch, int64_t d, int64_t n, int64_t E,
+                               void* phi, int yt, hipStream_t s)
+{
+    const int64_t xb = xt == 0 ? 4 : 2, yb = yt == 0 ? 4 : 2;
+    const int64_t row_phi = 2 * n * E * yb;
+    if (row_phi > (int64_t(1) << 31) - 4096)
+        return fail(MCK_ERR_UNSUPPORTED, "one row of phi exceeds 2^31 bytes");
+    int64_t rows_per = ((int64_t(1) << 31) - 4096) / row_phi;
+    const int64_t scratch_rows = ((int64_t)1 << 27) / n;
+    rows_per = rows_per > scratch_rows ? scratch_rows : rows_per;
+    rows_per = rows_per > batch ? batch : (rows_per < 1 ? 1 : rows_per);
+    float* u = nullptr;
+    hipError_t err = hipMallocAsync(reinterpret_cast<void**>(&u), (size_t)(2 * rows_per * n) * sizeof(float), s);
+    if (err != hipSuccess)
+        return fail(MCK_ERR_NO_MEMORY, std::string("long-vector scratch: ") + hipGetErrorString(err));
+    float* w = u + rows_per * n;
+    const uintptr_t xa = (uintptr_t)(4 * xb);
+    const bool vec = reinterpret_cast<uintptr_t>(x) % xa == 0 && d % 4 == 0;
+    const float cs = feature_scale(n, E);
+    for (int64_t r0 = 0; r0 < batch && err == hipSuccess; r0 += rows_per) {
+        const int64_t rows = batch - r0 < rows_per ? batch - r0 : rows_per;
+        err = mck::launch_forward_long(log2i(n), vec, xt, yt, static_cast<const char*>(x) + r0 * d * xb, rows,
+                                       (int)d, E, p->B, p->perm, p->G, p->Sh, cs,
+                                       static_cast<char*>(phi) + r0 * row_phi, u, w, s);
+    }
+    (void)hipFreeAsync(u, s);
+    return err == hipSuccess ? MCK_OK : hip_fail(err, "long-vector forward launch");
+}
+
 static mck_status forward_common(const float* x, int64_t batch, int64_t d, int64_t E, uint32_t seed, double sigma,
                                  mck_calibration calib, float* out, bool trig, mck_stream stream)
 {
@@ -404,9 +451,13 @@ static mck_status forward_common(const float* x, int64_t batch, int64_t d, int64
         return MCK_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
     Plan* p = nullptr;
+    if (n > MCK_MAX_N && !trig)
+        return check_single_pass(n);
     st = get_plan(seed, n, E, sigma, calib, s, &p);
     if (st != MCK_OK)
         return st;
+    if (n > MCK_MAX_N)
+        return forward_long(p, x, 0, batch, d, n, E, out, 0, s);
     const hipError_t err = mck::launch_forward(log2i(n), vec_ok(x, out, d, n), trig, x, batch, (int)d, E, p->B,
                                                p->goffF, p->GsF, trig ? p->Sh : p->S32, feature_scale(n, E),
                                                out, s);
@@ -454,6 +505,8 @@ mck_status mck_fastfood_forward_t(const void* x, mck_dtype x_type, int64_t batch
     st = get_plan(seed, n, E, sigma, calib, s, &p);
     if (st != MCK_OK)
         return st;
+    if (n > MCK_MAX_N)
+        return forward_long(p, x, xt, batch, d, n, E, phi, yt, s);
     // vector path: 4 elements per access, so 4-element alignment of both arrays
     const uintptr_t xa = 4u * (xt == 0 ? 4u : 2u), ya = 4u * (yt == 0 ? 4u : 2u);
     const bool vec = (reinterpret_cast<uintptr_t>(x) % xa == 0) && (reinterpret_cast<uintptr_t>(phi) % ya == 0) &&
@@ -475,6 +528,9 @@ mck_status mck_fastfood_backward(const float* x, const float* dphi, int64_t batc
 {
     int64_t n = 0;
     mck_status st = check_common(batch, d, E, &n);
+    if (st != MCK_OK)
+        return st;
+    st = check_single_pass(n);
     if (st != MCK_OK)
         return st;
     st = check_sigma(sigma);
@@ -517,6 +573,9 @@ static mck_status check_explicit(int64_t batch, int64_t d, int64_t n, int64_t E,
         return st;
     if (n != nn)
         return fail(MCK_ERR_INVALID_ARG, "n must equal mck_padded_dim(d)");
+    st = check_single_pass(n);
+    if (st != MCK_OK)
+        return st;
     if (!B || !perm || !G || !S)
         return fail(MCK_ERR_INVALID_ARG, "B, perm, G and S must be non-NULL");
     return MCK_OK;

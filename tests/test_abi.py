@@ -38,8 +38,9 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_padded_dim(lib):
-    assert [lib.mck_padded_dim(d) for d in (0, 1, 2, 3, 5, 784, 1024, 1025, 32768, 32769)] == \
-        [0, 2, 2, 4, 8, 1024, 1024, 2048, 32768, 0]
+    assert [lib.mck_padded_dim(d) for d in (0, 1, 2, 3, 5, 784, 1024, 1025, 32768, 32769, 1 << 24,
+                                            (1 << 24) + 1)] == \
+        [0, 2, 2, 4, 8, 1024, 1024, 2048, 32768, 65536, 1 << 24, 0]
 
 
 def test_status_strings(lib):
@@ -57,7 +58,8 @@ def test_validation_without_gpu(lib):
     # mck_fwht: n not a power of two, negative batch, n too large, NULL data
     assert _st(lib, "mck_fwht", null, 1, 3, null) == 1
     assert _st(lib, "mck_fwht", null, -1, 4, null) == 1
-    assert _st(lib, "mck_fwht", null, 1, 65536, null) == 2
+    assert _st(lib, "mck_fwht", null, 1, 1 << 25, null) == 2
+    assert _st(lib, "mck_fwht", ctypes.c_void_p(8), 1, 65536, null) == 1   # unaligned long rows
     assert _st(lib, "mck_fwht", null, 2, 8, null) == 1
     assert b"NULL" in lib.mck_last_error()
     assert _st(lib, "mck_fwht", null, 0, 8, null) == 0       # empty batch
@@ -74,7 +76,12 @@ def test_validation_without_gpu(lib):
     assert _st(lib, fwd, null, 4, 3000, 1, 1, 1.0, 1, null, null) == 2
     assert _st(lib, fwd, null, 4, 3000, 1, 1, 1.0, 0x105, null, null) == 2
     assert _st(lib, fwd, null, 4, 8, 1, 1, 1.0, 0, null, null) == 1
-    assert _st(lib, fwd, null, 4, 40000, 1, 1, 1.0, 0, null, null) == 2
+    assert _st(lib, fwd, null, 4, (1 << 24) + 1, 1, 1, 1.0, 0, null, null) == 2
+    # single-pass calls refuse n > 2^15
+    assert _st(lib, "mck_fastfood_project", ctypes.c_void_p(16), 4, 40000, 1, 1, 1.0, 0,
+               ctypes.c_void_p(16), null) == 2
+    assert _st(lib, "mck_fastfood_backward", ctypes.c_void_p(16), ctypes.c_void_p(16), 4, 40000, 1, 1, 1.0, 0,
+               ctypes.c_void_p(16), null, null, null, null) == 2
     assert _st(lib, fwd, null, 0, 8, 2, 1, 1.0, 0, null, null) == 0  # empty batch
     # backward: NULL dphi; nothing requested is a no-op
     bwd = "mck_fastfood_backward"

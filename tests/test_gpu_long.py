@@ -1,0 +1,119 @@
+"""GPU parity for n > 2^15 (row pass over 2^15-element chunks plus column
+passes over the high index bits) against the FP64 oracle.
+
+Tolerances as for the single-pass path: integer transform inputs bit-exact,
+float transform 1e-6 and FP32 features 1e-5 normwise per row; 16-bit phi
+within its unit roundoff (2.5e-3 bfloat16, 3e-4 half)."""
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mk():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1702_08159_amd as mk
+
+    mk._lib.lib()
+    return mk
+
+
+def rowwise_rel(a, ref):
+    a = np.asarray(a, np.float64).reshape(ref.shape)
+    return np.linalg.norm(a - ref, axis=1) / np.linalg.norm(ref, axis=1)
+
+
+@pytest.mark.parametrize("m,batch", [(16, 3), (17, 2), (20, 2), (21, 1), (22, 1), (24, 1)])
+def test_fwht_long_integer_bit_exact(mk, orc, m, batch):
+    import torch
+
+    n = 1 << m
+    rng = np.random.default_rng(m)
+    v = rng.integers(-1, 2, size=(batch, n)).astype(np.float32)
+    got = mk.fwht(torch.from_numpy(v).cuda()).cpu().numpy()
+    ref = orc.fwht(v.astype(np.float64))
+    assert np.array_equal(got.astype(np.float64), ref)
+
+
+@pytest.mark.parametrize("m", [16, 19, 23])
+def test_fwht_long_float(mk, orc, m):
+    import torch
+
+    n = 1 << m
+    v = workloads.normal(2, n, seed=m)
+    got = mk.fwht(torch.from_numpy(v).cuda()).cpu().numpy()
+    ref = orc.fwht(v.astype(np.float64))
+    assert rowwise_rel(got, ref).max() <= 1e-6
+
+
+@pytest.mark.parametrize("d,E,batch", [(40000, 2, 3), (1 << 17, 1, 2), (70001, 3, 9)])
+def test_forward_long_matches_oracle(mk, orc, d, E, batch):
+    import torch
+
+    n = mk.padded_dim(d)
+    sigma = float(np.sqrt(n))
+    x = workloads.normal(batch, d, seed=d)
+    phi = mk.forward(torch.from_numpy(x).cuda(), E, 4242, sigma).cpu().numpy()
+    ref, _, _ = orc.forward(x.astype(np.float64), E, 4242, sigma)
+    assert phi.shape == ref.shape
+    assert rowwise_rel(phi, ref).max() <= 1e-5
+
+
+def test_forward_long_unaligned_rows(mk, orc):
+    import torch
+
+    d, E, batch = 33000, 1, 3  # d not a multiple of 4: scalar loads
+    x = workloads.normal(batch, d, seed=5)
+    buf = torch.zeros(batch * d + 1, dtype=torch.float32, device="cuda")
+    xv = buf[1:].view(batch, d)
+    xv.copy_(torch.from_numpy(x).cuda())
+    phi = mk.forward(xv, E, 9, 181.0).cpu().numpy()
+    ref, _, _ = orc.forward(x.astype(np.float64), E, 9, 181.0)
+    assert rowwise_rel(phi, ref).max() <= 1e-5
+
+
+@pytest.mark.parametrize("name", ["bfloat16", "float16"])
+def test_long_vector_16bit_config(mk, orc, name):
+    # batch 64 of N(0,1) inputs with n = 2^20, E = 4, sigma = sqrt(n), phi in
+    # 16 bits; sampled rows against the oracle
+    import torch
+
+    dt = getattr(torch, name)
+    n, E, batch = 1 << 20, 4, 64
+    sigma = float(np.sqrt(n))
+    x = workloads.normal(batch, n, seed=20)
+    phi = mk.forward(torch.from_numpy(x).cuda(), E, workloads.FASTFOOD_SEED, sigma, out_dtype=dt)
+    rows = [0, 31, 63]
+    sub = phi[rows].float().cpu().numpy()
+    ref, _, _ = orc.forward(x[rows].astype(np.float64), E, workloads.FASTFOOD_SEED, sigma)
+    tol = {"bfloat16": 2.5e-3, "float16": 3e-4}[name]
+    assert rowwise_rel(sub, ref).max() <= tol
+    # and bit for bit the rounding of the FP32 path
+    phi32 = mk.forward(torch.from_numpy(x[rows]).cuda(), E, workloads.FASTFOOD_SEED, sigma)
+    assert torch.equal(phi32.to(dt), phi[rows])
+
+
+def test_long_x16_input(mk, orc):
+    import torch
+
+    n, E = 1 << 16, 2
+    x = torch.from_numpy(workloads.normal(4, n, seed=3)).cuda().to(torch.bfloat16)
+    phi = mk.forward(x, E, 1, 256.0, out_dtype=torch.bfloat16)
+    ref, _, _ = orc.forward(x.float().cpu().numpy().astype(np.float64), E, 1, 256.0)
+    assert rowwise_rel(phi.float().cpu().numpy(), ref).max() <= 2.5e-3
+
+
+def test_long_single_pass_only_calls_refuse(mk):
+    import torch
+
+    x = torch.zeros((2, 40000), device="cuda")
+    with pytest.raises(mk.MckError):
+        mk.project(x, 1, 1, 1.0)
+    with pytest.raises(mk.MckError):
+        mk.backward(x, torch.zeros((2, 2 * 65536), device="cuda"), 1, 1, 1.0)
