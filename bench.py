@@ -35,6 +35,8 @@ BWD_BYTES_PER_VECTOR = 8 * D + 8 * N * E          # read x and dphi, write dx
 HBM_PEAK_GBS = 8000.0
 GRAPH_STEPS = 10
 TRAIN_BATCH, TRAIN_CLASSES = 1024, 10
+LONG_BATCH, LONG_N, LONG_E = 64, 1 << 20, 4
+LONG_SIGMA = float(LONG_N) ** 0.5
 METRIC = "Fastfood vectors/s + %HBM peak at n=1024 E=16, fwd and fwd+bwd vs oracle error"
 
 # HBM bytes per forward launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of
@@ -70,6 +72,7 @@ def main():
     ap.add_argument("--bwd-steps", type=int, default=40)
     ap.add_argument("--train-steps", type=int, default=20)
     ap.add_argument("--lowp-steps", type=int, default=100)
+    ap.add_argument("--long-steps", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["fwd", "bwd", "train", "all"], default="all",
@@ -178,6 +181,38 @@ def main():
             lowp[name] = {"ms_per_step": ms, "vectors_per_s": BATCH / (ms * 1e-3),
                           "bytes_per_vector": 4 * D + 4 * N * E, "phi": phi16}
             log("forward, phi in %s: %.4f ms/step" % (name, ms))
+    longv = {}
+    if args.only in ("fwd", "all") and args.long_steps > 0:
+        # long vectors: batch 64 of N(0,1) rows, n = 2^20, E = 4, sigma = sqrt(n),
+        # phi in FP32 / bfloat16 / half (row pass + column passes per expansion)
+        xl = torch.from_numpy(workloads.normal(LONG_BATCH, LONG_N, seed=20)).to(dev)
+        for name, dt in (("f32", torch.float32), ("bf16", torch.bfloat16), ("f16", torch.float16)):
+            out = torch.empty((LONG_BATCH, 2 * LONG_N * LONG_E), dtype=dt, device=dev)
+
+            def lf():
+                mk.forward(xl, LONG_E, seed, LONG_SIGMA, out=out)
+
+            lf()
+            torch.cuda.synchronize()
+            t0.record(stream)
+            for _ in range(args.long_steps):
+                lf()
+            t1.record(stream)
+            torch.cuda.synchronize()
+            ms = t0.elapsed_time(t1) / args.long_steps
+            yb = 4 if name == "f32" else 2
+            alg = 4 * LONG_N + 2 * LONG_N * LONG_E * yb
+            longv[name] = {"ms_per_step": ms, "vectors_per_s": LONG_BATCH / (ms * 1e-3),
+                           "algorithmic_bytes_per_vector": alg,
+                           "achieved_GBs": alg * LONG_BATCH / (ms * 1e-3) / 1e9}
+            if name != "f32":
+                longv[name]["sample"] = out[:3].float().cpu().numpy()
+            log("long vectors (n=2^20, E=4), phi %s: %.3f ms/step" % (name, ms))
+            del out
+        for name in ("bf16", "f16"):
+            longv[name]["speedup_vs_f32"] = longv["f32"]["ms_per_step"] / longv[name]["ms_per_step"]
+        xl_head = xl[:3].cpu().numpy()
+        del xl
     if args.only in ("bwd", "all"):
         dphi = torch.from_numpy(workloads.grad_features(BATCH, 2 * N * E)).to(dev)
         grads = (torch.empty_like(x),) + tuple(torch.empty((E, N), dtype=torch.float32, device=dev)
@@ -269,6 +304,14 @@ def main():
             ph = rec["phi"][:256].float().cpu().numpy().astype(np.float64)
             rec["max_row_rel_err_vs_oracle"] = float(
                 (np.linalg.norm(ph - ref, axis=1) / np.linalg.norm(ref, axis=1)).max())
+        if longv:
+            refl, _, _ = oracle.forward(xl_head.astype(np.float64), LONG_E, seed, LONG_SIGMA)
+            for name in ("bf16", "f16"):
+                ph = longv[name]["sample"].astype(np.float64)
+                longv[name]["max_row_rel_err_vs_oracle"] = float(
+                    (np.linalg.norm(ph - refl, axis=1) / np.linalg.norm(refl, axis=1)).max())
+    for rec in longv.values():
+        rec.pop("sample", None)
     for rec in lowp.values():
         rec.pop("phi", None)
         rec["speedup_vs_f32"] = fwd_ms / rec["ms_per_step"] if math.isfinite(fwd_ms) else None
@@ -295,6 +338,8 @@ def main():
         "bwd_ms_per_step": bwd_ms,
         "bwd_steps": args.bwd_steps,
         "fwd_16bit_phi": lowp,
+        "long_vectors": {"config": {"batch": LONG_BATCH, "n": LONG_N, "E": LONG_E, "sigma": LONG_SIGMA,
+                                    "x": "N(0,1) float32"}, **longv} if longv else None,
         "train_step_ms": train_ms,
         "train_vectors_per_s": TRAIN_BATCH / (train_ms * 1e-3),
         "train_config": {"batch": TRAIN_BATCH, "classes": TRAIN_CLASSES, "d": D, "n": N, "E": E, "sigma": 1.0,
