@@ -73,6 +73,7 @@ def main():
     ap.add_argument("--train-steps", type=int, default=20)
     ap.add_argument("--lowp-steps", type=int, default=100)
     ap.add_argument("--long-steps", type=int, default=5)
+    ap.add_argument("--batched-steps", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["fwd", "bwd", "train", "all"], default="all",
@@ -213,6 +214,45 @@ def main():
             longv[name]["speedup_vs_f32"] = longv["f32"]["ms_per_step"] / longv[name]["ms_per_step"]
         xl_head = xl[:3].cpu().numpy()
         del xl
+    batched = None
+    if args.only in ("fwd", "all") and args.batched_steps > 0:
+        # 32 independent maps: n = 2^U{8..16}, batch U{16..4096}, E U{1..16},
+        # N(0,1) rows of length n, sigma = sqrt(n); one batched call vs one
+        # call per map
+        rng = np.random.default_rng(0)
+        ms_, bs_, es_ = rng.integers(8, 17, 32), rng.integers(16, 4097, 32), rng.integers(1, 17, 32)
+        maps, outs, alg = [], [], 0
+        for k in range(32):
+            n_k, b_k, e_k = 1 << int(ms_[k]), int(bs_[k]), int(es_[k])
+            xk = torch.randn((b_k, n_k), generator=torch.Generator(device=dev).manual_seed(k), device=dev)
+            maps.append((xk, e_k, 2000 + k, float(n_k) ** 0.5))
+            outs.append(torch.empty((b_k, 2 * n_k * e_k), dtype=torch.float32, device=dev))
+            alg += b_k * (4 * n_k + 8 * n_k * e_k)
+
+        def run_batched():
+            mk.forward_batched(maps, outs=outs)
+
+        def run_single():
+            for (xk, e_k, s_k, sg_k), o in zip(maps, outs):
+                mk.forward(xk, e_k, s_k, sg_k, out=o)
+
+        res = {}
+        for name, fn in (("batched", run_batched), ("one_call_per_map", run_single)):
+            fn()
+            torch.cuda.synchronize()
+            t0.record(stream)
+            for _ in range(args.batched_steps):
+                fn()
+            t1.record(stream)
+            torch.cuda.synchronize()
+            res[name] = t0.elapsed_time(t1) / args.batched_steps
+            log("32 uneven maps, %s: %.3f ms" % (name, res[name]))
+        batched = {"maps": 32, "phi_GB": sum(o.numel() for o in outs) * 4 / 1e9,
+                   "batched_ms": res["batched"], "one_call_per_map_ms": res["one_call_per_map"],
+                   "speedup": res["one_call_per_map"] / res["batched"],
+                   "achieved_GBs": alg / (res["batched"] * 1e-3) / 1e9}
+        del maps, outs
+        torch.cuda.empty_cache()
     if args.only in ("bwd", "all"):
         dphi = torch.from_numpy(workloads.grad_features(BATCH, 2 * N * E)).to(dev)
         grads = (torch.empty_like(x),) + tuple(torch.empty((E, N), dtype=torch.float32, device=dev)
@@ -338,6 +378,7 @@ def main():
         "bwd_ms_per_step": bwd_ms,
         "bwd_steps": args.bwd_steps,
         "fwd_16bit_phi": lowp,
+        "batched_uneven_maps": batched,
         "long_vectors": {"config": {"batch": LONG_BATCH, "n": LONG_N, "E": LONG_E, "sigma": LONG_SIGMA,
                                     "x": "N(0,1) float32"}, **longv} if longv else None,
         "train_step_ms": train_ms,

@@ -150,6 +150,34 @@ mck_status mck_fastfood_forward_t(const void* x, mck_dtype x_type, int64_t batch
                                   uint32_t seed, double sigma, mck_calibration calib, void* phi, mck_dtype phi_type,
                                   mck_stream stream);
 
+/*
+ * One of several independent feature maps for mck_fastfood_forward_batched:
+ * the arguments of mck_fastfood_forward (FP32 x and phi, caller-owned device
+ * arrays).
+ */
+typedef struct mck_instance {
+    const float* x; /* batch x d */
+    int64_t batch;
+    int64_t d;
+    int64_t E;
+    uint32_t seed;
+    double sigma;
+    mck_calibration calib;
+    float* phi; /* batch x 2nE */
+} mck_instance;
+
+/*
+ * Runs `count` independent feature maps (uneven n, batch, E, seeds), each with
+ * the result of mck_fastfood_forward, in as few launches as possible: the
+ * maps with n <= MCK_MAX_N are grouped by n into one launch per 32 maps of
+ * that n (blocks of all of them share one grid, so many small maps fill the
+ * GPU together); longer maps run through the row and column passes.  `inst`
+ * is a host array.  Every instance is validated before anything is enqueued;
+ * the error message names the first bad instance.  Plans are built (and
+ * kept from eviction) for the duration of the call.
+ */
+mck_status mck_fastfood_forward_batched(const mck_instance* inst, int64_t count, mck_stream stream);
+
 /* z = Z xhat without the trigonometric map: batch x (n E), expansion-major. */
 mck_status mck_fastfood_project(const float* x, int64_t batch, int64_t d, int64_t E, uint32_t seed,
                                 double sigma, mck_calibration calib, float* z, mck_stream stream);

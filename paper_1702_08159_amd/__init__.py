@@ -134,6 +134,39 @@ def _forward_t(x, E, seed, sigma, out, out_dtype, matern_t=0):
     return out
 
 
+def forward_batched(maps, outs=None):
+    """Several independent feature maps in one call: `maps` is a list of
+    (x, E, seed, sigma) or (x, E, seed, sigma, matern_t); returns the list of
+    phi (FP32).  Maps of the same n share one grouped launch."""
+    maps = list(maps)
+    if not maps:
+        return []
+    arr = (_lib.Instance * len(maps))()
+    res = []
+    dev = None
+    for k, m in enumerate(maps):
+        x, E, seed, sigma = m[:4]
+        mt = m[4] if len(m) > 4 else 0
+        _check(x, "x")
+        dev = dev or x.device
+        if x.device != dev:
+            raise ValueError("all maps must be on one device")
+        batch, d = _rows(x)
+        n = padded_dim(d)
+        if n == 0:
+            raise ValueError("d out of range")
+        phi = outs[k] if outs is not None else torch.empty((batch, 2 * n * E), dtype=torch.float32, device=dev)
+        _check(phi, "phi")
+        if phi.shape != (batch, 2 * n * E):
+            raise ValueError("phi must be batch x 2nE")
+        arr[k] = _lib.Instance(_ptr(x), batch, d, E, seed & 0xFFFFFFFF, float(sigma), calibration(mt), _ptr(phi))
+        res.append(phi)
+    with torch.cuda.device(dev):
+        _lib.call("mck_fastfood_forward_batched", ctypes.cast(arr, ctypes.c_void_p), len(maps),
+                  _stream(maps[0][0]))
+    return res
+
+
 def project(x: torch.Tensor, E: int, seed: int = PAPER_SEED, sigma: float = 1.0, matern_t: int = 0) -> torch.Tensor:
     """z = Z xhat: batch x nE (expansion-major)."""
     _check(x, "x")

@@ -32,6 +32,7 @@ SIGNATURES = {
     "mck_fastfood_forward": (_int, [_vp, _i64, _i64, _i64, _u32, _f64, _int, _vp, _vp]),
     "mck_fastfood_project": (_int, [_vp, _i64, _i64, _i64, _u32, _f64, _int, _vp, _vp]),
     "mck_fastfood_forward_t": (_int, [_vp, _int, _i64, _i64, _i64, _u32, _f64, _int, _vp, _int, _vp]),
+    "mck_fastfood_forward_batched": (_int, [_vp, _i64, _vp]),
     "mck_fastfood_backward": (_int, [_vp, _vp, _i64, _i64, _i64, _u32, _f64, _int, _vp, _vp, _vp, _vp, _vp]),
     "mck_fastfood_forward_p": (_int, [_vp, _i64, _i64, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
     "mck_fastfood_backward_p": (_int, [_vp, _vp, _i64, _i64, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
@@ -41,6 +42,12 @@ SIGNATURES = {
     "mck_axpy": (_int, [_vp, _vp, _i64, ctypes.c_float, _vp]),
     "mck_shutdown": (None, []),
 }
+
+
+class Instance(ctypes.Structure):
+    """mck_instance of the C interface."""
+    _fields_ = [("x", _vp), ("batch", _i64), ("d", _i64), ("E", _i64), ("seed", _u32), ("sigma", _f64),
+                ("calib", _int), ("phi", _vp)]
 
 
 class MckError(RuntimeError):

@@ -61,9 +61,8 @@ struct ChunkMap {
     int chunk;      // expansion chunk
 };
 
-__device__ __forceinline__ ChunkMap chunk_map(int nchunks)
+__device__ __forceinline__ ChunkMap chunk_map(int64_t b, int nchunks)
 {
-    const int64_t b = blockIdx.x;
     const int64_t q = b / kXcds;
     ChunkMap m;
     m.chunk = (int)(q % nchunks);
@@ -81,19 +80,22 @@ __device__ __forceinline__ ChunkMap chunk_map(int nchunks)
 //
 // XT, YT: storage types of x and of the output (kF32, kBF16, kF16); the
 // arithmetic is FP32 throughout, 16-bit outputs are rounded to nearest even.
-template <int M, int P, bool VEC, bool TRIG, int XT = kF32, int YT = kF32>
-__global__ void __launch_bounds__((Geo<M, P>::BLOCK), (Geo<M, P>::kMulti ? 1 : 4))
-    k_forward(const void* __restrict__ x, uint32_t x_bytes, int64_t batch, int d, int E, int echunk, int nchunks,
-              const float* __restrict__ B, const uint32_t* __restrict__ goff, const float* __restrict__ Gs,
-              const float* __restrict__ Sx, uint32_t par_bytes, uint32_t goff_bytes, float cs,
-              void* __restrict__ out, uint32_t out_bytes)
+// The body is shared by the plain launch (one map) and the grouped launch
+// (many maps of the same n, one descriptor each); `blk` is the block's index
+// within its map.
+template <int M, int P, bool VEC, bool TRIG, int XT, int YT>
+__device__ __forceinline__ void forward_body(const void* __restrict__ x, uint32_t x_bytes, int64_t batch, int d,
+                                             int E, int echunk, int nchunks, const float* __restrict__ B,
+                                             const uint32_t* __restrict__ goff, const float* __restrict__ Gs,
+                                             const float* __restrict__ Sx, uint32_t par_bytes, uint32_t goff_bytes,
+                                             float cs, void* __restrict__ out, uint32_t out_bytes, int64_t blk,
+                                             float* lds)
 {
     constexpr uint32_t XB = elem_bytes<XT>(), YB = elem_bytes<YT>();
     using g = Geo<M, P>;
     constexpr int EPL = g::EPL, n = g::n, K = g::K;
     constexpr bool PIPE = (P == 4);
-    __shared__ float lds[g::LDS_FLOATS];
-    const ChunkMap cm = chunk_map(nchunks);
+    const ChunkMap cm = chunk_map(blk, nchunks);
     if (cm.group * g::RPB >= batch)
         return;  // whole block past the end (uniform)
     const uint32_t lane = threadIdx.x;
@@ -204,6 +206,56 @@ __global__ void __launch_bounds__((Geo<M, P>::BLOCK), (Geo<M, P>::kMulti ? 1 : 4
                 bstore_elem<YT>(rY, yoff + YB * ((uint32_t)e * n + rpart(M, P, 0, k)), v[k]);
         }
     }
+}
+
+template <int M, int P, bool VEC, bool TRIG, int XT = kF32, int YT = kF32>
+__global__ void __launch_bounds__((Geo<M, P>::BLOCK), (Geo<M, P>::kMulti ? 1 : 4))
+    k_forward(const void* __restrict__ x, uint32_t x_bytes, int64_t batch, int d, int E, int echunk, int nchunks,
+              const float* __restrict__ B, const uint32_t* __restrict__ goff, const float* __restrict__ Gs,
+              const float* __restrict__ Sx, uint32_t par_bytes, uint32_t goff_bytes, float cs,
+              void* __restrict__ out, uint32_t out_bytes)
+{
+    __shared__ float lds[Geo<M, P>::LDS_FLOATS];
+    forward_body<M, P, VEC, TRIG, XT, YT>(x, x_bytes, batch, d, E, echunk, nchunks, B, goff, Gs, Sx, par_bytes,
+                                          goff_bytes, cs, out, out_bytes, blockIdx.x, lds);
+}
+
+// Grouped launch: up to kGroupMax feature maps of the same n (FP32 x and
+// phi) in one grid; map i owns blocks [block0, block0 + blocks) and its
+// descriptor travels in the kernel arguments.
+constexpr int kGroupMax = 32;
+
+struct FwdDesc {
+    const void* x;
+    void* out;
+    const float* B;
+    const uint32_t* goff;
+    const float* Gs;
+    const float* Sx;
+    int64_t batch;
+    int64_t block0;
+    int d, E, echunk, nchunks;
+    uint32_t x_bytes, out_bytes, par_bytes, goff_bytes;
+    float cs;
+};
+
+struct FwdGroup {
+    int count;
+    FwdDesc m[kGroupMax];
+};
+
+template <int M, int P, bool VEC>
+__global__ void __launch_bounds__((Geo<M, P>::BLOCK), (Geo<M, P>::kMulti ? 1 : 4)) k_forward_group(FwdGroup grp)
+{
+    __shared__ float lds[Geo<M, P>::LDS_FLOATS];
+    const int64_t b = blockIdx.x;
+    int i = 0;
+    while (i + 1 < grp.count && grp.m[i + 1].block0 <= b)
+        ++i;
+    const FwdDesc& q = grp.m[i];
+    forward_body<M, P, VEC, true, kF32, kF32>(q.x, q.x_bytes, q.batch, q.d, q.E, q.echunk, q.nchunks, q.B, q.goff,
+                                              q.Gs, q.Sx, q.par_bytes, q.goff_bytes, q.cs, q.out, q.out_bytes,
+                                              b - q.block0, lds);
 }
 
 

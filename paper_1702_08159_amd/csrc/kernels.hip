@@ -783,6 +783,69 @@ hipError_t launch_forward(int M, bool vec, bool trig, const float* x, int64_t ba
     return dispatch_m<RunForwardT<kF32, kF32>::Run>(M, vec, trig, x, batch, d, E, B, goff, Gs, Sx, cs, out, s);
 }
 
+namespace {
+
+template <int M>
+struct RunGroup {
+    static hipError_t run(bool vec, const GroupInst* inst, int count, hipStream_t s)
+    {
+        constexpr int P = fwd_p(M);
+        using g = Geo<M, P>;
+        // split expansions so that the whole group holds >= ~16k waves
+        int64_t base_waves = 0;
+        for (int i = 0; i < count; ++i)
+            base_waves += (inst[i].batch + g::RPB - 1) / g::RPB * (g::BLOCK / 64);
+        const int64_t factor = base_waves > 0 ? (16384 + base_waves - 1) / base_waves : 1;
+        for (int i0 = 0; i0 < count; i0 += kGroupMax) {
+            FwdGroup grp;
+            grp.count = count - i0 < kGroupMax ? count - i0 : kGroupMax;
+            int64_t blocks = 0;
+            for (int k = 0; k < grp.count; ++k) {
+                const GroupInst& in = inst[i0 + k];
+                FwdDesc& q = grp.m[k];
+                const int64_t groups = (in.batch + g::RPB - 1) / g::RPB;
+                int64_t nchunks = factor > in.E ? in.E : factor;
+                const int64_t echunk = (in.E + nchunks - 1) / nchunks;
+                nchunks = (in.E + echunk - 1) / echunk;
+                q.x = in.x;
+                q.out = in.phi;
+                q.B = in.B;
+                q.goff = in.goff;
+                q.Gs = in.Gs;
+                q.Sx = in.Sh;
+                q.batch = in.batch;
+                q.block0 = blocks;
+                q.d = in.d;
+                q.E = (int)in.E;
+                q.echunk = (int)echunk;
+                q.nchunks = (int)nchunks;
+                q.x_bytes = (uint32_t)(4 * in.batch * in.d);
+                q.out_bytes = (uint32_t)(4 * in.batch * 2 * g::n * in.E);
+                q.par_bytes = (uint32_t)(4 * g::n * in.E);
+                q.goff_bytes = (uint32_t)(4 * g::RPB * g::n * in.E);
+                q.cs = in.cs;
+                blocks += ((groups + kXcds - 1) / kXcds) * kXcds * nchunks;
+            }
+            const dim3 grid((unsigned)blocks), blk(g::BLOCK);
+            if (vec && M >= 2)
+                k_forward_group<M, P, true><<<grid, blk, 0, s>>>(grp);
+            else
+                k_forward_group<M, P, false><<<grid, blk, 0, s>>>(grp);
+            const hipError_t err = hipGetLastError();
+            if (err != hipSuccess)
+                return err;
+        }
+        return hipSuccess;
+    }
+};
+
+}  // namespace
+
+hipError_t launch_forward_group(int M, bool vec, const GroupInst* inst, int count, hipStream_t s)
+{
+    return dispatch_m<RunGroup>(M, vec, inst, count, s);
+}
+
 BwdGeometry backward_geometry(int M, int64_t batch, int d)
 {
     BwdGeometry g{1, 1, 64};

@@ -50,6 +50,23 @@ hipError_t launch_forward_long(int M, bool vec, int xt, int yt, const void* x, i
                                void* phi, float* u, float* w, hipStream_t s);
 hipError_t launch_sh(const double* S64, float* Sh, int64_t count, hipStream_t s);
 
+// Grouped forward (FP32 x and phi, n = 2^M <= 2^15): several feature maps
+// of the same n in one launch per kGroupMax maps.  Each map's x and phi
+// byte ranges must be below 2^31.
+struct GroupInst {
+    const float* x;
+    int64_t batch;
+    int d;
+    int64_t E;
+    const float* B;
+    const uint32_t* goff;
+    const float* Gs;
+    const float* Sh;
+    float cs;
+    float* phi;
+};
+hipError_t launch_forward_group(int M, bool vec, const GroupInst* inst, int count, hipStream_t s);
+
 // Backward geometry: blocks, passes per block.
 struct BwdGeometry {
     int64_t blocks;

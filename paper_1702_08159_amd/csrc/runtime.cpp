@@ -8,6 +8,8 @@
 #include <cstdint>
 #include <cstring>
 #include <list>
+#include <map>
+#include <vector>
 #include <mutex>
 #include <string>
 
@@ -111,6 +113,7 @@ mck_status check_common(int64_t batch, int64_t d, int64_t E, int64_t* n_out)
 
 // ------------------------------------------------------------------ plan cache
 struct Plan {
+    int pins = 0;  // > 0 while a batched call holds it: not evicted
     int device = 0;
     uint32_t seed = 0;
     int64_t n = 0, E = 0;
@@ -152,7 +155,7 @@ void free_plan(Plan& p)
 
 // Returns the plan for the arguments, building it on `stream` if needed.
 mck_status get_plan(uint32_t seed, int64_t n, int64_t E, double sigma, int calib, hipStream_t stream,
-                    Plan** out)
+                    Plan** out, bool pin = false)
 {
     int dev = 0;
     hipError_t err = hipGetDevice(&dev);
@@ -164,6 +167,8 @@ mck_status get_plan(uint32_t seed, int64_t n, int64_t E, double sigma, int calib
             it->calib == calib) {
             g_plans.splice(g_plans.begin(), g_plans, it);
             *out = &g_plans.front();
+            if (pin)
+                ++g_plans.front().pins;
             return MCK_OK;
         }
     }
@@ -184,14 +189,17 @@ mck_status get_plan(uint32_t seed, int64_t n, int64_t E, double sigma, int calib
         off[i] = total;
         total += align_up(sz[i]);
     }
-    // evict least recently used plans beyond the limits
     size_t used = 0;
     for (auto& q : g_plans)
         used += q.bytes;
-    while (!g_plans.empty() && (g_plans.size() >= kMaxPlans || used + total > kMaxPlanBytes)) {
-        used -= g_plans.back().bytes;
-        free_plan(g_plans.back());
-        g_plans.pop_back();
+    // evict least recently used unpinned plans
+    for (auto it = g_plans.end(); it != g_plans.begin() && (g_plans.size() >= kMaxPlans || used + total > kMaxPlanBytes);) {
+        --it;
+        if (it->pins > 0)
+            continue;
+        used -= it->bytes;
+        free_plan(*it);
+        it = g_plans.erase(it);
     }
     err = hipMalloc(&p.block, total);
     if (err != hipSuccess) {
@@ -232,6 +240,8 @@ mck_status get_plan(uint32_t seed, int64_t n, int64_t E, double sigma, int calib
     }
     g_plans.push_front(p);
     *out = &g_plans.front();
+    if (pin)
+        ++g_plans.front().pins;
     return MCK_OK;
 }
 
@@ -514,6 +524,78 @@ mck_status mck_fastfood_forward_t(const void* x, mck_dtype x_type, int64_t batch
     const hipError_t err = mck::launch_forward_t(log2i(n), vec, xt, yt, x, batch, (int)d, E, p->B, p->goffF, p->GsF,
                                                  p->Sh, feature_scale(n, E), phi, s);
     return err == hipSuccess ? MCK_OK : hip_fail(err, "forward launch");
+}
+
+mck_status mck_fastfood_forward_batched(const mck_instance* inst, int64_t count, mck_stream stream)
+{
+    if (count < 0 || (count > 0 && inst == nullptr))
+        return fail(MCK_ERR_INVALID_ARG, "count must be >= 0 and inst non-NULL");
+    // validate everything before enqueueing anything
+    std::vector<int64_t> ns((size_t)count);
+    for (int64_t i = 0; i < count; ++i) {
+        const mck_instance& q = inst[i];
+        mck_status st = check_common(q.batch, q.d, q.E, &ns[i]);
+        if (st == MCK_OK)
+            st = check_sigma(q.sigma);
+        if (st == MCK_OK) {
+            int mt = 0;
+            st = check_calib((int)q.calib, ns[i], &mt);
+        }
+        if (st == MCK_OK && q.batch > 0 && (q.x == nullptr || q.phi == nullptr))
+            st = fail(MCK_ERR_INVALID_ARG, "x or phi is NULL");
+        if (st != MCK_OK) {
+            g_last_error = "instance " + std::to_string(i) + ": " + g_last_error;
+            return st;
+        }
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<Plan*> plans((size_t)count, nullptr);
+    auto unpin = [&]() {
+        std::lock_guard<std::mutex> lock(g_mutex);
+        for (Plan* p : plans)
+            if (p)
+                --p->pins;
+    };
+    mck_status st = MCK_OK;
+    for (int64_t i = 0; i < count && st == MCK_OK; ++i)
+        if (inst[i].batch > 0)
+            st = get_plan(inst[i].seed, ns[i], inst[i].E, inst[i].sigma, inst[i].calib, s, &plans[i], true);
+    if (st != MCK_OK) {
+        unpin();
+        return st;
+    }
+    // group the single-launch maps by (log2 n, vector path); the rest run alone
+    std::map<std::pair<int, bool>, std::vector<mck::GroupInst>> groups;
+    const int64_t lim = (int64_t(1) << 31) - 4096;
+    for (int64_t i = 0; i < count && st == MCK_OK; ++i) {
+        const mck_instance& q = inst[i];
+        if (q.batch == 0)
+            continue;
+        const int64_t n = ns[i];
+        const Plan* p = plans[i];
+        if (n <= MCK_MAX_N && 4 * q.batch * q.d <= lim && 4 * q.batch * 2 * n * q.E <= lim) {
+            groups[{log2i(n), vec_ok(q.x, q.phi, q.d, n)}].push_back(
+                {q.x, q.batch, (int)q.d, q.E, p->B, p->goffF, p->GsF, p->Sh, feature_scale(n, q.E), q.phi});
+        } else if (n > MCK_MAX_N) {
+            st = forward_long(p, q.x, 0, q.batch, q.d, n, q.E, q.phi, 0, s);
+        } else {
+            const hipError_t err = mck::launch_forward(log2i(n), vec_ok(q.x, q.phi, q.d, n), true, q.x, q.batch,
+                                                       (int)q.d, q.E, p->B, p->goffF, p->GsF, p->Sh,
+                                                       feature_scale(n, q.E), q.phi, s);
+            if (err != hipSuccess)
+                st = hip_fail(err, "forward launch");
+        }
+    }
+    for (auto& kv : groups) {
+        if (st != MCK_OK)
+            break;
+        const hipError_t err = mck::launch_forward_group(kv.first.first, kv.first.second, kv.second.data(),
+                                                         (int)kv.second.size(), s);
+        if (err != hipSuccess)
+            st = hip_fail(err, "grouped forward launch");
+    }
+    unpin();
+    return st;
 }
 
 mck_status mck_fastfood_project(const float* x, int64_t batch, int64_t d, int64_t E, uint32_t seed, double sigma,
