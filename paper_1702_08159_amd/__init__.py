@@ -6,10 +6,14 @@ CUDA (ROCm) tensors on the current device, and work is enqueued on torch's
 current stream.
 
     phi = fastfood(x, E=16, seed=1398239763, sigma=2.0)   # autograd w.r.t. x
+    phi = forward(x, E, seed, sigma, out_dtype=torch.bfloat16)  # 16-bit storage
+    phi = forward(x, E, seed, sigma, matern_t=40)         # RBF-Matern calibration
+    phis = forward_batched([(x1, E1, s1, g1), (x2, E2, s2, g2)])  # uneven maps
     z = project(x, E, seed, sigma)                        # Z xhat, no trig
     p = params(seed, n, E, sigma)                         # generated B, perm, G, S
-    y = fwht(v)                                           # H v along the last axis
+    y = fwht(v)                                           # H v along the last axis (n <= 2^24)
     phi = FastfoodExplicit.apply(x, B, perm, G, S)        # learnable diagonals
+    out = train_step(x, labels, W, b, B, perm, G, S, lr)  # softmax(W phi + b) SGD step
 """
 from __future__ import annotations
 

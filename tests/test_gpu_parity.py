@@ -299,3 +299,30 @@ def test_autograd_function(mk, torch_mod, orc):
     (phi * w).sum().backward()
     rx, _, _, _ = _oracle_grads(orc, x.detach().cpu().numpy(), w.cpu().numpy(), 2, 21, 1.5)
     assert rowwise_rel(x.grad.cpu().numpy(), rx).max() <= FEAT_TOL
+
+
+def test_forward_graph_replays_match_eager(mk, torch_mod):
+    # the benchmark replays the forward from a HIP graph: every replay, with
+    # eager work and synchronisation in between, must reproduce eager phi
+    torch = torch_mod
+    x = to_dev(torch, workloads.mnist_sparse(512))
+    ref = mk.forward(x, 8, workloads.FASTFOOD_SEED, 2.0).clone()
+    out = torch.empty_like(ref)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        mk.forward(x, 8, workloads.FASTFOOD_SEED, 2.0, out=out)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(3):
+            mk.forward(x, 8, workloads.FASTFOOD_SEED, 2.0, out=out)
+    for k in range(4):
+        out.fill_(float("nan"))
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), k
+        junk = mk.forward(x[:7], 3, 11, 1.0)  # eager work between replays
+        torch.cuda.synchronize()
+        del junk
