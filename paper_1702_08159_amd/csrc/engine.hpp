@@ -402,4 +402,12 @@ __device__ __forceinline__ void cossin_rev(float t, float c, float& co, float& s
     si = c * __builtin_amdgcn_sinf(r);
 }
 
+// The same without the scale (callers that fold c into a later product).
+__device__ __forceinline__ void cossin_rev1(float t, float& co, float& si)
+{
+    const float r = __builtin_amdgcn_fractf(t);
+    co = __builtin_amdgcn_cosf(r);
+    si = __builtin_amdgcn_sinf(r);
+}
+
 }  // namespace mck

@@ -95,7 +95,7 @@ template <int M>
 __device__ __forceinline__ void block_partials(float* lds, const LaneArr<float, M, BwdGeo<M>::P>& aS,
                                                const LaneArr<float, M, BwdGeo<M>::P>& aG,
                                                const LaneArr<float, M, BwdGeo<M>::P>& aB, float* dst,
-                                               uint32_t wave, uint32_t grp, uint32_t t)
+                                               uint32_t wave, uint32_t grp, uint32_t t, float scaleS)
 {
     using bg = BwdGeo<M>;
     constexpr int P = bg::P;
@@ -121,7 +121,7 @@ __device__ __forceinline__ void block_partials(float* lds, const LaneArr<float, 
             float s = 0.f;
             for (int k = 0; k < SLOTS; ++k)
                 s += lds[k * n + i];
-            dst[(int64_t)a * n + i] = s;
+            dst[(int64_t)a * n + i] = a == 0 ? s * scaleS : s;
         }
     }
     __syncthreads();
@@ -279,7 +279,7 @@ __global__ void __launch_bounds__(BwdGeo<M>::THREADS)
         }
 
         if constexpr (PARAMS)
-            block_partials<M>(lds, aS, aG, aB, partial + (((int64_t)blockIdx.x * E + e) * 3) * n, wave, grp, t);
+            block_partials<M>(lds, aS, aG, aB, partial + (((int64_t)blockIdx.x * E + e) * 3) * n, wave, grp, t, 1.f);
     }
 }
 
@@ -389,7 +389,7 @@ __global__ void __launch_bounds__(BwdGeo<M>::THREADS)
             const uint32_t* srcO = goff + (int64_t)e * GOFF_E;
             for (int i = threadIdx.x; i < n; i += bg::THREADS) {
                 prm[PB + i] = srcB[i];
-                prm[PS + i] = srcS[i];
+                prm[PS + i] = cs * srcS[i];
                 prm[PH + i] = srcH[i];
                 // lane-major source (t * EPL + r) to float4-major
                 const int tq = i / EPL, r = i % EPL;
@@ -443,8 +443,10 @@ __global__ void __launch_bounds__(BwdGeo<M>::THREADS)
             ld_nat(q, PH);
 #pragma unroll
             for (int r = 0; r < EPL; ++r) {
+                // dz / c: the scale c rides in the staged S (c S) and in
+                // the final dS sum
                 float co, si;
-                cossin_rev(v[r] * q[r], cs, co, si);
+                cossin_rev1(v[r] * q[r], co, si);
                 const float dz = co * sn[r] - si * cn[r];
                 if constexpr (PARAMS)
                     aS[r] += dz * v[r];
@@ -494,22 +496,31 @@ __global__ void __launch_bounds__(BwdGeo<M>::THREADS)
             }
             if (dx != nullptr) {
                 float* drow = dxl + (uint32_t)(p * bg::ROWS + (int)(wave * g::RPB + grp)) * (uint32_t)d4;
-                if constexpr (VEC) {
+                if constexpr (VEC && EPL >= 4) {
+                    // all reads first (from a clamped, always-valid address),
+                    // then the adds and the masked writes: one LDS round trip
+                    if (e > 0) {
+                        float4 o[NQ];
+#pragma unroll
+                        for (int j = 0; j < EPL / 4; ++j) {
+                            const uint32_t i0 = ct | rpart(M, P, 0, 4 * j);
+                            const bool ok = valid && (int)i0 < d;
+                            o[j] = *reinterpret_cast<const float4*>(drow + (ok ? i0 : 0u));
+                        }
+#pragma unroll
+                        for (int j = 0; j < EPL / 4; ++j) {
+                            v[4 * j] += o[j].x;
+                            v[4 * j + 1] += o[j].y;
+                            v[4 * j + 2] += o[j].z;
+                            v[4 * j + 3] += o[j].w;
+                        }
+                    }
 #pragma unroll
                     for (int j = 0; j < EPL / 4; ++j) {
                         const uint32_t i0 = ct | rpart(M, P, 0, 4 * j);
-                        if (valid && (int)i0 < d) {
-                            float4* dq = reinterpret_cast<float4*>(drow + i0);
-                            float4 a = make_float4(v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]);
-                            if (e > 0) {
-                                const float4 o = *dq;
-                                a.x += o.x;
-                                a.y += o.y;
-                                a.z += o.z;
-                                a.w += o.w;
-                            }
-                            *dq = a;
-                        }
+                        if (valid && (int)i0 < d)
+                            *reinterpret_cast<float4*>(drow + i0) =
+                                make_float4(v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]);
                     }
                 } else {
 #pragma unroll
@@ -522,7 +533,7 @@ __global__ void __launch_bounds__(BwdGeo<M>::THREADS)
             }
         }
         if constexpr (PARAMS)
-            block_partials<M>(lds, aS, aG, aB, partial + (((int64_t)blockIdx.x * E + e) * 3) * n, wave, grp, t);
+            block_partials<M>(lds, aS, aG, aB, partial + (((int64_t)blockIdx.x * E + e) * 3) * n, wave, grp, t, cs);
         else
             __syncthreads();  // the parameter stage is rewritten next
     }
