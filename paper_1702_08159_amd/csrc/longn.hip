@@ -3,22 +3,28 @@
 //
 // H_n = H_{n/2^15} (x) H_{2^15} (Sylvester's H is the tensor product of one
 // 2x2 butterfly per index bit, section "Fast Walsh Hadamard"), so the
-// transform splits into
+// transform splits into two commuting factors
 //   a row pass:    H_{2^15} on each contiguous chunk of 2^15 elements
 //                  (the register/LDS engine, one chunk per 1024-lane block);
 //   column passes: H over the remaining high index bits, at most 5 per pass:
 //                  each lane holds the 2^B elements of four adjacent columns
 //                  (stride 2^s) in VGPRs, so consecutive lanes read
 //                  consecutive 16-byte pieces.
-// The feature map per expansion is then four passes over an FP32 scratch
-// copy of the batch:
-//   1. row pass with input B o xhat (x read in place, zero padding by range);
-//   2. column pass(es)                           -> u = H B xhat
-//   3. row pass with input G_i u[perm[i]]        (gather from L2 / MALL)
+// The feature map per expansion is four passes over two FP32 scratch copies
+// u, w of the batch:
+//   1. column pass(es) on B o xhat (x read in place, zero padding by range)
+//   2. row pass -> u = H B xhat, held in LDS; Pi is applied as a bucket
+//      exchange between chunks: the chunk's elements go out to w grouped by
+//      the destination chunk that gathers them (srcA order, coalesced)
+//   3. row pass: each destination chunk reads its C groups from w
+//      (contiguous runs), places them by dstB in LDS, multiplies by G and
+//      transforms -> u
 //   4. column pass(es); the last one multiplies by S / (2 pi) and writes
 //      c cos, c sin in the storage type of phi.
-// Row-pass blocks are mapped so that an XCD works on one row at a time,
-// which keeps that row's u (4 MB at n = 2^20) in its L2 for the gather.
+// A direct gather u[perm[i]] over the whole row would read one 4-byte value
+// per 64-byte line from L2; the exchange moves every value twice, in full
+// lines.  Row-pass blocks are mapped so that an XCD works on one row at a
+// time.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -33,11 +39,24 @@ constexpr int kRowM = 15;        // chunk length 2^15 of the row pass
 constexpr int kRowP = 5;         // 32 elements per lane, 1024 lanes per chunk
 constexpr int kColThreads = 256;
 constexpr int kColMaxB = 5;
+constexpr int kMaxChunks = 1 << (24 - kRowM);
 
 using RG = Geo<kRowM, kRowP>;
 
-// Row pass input modes.
-enum : int { kInPlace = 0, kInX = 1, kInGather = 2 };
+// Row pass input and output modes.
+enum : int { kInRow = 0, kInBucket = 1 };
+enum : int { kOutRow = 0, kOutBucket = 1 };
+
+struct RowArgs {
+    float* dst;
+    const float* src;
+    int64_t rows, chunks;
+    const float* G;          // kInBucket: G of the expansion
+    const uint16_t* srcA;    // kOutBucket
+    const uint16_t* dstB;    // kInBucket
+    const int32_t* bpre;     // kInBucket
+    const int32_t* bdelta;   // kInBucket
+};
 
 // XCD-aware (row, chunk) of a row-pass block: blocks are dealt to the 8 XCDs
 // round robin; XCD x takes rows x, x + 8, ... one after another, all chunks
@@ -50,66 +69,107 @@ __device__ __forceinline__ void row_chunk(int64_t rows, int64_t chunks, int64_t&
     c = q % chunks;
 }
 
-// One 2^15 chunk per block: load (mode), H_{2^15}, store to dst (FP32,
-// natural order).  dst rows have length n = chunks * 2^15.
-template <int MODE, bool VEC, int XT>
-__global__ void __launch_bounds__(RG::BLOCK)
-    k_rows(float* __restrict__ dst, const float* src, int64_t rows, int64_t chunks, const void* __restrict__ x,
-           int d, const float* __restrict__ Bv, const int32_t* __restrict__ perm, const float* __restrict__ Gv)
+// One 2^15 chunk per block: H_{2^15} of the chunk's input, output to dst
+// (rows of length n = chunks 2^15).
+//   kInRow:    the chunk of src (natural order)
+//   kInBucket: G o (the elements Pi sends to this chunk), gathered from the
+//              bucket-ordered src
+//   kOutRow:    natural order
+//   kOutBucket: bucket order of this source chunk (srcA)
+template <int IN, int OUT, bool VEC>
+__global__ void __launch_bounds__(RG::BLOCK) k_rows(RowArgs a)
 {
-    constexpr int M = kRowM, P = kRowP, EPL = RG::EPL, K = RG::K;
+    constexpr int M = kRowM, P = kRowP, EPL = RG::EPL, K = RG::K, BLOCK = RG::BLOCK;
     constexpr int64_t CH = RG::n;
     __shared__ float lds[RG::LDS_FLOATS];
     int64_t r, c;
-    row_chunk(rows, chunks, r, c);
-    if (r >= rows)
+    row_chunk(a.rows, a.chunks, r, c);
+    if (r >= a.rows)
         return;  // uniform per block
-    const int64_t n = chunks * CH;
+    const int64_t n = a.chunks * CH;
     const uint32_t t = threadIdx.x;
     const uint32_t tb = tpart<M, P, 0>(t);
-    float* out = dst + r * n + c * CH;
-    const rsrc_t ro = make_rsrc(out, (uint32_t)(CH * 4));
+    const rsrc_t ro = make_rsrc(a.dst + r * n + c * CH, (uint32_t)(CH * 4));
     float v[EPL];
-    if constexpr (MODE == kInPlace) {
-        bload_row<M, P, VEC>(v, ro, 0u, (int)CH, t, true);
-    } else if constexpr (MODE == kInX) {
-        // xhat o B: the chunk's part of row r of x (elements past d read 0)
-        constexpr uint32_t XB = elem_bytes<XT>();
-        const int64_t left = (int64_t)d - c * CH;
-        const int dl = left <= 0 ? 0 : (left >= CH ? (int)CH : (int)left);
-        const char* xb = static_cast<const char*>(x) + (r * d + (dl > 0 ? c * CH : 0)) * XB;
-        const rsrc_t rx = make_rsrc(xb, (uint32_t)dl * XB);
-        bload_row_t<M, P, VEC, XT>(v, rx, 0u, dl, t, dl > 0);
-        float bq[EPL];
-        bload_coal<M, P>(bq, make_rsrc(Bv + c * CH, (uint32_t)(CH * 4)), 0u, t);
-#pragma unroll
-        for (int k = 0; k < EPL; ++k)
-            v[k] *= bq[k];
+    if constexpr (IN == kInRow) {
+        bload_row<M, P, VEC>(v, make_rsrc(a.src + r * n + c * CH, (uint32_t)(CH * 4)), 0u, (int)CH, t, true);
     } else {
-        // G_i src[perm[i]] for the chunk's i (gather within row r of src)
-        const rsrc_t rs = make_rsrc(src + r * n, (uint32_t)(n * 4));
-        const rsrc_t rp = make_rsrc(perm + c * CH, (uint32_t)(CH * 4));
-        const rsrc_t rg = make_rsrc(Gv + c * CH, (uint32_t)(CH * 4));
+        __shared__ int32_t spre[kMaxChunks + 1], sdel[kMaxChunks];
+        const int C = (int)a.chunks;
+        for (int i = (int)t; i <= C; i += BLOCK) {
+            spre[i] = a.bpre[c * (C + 1) + i];
+            if (i < C)
+                sdel[i] = a.bdelta[c * C + i];
+        }
         float gq[EPL];
-        uint32_t pq[EPL];
-        bload_coal<M, P>(gq, rg, 0u, t);
+        bload_coal<M, P>(gq, make_rsrc(a.G + c * CH, (uint32_t)(CH * 4)), 0u, t);
+        __syncthreads();
+        // the p-th received element (p = j BLOCK + t) is in group ci, the
+        // last with spre[ci] <= p
+        uint32_t at[EPL];
+        int lo = 0;
 #pragma unroll
-        for (int j = 0; j < EPL / 4; ++j)
-            bload4u(&pq[4 * j], rp, 4u * tb, 4u * rpart(M, P, 0, 4 * j));
+        for (int j = 0; j < EPL; ++j) {
+            const int p = j * BLOCK + (int)t;
+            int hi = C;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (spre[mid] <= p)
+                    lo = mid;
+                else
+                    hi = mid;
+            }
+            at[j] = (uint32_t)(p + sdel[lo]);
+        }
+        const rsrc_t rs = make_rsrc(a.src + r * n, (uint32_t)(n * 4));
+        const rsrc_t rd = make_rsrc(a.dstB, (uint32_t)(n * 2));
+        float val[EPL];
+        uint32_t di[EPL];
+#pragma unroll
+        for (int j = 0; j < EPL; ++j) {
+            val[j] = bload1(rs, 4u * at[j], 0u);
+            di[j] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(rd, (int)(2u * at[j]), 0, 0);
+        }
+#pragma unroll
+        for (int j = 0; j < EPL; ++j)
+            lds[phys<P>(di[j] & (uint32_t)(CH - 1))] = val[j];
+        __syncthreads();
+        lds_get<M, P, 0>(lds, t, v);
+        __syncthreads();
 #pragma unroll
         for (int k = 0; k < EPL; ++k)
-            v[k] = gq[k] * bload1(rs, 4u * (pq[k] & (uint32_t)(n - 1)), 0u);
+            v[k] *= gq[k];
     }
-    fwht_up<M, P>(v, lds, t);
-    relayout<M, P, K, 0>(v, lds, t);
-    if constexpr (VEC || MODE != kInPlace) {
+    if constexpr (OUT == kOutBucket) {
+        // prefetch this chunk's srcA (4 offsets per 8-byte load)
+        constexpr int NQ = EPL / 4;
+        const rsrc_t ra = make_rsrc(a.srcA + c * CH, (uint32_t)(CH * 2));
+        u32x2_t sa[NQ];
 #pragma unroll
-        for (int j = 0; j < EPL / 4; ++j)
-            bstore4(ro, 4u * (tb | rpart(M, P, 0, 4 * j)), v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]);
+        for (int j = 0; j < NQ; ++j)
+            sa[j] = __builtin_bit_cast(u32x2_t, __builtin_amdgcn_raw_buffer_load_b64(
+                                                    ra, (int)(8u * (j * BLOCK + t)), 0, 0));
+        fwht_up<M, P>(v, lds, t);
+        lds_put<M, P, K>(lds, t, v);
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < NQ; ++j) {
+            const uint32_t s0 = sa[j].x & 0xffffu, s1 = sa[j].x >> 16, s2 = sa[j].y & 0xffffu, s3 = sa[j].y >> 16;
+            bstore4(ro, 16u * (j * BLOCK + t), lds[phys<P>(s0)], lds[phys<P>(s1)], lds[phys<P>(s2)],
+                    lds[phys<P>(s3)]);
+        }
     } else {
+        fwht_up<M, P>(v, lds, t);
+        relayout<M, P, K, 0>(v, lds, t);
+        if constexpr (VEC || IN != kInRow) {
 #pragma unroll
-        for (int k = 0; k < EPL; ++k)
-            bstore1(ro, 4u * tb, 4u * rpart(M, P, 0, k), v[k]);
+            for (int j = 0; j < EPL / 4; ++j)
+                bstore4(ro, 4u * (tb | rpart(M, P, 0, 4 * j)), v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < EPL; ++k)
+                bstore1(ro, 4u * tb, 4u * rpart(M, P, 0, k), v[k]);
+        }
     }
 }
 
@@ -180,6 +240,87 @@ __global__ void __launch_bounds__(kColThreads)
     }
 }
 
+// The first column pass of an expansion: the same butterflies on
+// B o xhat, read from x (rows of d elements of type XT; past d reads zero
+// through the range check) and written to out (rows of n floats).
+template <int B, int XT, bool VEC>
+__global__ void __launch_bounds__(kColThreads)
+    k_cols_x(float* __restrict__ out, const void* __restrict__ x, int d, const float* __restrict__ Bv, int64_t rows,
+             int64_t n, int s, int64_t blocks_per_row)
+{
+    constexpr int L = 1 << B;
+    constexpr uint32_t XB = elem_bytes<XT>();
+    const int64_t r = (int64_t)blockIdx.x / blocks_per_row;
+    const int64_t q = ((int64_t)blockIdx.x % blocks_per_row) * kColThreads + threadIdx.x;
+    const int64_t lo_groups = (int64_t)1 << (s - 2);
+    if (r >= rows || q >= (n >> B) / 4)
+        return;
+    const int64_t hi = q / lo_groups, lo = (q % lo_groups) * 4;
+    const int64_t base = hi * ((int64_t)L << s) + lo;
+    const rsrc_t rx = make_rsrc(static_cast<const char*>(x) + r * d * XB, (uint32_t)d * XB);
+    const rsrc_t rb = make_rsrc(Bv, (uint32_t)(n * 4));
+    const rsrc_t ro = make_rsrc(out + r * n, (uint32_t)(n * 4));
+    float v[L][4];
+#pragma unroll
+    for (int k = 0; k < L; ++k) {
+        const uint32_t i = (uint32_t)(base + ((int64_t)k << s));
+        float bq[4];
+        bload4(bq, rb, 4u * i, 0u);
+        if constexpr (VEC && XT == kF32) {
+            bload4<2>(v[k], rx, 4u * i, 0u);
+        } else if constexpr (VEC) {
+            const u32x2_t h = __builtin_bit_cast(u32x2_t, __builtin_amdgcn_raw_buffer_load_b64(rx, (int)(2u * i), 0, 2));
+            unpack2<XT>(h.x, v[k][0], v[k][1]);
+            unpack2<XT>(h.y, v[k][2], v[k][3]);
+        } else {
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                if constexpr (XT == kF32)
+                    v[k][m] = bload1<2>(rx, 4u * (i + m), 0u);
+                else
+                    v[k][m] = widen1<XT>((uint32_t)__builtin_amdgcn_raw_buffer_load_b16(rx, (int)(2u * (i + m)), 0, 2));
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            v[k][m] *= bq[m];
+    }
+#pragma unroll
+    for (int h = 1; h < L; h <<= 1)
+#pragma unroll
+        for (int k = 0; k < L; ++k)
+            if ((k & h) == 0)
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const float a = v[k][m], b = v[k | h][m];
+                    v[k][m] = a + b;
+                    v[k | h][m] = a - b;
+                }
+#pragma unroll
+    for (int k = 0; k < L; ++k)
+        bstore4(ro, (uint32_t)((base + ((int64_t)k << s)) * 4), v[k][0], v[k][1], v[k][2], v[k][3]);
+}
+
+template <int XT, bool VEC>
+hipError_t col_pass_x(int B, float* out, const void* x, int d, const float* Bv, int64_t rows, int64_t n, int s,
+                      hipStream_t st)
+{
+    const int64_t groups = (n >> B) / 4;
+    const int64_t bpr = (groups + kColThreads - 1) / kColThreads;
+    const dim3 grid((unsigned)(rows * bpr)), blk(kColThreads);
+#define MCK_COLX_ARGS out, x, d, Bv, rows, n, s, bpr
+    switch (B) {
+    case 1: k_cols_x<1, XT, VEC><<<grid, blk, 0, st>>>(MCK_COLX_ARGS); break;
+    case 2: k_cols_x<2, XT, VEC><<<grid, blk, 0, st>>>(MCK_COLX_ARGS); break;
+    case 3: k_cols_x<3, XT, VEC><<<grid, blk, 0, st>>>(MCK_COLX_ARGS); break;
+    case 4: k_cols_x<4, XT, VEC><<<grid, blk, 0, st>>>(MCK_COLX_ARGS); break;
+    case 5: k_cols_x<5, XT, VEC><<<grid, blk, 0, st>>>(MCK_COLX_ARGS); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef MCK_COLX_ARGS
+    return hipGetLastError();
+}
+
 template <bool EPI, int YT>
 hipError_t col_pass(int B, float* data, int64_t rows, int64_t n, int s, const float* Sh, float cs, int e, int E,
                     void* phi, hipStream_t st)
@@ -201,59 +342,156 @@ hipError_t col_pass(int B, float* data, int64_t rows, int64_t n, int s, const fl
 }
 
 // Column passes over bits [15, M): the first takes the bits beyond a
-// multiple of 5, each later one 5 bits; the last may carry the epilogue.
-template <int YT>
-hipError_t col_passes(int M, float* data, int64_t rows, bool epi, const float* Sh, float cs, int e, int E,
-                      void* phi, hipStream_t st)
+// multiple of 5, each later one 5 bits.  With x the first pass reads B o
+// xhat from x; with epi the last one carries the feature epilogue.
+template <int XT, bool VEC, int YT>
+hipError_t col_passes(int M, float* data, int64_t rows, const void* x, int d, const float* Bv, bool epi,
+                      const float* Sh, float cs, int e, int E, void* phi, hipStream_t st)
 {
     const int64_t n = int64_t(1) << M;
     int s = kRowM;
     int rem = M - kRowM;
+    bool first = true;
     while (rem > 0) {
         const int B = rem % kColMaxB == 0 ? kColMaxB : rem % kColMaxB;
         const bool last = rem == B;
-        hipError_t err = (epi && last) ? col_pass<true, YT>(B, data, rows, n, s, Sh, cs, e, E, phi, st)
-                                       : col_pass<false, kF32>(B, data, rows, n, s, nullptr, 0.f, 0, 0, nullptr, st);
+        hipError_t err;
+        if (first && x != nullptr)
+            err = col_pass_x<XT, VEC>(B, data, x, d, Bv, rows, n, s, st);
+        else if (epi && last)
+            err = col_pass<true, YT>(B, data, rows, n, s, Sh, cs, e, E, phi, st);
+        else
+            err = col_pass<false, kF32>(B, data, rows, n, s, nullptr, 0.f, 0, 0, nullptr, st);
         if (err != hipSuccess)
             return err;
+        first = false;
         s += B;
         rem -= B;
     }
     return hipSuccess;
 }
 
-template <int MODE, int XT>
-hipError_t row_pass(bool vec, float* dst, const float* src, int64_t rows, int64_t chunks, const void* x, int d,
-                    const float* Bv, const int32_t* perm, const float* Gv, hipStream_t st)
+template <int IN, int OUT>
+hipError_t row_pass(bool vec, const RowArgs& a, hipStream_t st)
 {
-    const int64_t blocks = ((rows + kXcds - 1) / kXcds) * kXcds * chunks;
+    const int64_t blocks = ((a.rows + kXcds - 1) / kXcds) * kXcds * a.chunks;
     const dim3 grid((unsigned)blocks), blk(RG::BLOCK);
     if (vec)
-        k_rows<MODE, true, XT><<<grid, blk, 0, st>>>(dst, src, rows, chunks, x, d, Bv, perm, Gv);
+        k_rows<IN, OUT, true><<<grid, blk, 0, st>>>(a);
     else
-        k_rows<MODE, false, XT><<<grid, blk, 0, st>>>(dst, src, rows, chunks, x, d, Bv, perm, Gv);
+        k_rows<IN, OUT, false><<<grid, blk, 0, st>>>(a);
     return hipGetLastError();
 }
 
 template <int XT, int YT>
 hipError_t forward_long(int M, bool vec, const void* x, int64_t batch, int d, int64_t E, const float* B,
-                        const int32_t* perm, const float* G, const float* Sh, float cs, void* phi, float* u,
-                        float* w, hipStream_t st)
+                        const uint16_t* srcA, const uint16_t* dstB, const int32_t* bpre, const int32_t* bdelta,
+                        const float* G, const float* Sh, float cs, void* phi, float* u, float* w, hipStream_t st)
 {
-    const int64_t n = int64_t(1) << M, chunks = n >> kRowM;
+    const int64_t n = int64_t(1) << M, C = n >> kRowM;
     for (int64_t e = 0; e < E; ++e) {
-        hipError_t err = row_pass<kInX, XT>(vec, u, nullptr, batch, chunks, x, d, B + e * n, nullptr, nullptr, st);
+        hipError_t err = vec ? col_passes<XT, true, kF32>(M, u, batch, x, d, B + e * n, false, nullptr, 0.f, 0, 0,
+                                                          nullptr, st)
+                             : col_passes<XT, false, kF32>(M, u, batch, x, d, B + e * n, false, nullptr, 0.f, 0, 0,
+                                                           nullptr, st);
+        RowArgs a{w, u, batch, C, nullptr, srcA + e * n, nullptr, nullptr, nullptr};
         if (err == hipSuccess)
-            err = col_passes<kF32>(M, u, batch, false, nullptr, 0.f, 0, 0, nullptr, st);
+            err = row_pass<kInRow, kOutBucket>(true, a, st);
+        RowArgs b{u, w, batch, C, G + e * n, nullptr, dstB + e * n, bpre + e * C * (C + 1), bdelta + e * C * C};
         if (err == hipSuccess)
-            err = row_pass<kInGather, kF32>(true, w, u, batch, chunks, nullptr, 0, nullptr, perm + e * n,
-                                             G + e * n, st);
+            err = row_pass<kInBucket, kOutRow>(true, b, st);
         if (err == hipSuccess)
-            err = col_passes<YT>(M, w, batch, true, Sh + e * n, cs, (int)e, (int)E, phi, st);
+            err = col_passes<kF32, true, YT>(M, u, batch, nullptr, 0, nullptr, true, Sh + e * n, cs, (int)e,
+                                             (int)E, phi, st);
         if (err != hipSuccess)
             return err;
     }
     return hipSuccess;
+}
+
+// Bucket construction (once per plan).  counts[e][ci][co]: elements that
+// destination chunk co takes from source chunk ci.
+__global__ void __launch_bounds__(1024)
+    k_bucket_count(const int32_t* __restrict__ perm, int64_t n, int C, int32_t* __restrict__ counts)
+{
+    __shared__ int32_t h[kMaxChunks];
+    const int64_t e = blockIdx.x / C;
+    const int co = (int)(blockIdx.x % C);
+    for (int i = threadIdx.x; i < C; i += blockDim.x)
+        h[i] = 0;
+    __syncthreads();
+    const int32_t* pc = perm + e * n + (int64_t)co * RG::n;
+    for (int j = threadIdx.x; j < RG::n; j += blockDim.x)
+        atomicAdd(&h[(pc[j] & (int32_t)(n - 1)) >> kRowM], 1);
+    __syncthreads();
+    for (int ci = threadIdx.x; ci < C; ci += blockDim.x)
+        counts[(e * C + ci) * C + co] = h[ci];
+}
+
+// seg[e][ci][co]: start of group (ci, co) within source chunk ci (one
+// thread per (e, ci)).
+__global__ void k_bucket_seg(const int32_t* __restrict__ counts, int64_t E, int C, int32_t* __restrict__ seg)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // e C + ci
+    if (g >= E * C)
+        return;
+    int32_t acc = 0;
+    for (int co = 0; co < C; ++co) {
+        seg[g * (C + 1) + co] = acc;
+        acc += counts[g * C + co];
+    }
+    seg[g * (C + 1) + C] = acc;
+}
+
+// bpre and bdelta (one thread per (e, co)).
+__global__ void k_bucket_pre(const int32_t* __restrict__ counts, const int32_t* __restrict__ seg, int64_t E, int C,
+                             int32_t* __restrict__ bpre, int32_t* __restrict__ bdelta)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // e C + co
+    if (g >= E * C)
+        return;
+    const int64_t e = g / C;
+    const int co = (int)(g % C);
+    int32_t acc = 0;
+    for (int ci = 0; ci < C; ++ci) {
+        const int64_t src = e * C + ci;
+        bpre[g * (C + 1) + ci] = acc;
+        bdelta[g * C + ci] = ci * RG::n + seg[src * (C + 1) + co] - acc;
+        acc += counts[src * C + co];
+    }
+    bpre[g * (C + 1) + C] = acc;
+}
+
+// srcA / dstB: thread ci of block (e, co) walks destination chunk co in
+// order and appends the elements whose source is in chunk ci to group
+// (ci, co).
+__global__ void __launch_bounds__(512)
+    k_bucket_fill(const int32_t* __restrict__ perm, int64_t n, int C, const int32_t* __restrict__ seg,
+                  uint16_t* __restrict__ srcA, uint16_t* __restrict__ dstB)
+{
+    constexpr int TILE = 1024;
+    __shared__ int32_t tile[TILE];
+    const int64_t e = blockIdx.x / C;
+    const int co = (int)(blockIdx.x % C);
+    const int ci = threadIdx.x;
+    const int32_t* pc = perm + e * n + (int64_t)co * RG::n;
+    int64_t pos = ci < C ? e * n + (int64_t)ci * RG::n + seg[(e * C + ci) * (C + 1) + co] : 0;
+    for (int base = 0; base < RG::n; base += TILE) {
+        __syncthreads();
+        for (int j = threadIdx.x; j < TILE; j += blockDim.x)
+            tile[j] = pc[base + j] & (int32_t)(n - 1);
+        __syncthreads();
+        if (ci < C) {
+            for (int j = 0; j < TILE; ++j) {
+                const int32_t src = tile[j];
+                if ((src >> kRowM) == ci) {
+                    srcA[pos] = (uint16_t)(src & (RG::n - 1));
+                    dstB[pos] = (uint16_t)(base + j);
+                    ++pos;
+                }
+            }
+        }
+    }
 }
 
 }  // namespace
@@ -268,21 +506,22 @@ hipError_t launch_fwht_long(int M, float* data, int64_t batch, bool vec, hipStre
 {
     if (M <= kRowM || M > 24)
         return hipErrorInvalidValue;
-    const int64_t n = int64_t(1) << M, chunks = n >> kRowM;
-    hipError_t err = row_pass<kInPlace, kF32>(vec, data, nullptr, batch, chunks, nullptr, 0, nullptr, nullptr,
-                                              nullptr, s);
+    const int64_t n = int64_t(1) << M;
+    RowArgs a{data, data, batch, n >> kRowM, nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipError_t err = row_pass<kInRow, kOutRow>(vec, a, s);
     if (err != hipSuccess)
         return err;
-    return col_passes<kF32>(M, data, batch, false, nullptr, 0.f, 0, 0, nullptr, s);
+    return col_passes<kF32, true, kF32>(M, data, batch, nullptr, 0, nullptr, false, nullptr, 0.f, 0, 0, nullptr, s);
 }
 
 hipError_t launch_forward_long(int M, bool vec, int xt, int yt, const void* x, int64_t batch, int d, int64_t E,
-                               const float* B, const int32_t* perm, const float* G, const float* Sh, float cs,
-                               void* phi, float* u, float* w, hipStream_t s)
+                               const float* B, const uint16_t* srcA, const uint16_t* dstB, const int32_t* bpre,
+                               const int32_t* bdelta, const float* G, const float* Sh, float cs, void* phi, float* u,
+                               float* w, hipStream_t s)
 {
     if (M <= kRowM || M > 24)
         return hipErrorInvalidValue;
-#define MCK_FL_ARGS M, vec, x, batch, d, E, B, perm, G, Sh, cs, phi, u, w, s
+#define MCK_FL_ARGS M, vec, x, batch, d, E, B, srcA, dstB, bpre, bdelta, G, Sh, cs, phi, u, w, s
     if (xt == kF32 && yt == kF32)
         return forward_long<kF32, kF32>(MCK_FL_ARGS);
     if (xt == kF32 && yt == kBF16)
@@ -295,6 +534,25 @@ hipError_t launch_forward_long(int M, bool vec, int xt, int yt, const void* x, i
         return forward_long<kF16, kF16>(MCK_FL_ARGS);
 #undef MCK_FL_ARGS
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_buckets(int M, int64_t E, const int32_t* perm, uint16_t* srcA, uint16_t* dstB, int32_t* bpre,
+                          int32_t* bdelta, int32_t* scratch, hipStream_t s)
+{
+    if (M <= kRowM || M > 24)
+        return hipErrorInvalidValue;
+    const int64_t n = int64_t(1) << M;
+    const int C = (int)(n >> kRowM);
+    int32_t* counts = scratch;
+    int32_t* seg = scratch + E * C * C;
+    const unsigned blocks = (unsigned)(E * C);
+    k_bucket_count<<<dim3(blocks), dim3(1024), 0, s>>>(perm, n, C, counts);
+    const unsigned tb = (unsigned)((E * C + 255) / 256);
+    k_bucket_seg<<<dim3(tb), dim3(256), 0, s>>>(counts, E, C, seg);
+    k_bucket_pre<<<dim3(tb), dim3(256), 0, s>>>(counts, seg, E, C, bpre, bdelta);
+    const int threads = C < 64 ? 64 : C;
+    k_bucket_fill<<<dim3(blocks), dim3((unsigned)threads), 0, s>>>(perm, n, C, seg, srcA, dstB);
+    return hipGetLastError();
 }
 
 }  // namespace mck

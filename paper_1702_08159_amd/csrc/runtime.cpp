@@ -132,6 +132,13 @@ struct Plan {
     uint32_t* goffB = nullptr;  // backward gather offsets
     float* GkB = nullptr;       // G in destination order, backward layout
     float* Sh = nullptr;        // S / (2 pi)
+    // n > MCK_MAX_N: Pi as buckets between 2^15-element source and
+    // destination chunks (C = n / 2^15 of each, layout in launch.hpp)
+    uint16_t* srcA = nullptr;
+    uint16_t* dstB = nullptr;
+    int32_t* bpre = nullptr;
+    int32_t* bdelta = nullptr;
+    int32_t* bscratch = nullptr;  // build scratch: segment starts and counts
 };
 
 std::mutex g_mutex;
@@ -182,10 +189,13 @@ mck_status get_plan(uint32_t seed, int64_t n, int64_t E, double sigma, int calib
     const size_t en = (size_t)(n * E);
     int64_t gf = 0, gb = 0;
     mck::plan_elems(log2i(n), &gf, &gb);
-    size_t off[11], total = 0;
-    const size_t sz[11] = {en * 4, en * 4, en * 4, en * 8, en * 4, (size_t)E * 8,
-                           (size_t)gf * E * 4, en * 4, (size_t)gb * E * 4, en * 4, en * 4};
-    for (int i = 0; i < 11; ++i) {
+    const size_t C = n > MCK_MAX_N ? (size_t)(n / MCK_MAX_N) : 0;
+    const size_t ec1 = (size_t)E * C * (C + 1) * 4, ecc = (size_t)E * C * C * 4;
+    size_t off[16], total = 0;
+    const size_t sz[16] = {en * 4, en * 4, en * 4, en * 8, en * 4, (size_t)E * 8,
+                           (size_t)gf * E * 4, en * 4, (size_t)gb * E * 4, en * 4, en * 4,
+                           C ? en * 2 : 0, C ? en * 2 : 0, ec1, ecc, ec1 + ecc};
+    for (int i = 0; i < 16; ++i) {
         off[i] = total;
         total += align_up(sz[i]);
     }
@@ -219,6 +229,13 @@ mck_status get_plan(uint32_t seed, int64_t n, int64_t E, double sigma, int calib
     p.goffB = reinterpret_cast<uint32_t*>(b + off[8]);
     p.GkB = reinterpret_cast<float*>(b + off[9]);
     p.Sh = reinterpret_cast<float*>(b + off[10]);
+    if (C) {
+        p.srcA = reinterpret_cast<uint16_t*>(b + off[11]);
+        p.dstB = reinterpret_cast<uint16_t*>(b + off[12]);
+        p.bpre = reinterpret_cast<int32_t*>(b + off[13]);
+        p.bdelta = reinterpret_cast<int32_t*>(b + off[14]);
+        p.bscratch = reinterpret_cast<int32_t*>(b + off[15]);
+    }
     int matern_t = 0;
     {
         const mck_status cst = check_calib(calib, n, &matern_t);
@@ -232,6 +249,8 @@ mck_status get_plan(uint32_t seed, int64_t n, int64_t E, double sigma, int calib
         err = n > MCK_MAX_N ? mck::launch_sh(p.S64, p.Sh, n * E, stream)
                             : mck::launch_derive(log2i(n), E, p.perm, p.G, p.S64, p.S32, p.goffF, p.GsF, p.goffB,
                                                  p.GkB, p.Sh, stream);
+    if (err == hipSuccess && n > MCK_MAX_N)
+        err = mck::launch_buckets(log2i(n), E, p.perm, p.srcA, p.dstB, p.bpre, p.bdelta, p.bscratch, stream);
     if (err == hipSuccess)
         err = hipStreamSynchronize(stream);  // the plan may be used from other streams next
     if (err != hipSuccess) {
@@ -432,7 +451,7 @@ static mck_status forward_long(const Plan* p, const void* x, int xt, int64_t bat
     for (int64_t r0 = 0; r0 < batch && err == hipSuccess; r0 += rows_per) {
         const int64_t rows = batch - r0 < rows_per ? batch - r0 : rows_per;
         err = mck::launch_forward_long(log2i(n), vec, xt, yt, static_cast<const char*>(x) + r0 * d * xb, rows,
-                                       (int)d, E, p->B, p->perm, p->G, p->Sh, cs,
+                                       (int)d, E, p->B, p->srcA, p->dstB, p->bpre, p->bdelta, p->G, p->Sh, cs,
                                        static_cast<char*>(phi) + r0 * row_phi, u, w, s);
     }
     (void)hipFreeAsync(u, s);
