@@ -46,26 +46,23 @@ hipError_t launch_forward_t(int M, bool vec, int xt, int yt, const void* x, int6
 // plans comes from launch_sh (S / 2 pi from the FP64 S).
 hipError_t launch_fwht_long(int M, float* data, int64_t batch, bool vec, hipStream_t s);
 hipError_t launch_forward_long(int M, bool vec, int xt, int yt, const void* x, int64_t batch, int d, int64_t E,
-                               const float* B, const uint16_t* srcA, const uint16_t* dstB, const int32_t* bpre,
-                               const int32_t* bdelta, const float* G, const float* Sh, float cs, void* phi, float* u,
-                               float* w, hipStream_t s);
-// Pi (destination i takes source perm[i]) of each expansion as buckets
-// between the C = n / 2^15 source chunks and C destination chunks of 2^15
-// elements.  Per expansion (arrays of expansion e start at e n, e C (C + 1)
-// and e C C):
-//   srcA, dstB [ci 2^15 + q]: chunk-local source and destination offsets of
-//       the q-th element leaving source chunk ci; the elements of one source
-//       chunk are grouped by destination chunk, ascending destination within
-//       a group;
-//   bpre [co (C + 1) + ci]: how many elements destination chunk co receives
-//       from source chunks below ci (bpre[co][C] = 2^15);
-//   bdelta [co C + ci]: position of group (ci, co) in srcA / dstB minus
-//       bpre[co][ci], so the p-th element that destination chunk co receives
-//       sits at p + bdelta[co][ci] for the ci with bpre[co][ci] <= p <
-//       bpre[co][ci + 1].
-// scratch: E C (2C + 1) ints.
-hipError_t launch_buckets(int M, int64_t E, const int32_t* perm, uint16_t* srcA, uint16_t* dstB, int32_t* bpre,
-                          int32_t* bdelta, int32_t* scratch, hipStream_t s);
+                               const float* B, const uint32_t* packA, const uint16_t* dstB, const int32_t* pdelta,
+                               const float* G, const float* Sh, float cs, void* phi, float* u, float* w,
+                               hipStream_t s);
+// Pi (destination i takes source perm[i]) of each expansion as an exchange
+// between the C = n / 2^15 chunks of 2^15 elements.  The exchange buffer T
+// holds, for each destination chunk co, the elements it receives, grouped
+// by source chunk ci (ascending), ascending destination within a group.
+// Per expansion (arrays of expansion e start at e n and e C C):
+//   packA [ci 2^15 + q] = co << 15 | s: the q-th element leaving source
+//       chunk ci (grouped by co, the same order within a group) is its
+//       element s and goes to destination chunk co;
+//   pdelta [ci C + co]: its position in T is q + pdelta[ci][co];
+//   dstB [co 2^15 + p]: T position co 2^15 + p lands at element dstB of
+//       destination chunk co.
+// scratch: E C (3C + 2) ints.
+hipError_t launch_buckets(int M, int64_t E, const int32_t* perm, uint32_t* packA, uint16_t* dstB, int32_t* pdelta,
+                          int32_t* scratch, hipStream_t s);
 hipError_t launch_sh(const double* S64, float* Sh, int64_t count, hipStream_t s);
 
 // Grouped forward (FP32 x and phi, n = 2^M <= 2^15): several feature maps

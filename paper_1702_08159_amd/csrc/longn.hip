@@ -13,12 +13,11 @@
 // The feature map per expansion is four passes over two FP32 scratch copies
 // u, w of the batch:
 //   1. column pass(es) on B o xhat (x read in place, zero padding by range)
-//   2. row pass -> u = H B xhat, held in LDS; Pi is applied as a bucket
-//      exchange between chunks: the chunk's elements go out to w grouped by
-//      the destination chunk that gathers them (srcA order, coalesced)
-//   3. row pass: each destination chunk reads its C groups from w
-//      (contiguous runs), places them by dstB in LDS, multiplies by G and
-//      transforms -> u
+//   2. row pass -> u = H B xhat, held in LDS; Pi is applied as an exchange
+//      between chunks: each element goes out to w at the place its
+//      destination chunk will read it (runs of consecutive positions)
+//   3. row pass: each destination chunk reads its contiguous part of w,
+//      places the values by dstB in LDS, multiplies by G and transforms -> u
 //   4. column pass(es); the last one multiplies by S / (2 pi) and writes
 //      c cos, c sin in the storage type of phi.
 // A direct gather u[perm[i]] over the whole row would read one 4-byte value
@@ -52,10 +51,9 @@ struct RowArgs {
     const float* src;
     int64_t rows, chunks;
     const float* G;          // kInBucket: G of the expansion
-    const uint16_t* srcA;    // kOutBucket
+    const uint32_t* packA;   // kOutBucket
+    const int32_t* pdelta;   // kOutBucket
     const uint16_t* dstB;    // kInBucket
-    const int32_t* bpre;     // kInBucket
-    const int32_t* bdelta;   // kInBucket
 };
 
 // XCD-aware (row, chunk) of a row-pass block: blocks are dealt to the 8 XCDs
@@ -72,14 +70,14 @@ __device__ __forceinline__ void row_chunk(int64_t rows, int64_t chunks, int64_t&
 // One 2^15 chunk per block: H_{2^15} of the chunk's input, output to dst
 // (rows of length n = chunks 2^15).
 //   kInRow:    the chunk of src (natural order)
-//   kInBucket: G o (the elements Pi sends to this chunk), gathered from the
-//              bucket-ordered src
+//   kInBucket: G o (the elements Pi sends to this chunk), read from the
+//              chunk's part of the exchange buffer src
 //   kOutRow:    natural order
-//   kOutBucket: bucket order of this source chunk (srcA)
+//   kOutBucket: every element to its place in the exchange buffer dst
 template <int IN, int OUT, bool VEC>
 __global__ void __launch_bounds__(RG::BLOCK) k_rows(RowArgs a)
 {
-    constexpr int M = kRowM, P = kRowP, EPL = RG::EPL, K = RG::K, BLOCK = RG::BLOCK;
+    constexpr int M = kRowM, P = kRowP, EPL = RG::EPL, K = RG::K, BLOCK = RG::BLOCK, NQ = EPL / 4;
     constexpr int64_t CH = RG::n;
     __shared__ float lds[RG::LDS_FLOATS];
     int64_t r, c;
@@ -89,50 +87,29 @@ __global__ void __launch_bounds__(RG::BLOCK) k_rows(RowArgs a)
     const int64_t n = a.chunks * CH;
     const uint32_t t = threadIdx.x;
     const uint32_t tb = tpart<M, P, 0>(t);
-    const rsrc_t ro = make_rsrc(a.dst + r * n + c * CH, (uint32_t)(CH * 4));
     float v[EPL];
     if constexpr (IN == kInRow) {
         bload_row<M, P, VEC>(v, make_rsrc(a.src + r * n + c * CH, (uint32_t)(CH * 4)), 0u, (int)CH, t, true);
     } else {
-        __shared__ int32_t spre[kMaxChunks + 1], sdel[kMaxChunks];
-        const int C = (int)a.chunks;
-        for (int i = (int)t; i <= C; i += BLOCK) {
-            spre[i] = a.bpre[c * (C + 1) + i];
-            if (i < C)
-                sdel[i] = a.bdelta[c * C + i];
+        // lane t holds exchange positions 4 (j BLOCK + t) + {0..3}
+        const rsrc_t rs = make_rsrc(a.src + r * n + c * CH, (uint32_t)(CH * 4));
+        const rsrc_t rd = make_rsrc(a.dstB + c * CH, (uint32_t)(CH * 2));
+        float val[NQ][4];
+        u32x2_t di[NQ];
+#pragma unroll
+        for (int j = 0; j < NQ; ++j) {
+            bload4(val[j], rs, 16u * (j * BLOCK + t), 0u);
+            di[j] = __builtin_bit_cast(u32x2_t, __builtin_amdgcn_raw_buffer_load_b64(rd, (int)(8u * (j * BLOCK + t)), 0, 0));
         }
         float gq[EPL];
         bload_coal<M, P>(gq, make_rsrc(a.G + c * CH, (uint32_t)(CH * 4)), 0u, t);
-        __syncthreads();
-        // the p-th received element (p = j BLOCK + t) is in group ci, the
-        // last with spre[ci] <= p
-        uint32_t at[EPL];
-        int lo = 0;
 #pragma unroll
-        for (int j = 0; j < EPL; ++j) {
-            const int p = j * BLOCK + (int)t;
-            int hi = C;
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (spre[mid] <= p)
-                    lo = mid;
-                else
-                    hi = mid;
-            }
-            at[j] = (uint32_t)(p + sdel[lo]);
+        for (int j = 0; j < NQ; ++j) {
+            lds[phys<P>(di[j].x & 0x7fffu)] = val[j][0];
+            lds[phys<P>((di[j].x >> 16) & 0x7fffu)] = val[j][1];
+            lds[phys<P>(di[j].y & 0x7fffu)] = val[j][2];
+            lds[phys<P>((di[j].y >> 16) & 0x7fffu)] = val[j][3];
         }
-        const rsrc_t rs = make_rsrc(a.src + r * n, (uint32_t)(n * 4));
-        const rsrc_t rd = make_rsrc(a.dstB, (uint32_t)(n * 2));
-        float val[EPL];
-        uint32_t di[EPL];
-#pragma unroll
-        for (int j = 0; j < EPL; ++j) {
-            val[j] = bload1(rs, 4u * at[j], 0u);
-            di[j] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(rd, (int)(2u * at[j]), 0, 0);
-        }
-#pragma unroll
-        for (int j = 0; j < EPL; ++j)
-            lds[phys<P>(di[j] & (uint32_t)(CH - 1))] = val[j];
         __syncthreads();
         lds_get<M, P, 0>(lds, t, v);
         __syncthreads();
@@ -141,24 +118,31 @@ __global__ void __launch_bounds__(RG::BLOCK) k_rows(RowArgs a)
             v[k] *= gq[k];
     }
     if constexpr (OUT == kOutBucket) {
-        // prefetch this chunk's srcA (4 offsets per 8-byte load)
-        constexpr int NQ = EPL / 4;
-        const rsrc_t ra = make_rsrc(a.srcA + c * CH, (uint32_t)(CH * 2));
-        u32x2_t sa[NQ];
+        // lane t sends source-order positions q = 4 (j BLOCK + t) + {0..3}
+        __shared__ int32_t sdel[kMaxChunks];
+        const int C = (int)a.chunks;
+        for (int i = (int)t; i < C; i += BLOCK)
+            sdel[i] = a.pdelta[c * C + i];
+        const rsrc_t ra = make_rsrc(a.packA + c * CH, (uint32_t)(CH * 4));
+        uint32_t pk[NQ][4];
 #pragma unroll
         for (int j = 0; j < NQ; ++j)
-            sa[j] = __builtin_bit_cast(u32x2_t, __builtin_amdgcn_raw_buffer_load_b64(
-                                                    ra, (int)(8u * (j * BLOCK + t)), 0, 0));
+            bload4u(pk[j], ra, 16u * (j * BLOCK + t), 0u);
         fwht_up<M, P>(v, lds, t);
         lds_put<M, P, K>(lds, t, v);
         __syncthreads();
+        const rsrc_t ro = make_rsrc(a.dst + r * n, (uint32_t)(n * 4));
 #pragma unroll
-        for (int j = 0; j < NQ; ++j) {
-            const uint32_t s0 = sa[j].x & 0xffffu, s1 = sa[j].x >> 16, s2 = sa[j].y & 0xffffu, s3 = sa[j].y >> 16;
-            bstore4(ro, 16u * (j * BLOCK + t), lds[phys<P>(s0)], lds[phys<P>(s1)], lds[phys<P>(s2)],
-                    lds[phys<P>(s3)]);
-        }
+        for (int j = 0; j < NQ; ++j)
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const uint32_t q = 4u * (j * BLOCK + t) + m;
+                const uint32_t w = pk[j][m];
+                const int32_t pos = (int32_t)q + sdel[(w >> kRowM) & (kMaxChunks - 1)];
+                bstore1(ro, 4u * (uint32_t)pos, 0u, lds[phys<P>(w & 0x7fffu)]);
+            }
     } else {
+        const rsrc_t ro = make_rsrc(a.dst + r * n + c * CH, (uint32_t)(CH * 4));
         fwht_up<M, P>(v, lds, t);
         relayout<M, P, K, 0>(v, lds, t);
         if constexpr (VEC || IN != kInRow) {
@@ -385,8 +369,8 @@ hipError_t row_pass(bool vec, const RowArgs& a, hipStream_t st)
 
 template <int XT, int YT>
 hipError_t forward_long(int M, bool vec, const void* x, int64_t batch, int d, int64_t E, const float* B,
-                        const uint16_t* srcA, const uint16_t* dstB, const int32_t* bpre, const int32_t* bdelta,
-                        const float* G, const float* Sh, float cs, void* phi, float* u, float* w, hipStream_t st)
+                        const uint32_t* packA, const uint16_t* dstB, const int32_t* pdelta, const float* G,
+                        const float* Sh, float cs, void* phi, float* u, float* w, hipStream_t st)
 {
     const int64_t n = int64_t(1) << M, C = n >> kRowM;
     for (int64_t e = 0; e < E; ++e) {
@@ -394,10 +378,10 @@ hipError_t forward_long(int M, bool vec, const void* x, int64_t batch, int d, in
                                                           nullptr, st)
                              : col_passes<XT, false, kF32>(M, u, batch, x, d, B + e * n, false, nullptr, 0.f, 0, 0,
                                                            nullptr, st);
-        RowArgs a{w, u, batch, C, nullptr, srcA + e * n, nullptr, nullptr, nullptr};
+        const RowArgs a{w, u, batch, C, nullptr, packA + e * n, pdelta + e * C * C, nullptr};
         if (err == hipSuccess)
             err = row_pass<kInRow, kOutBucket>(true, a, st);
-        RowArgs b{u, w, batch, C, G + e * n, nullptr, dstB + e * n, bpre + e * C * (C + 1), bdelta + e * C * C};
+        const RowArgs b{u, w, batch, C, G + e * n, nullptr, nullptr, dstB + e * n};
         if (err == hipSuccess)
             err = row_pass<kInBucket, kOutRow>(true, b, st);
         if (err == hipSuccess)
@@ -409,7 +393,7 @@ hipError_t forward_long(int M, bool vec, const void* x, int64_t batch, int d, in
     return hipSuccess;
 }
 
-// Bucket construction (once per plan).  counts[e][ci][co]: elements that
+// Exchange construction (once per plan).  counts[e][ci][co]: elements that
 // destination chunk co takes from source chunk ci.
 __global__ void __launch_bounds__(1024)
     k_bucket_count(const int32_t* __restrict__ perm, int64_t n, int C, int32_t* __restrict__ counts)
@@ -428,8 +412,8 @@ __global__ void __launch_bounds__(1024)
         counts[(e * C + ci) * C + co] = h[ci];
 }
 
-// seg[e][ci][co]: start of group (ci, co) within source chunk ci (one
-// thread per (e, ci)).
+// seg[e][ci][co]: start of group (ci, co) among the elements leaving source
+// chunk ci (one thread per (e, ci)).
 __global__ void k_bucket_seg(const int32_t* __restrict__ counts, int64_t E, int C, int32_t* __restrict__ seg)
 {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // e C + ci
@@ -437,15 +421,15 @@ __global__ void k_bucket_seg(const int32_t* __restrict__ counts, int64_t E, int 
         return;
     int32_t acc = 0;
     for (int co = 0; co < C; ++co) {
-        seg[g * (C + 1) + co] = acc;
+        seg[g * C + co] = acc;
         acc += counts[g * C + co];
     }
-    seg[g * (C + 1) + C] = acc;
 }
 
-// bpre and bdelta (one thread per (e, co)).
+// pre[e][co][ci]: start of group (ci, co) among the elements destination
+// chunk co receives; pdelta from seg and pre (one thread per (e, co)).
 __global__ void k_bucket_pre(const int32_t* __restrict__ counts, const int32_t* __restrict__ seg, int64_t E, int C,
-                             int32_t* __restrict__ bpre, int32_t* __restrict__ bdelta)
+                             int32_t* __restrict__ pre, int32_t* __restrict__ pdelta)
 {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // e C + co
     if (g >= E * C)
@@ -455,19 +439,18 @@ __global__ void k_bucket_pre(const int32_t* __restrict__ counts, const int32_t* 
     int32_t acc = 0;
     for (int ci = 0; ci < C; ++ci) {
         const int64_t src = e * C + ci;
-        bpre[g * (C + 1) + ci] = acc;
-        bdelta[g * C + ci] = ci * RG::n + seg[src * (C + 1) + co] - acc;
+        pre[g * C + ci] = acc;
+        pdelta[src * C + co] = co * RG::n + acc - seg[src * C + co];
         acc += counts[src * C + co];
     }
-    bpre[g * (C + 1) + C] = acc;
 }
 
-// srcA / dstB: thread ci of block (e, co) walks destination chunk co in
+// packA / dstB: thread ci of block (e, co) walks destination chunk co in
 // order and appends the elements whose source is in chunk ci to group
-// (ci, co).
+// (ci, co) on both sides.
 __global__ void __launch_bounds__(512)
     k_bucket_fill(const int32_t* __restrict__ perm, int64_t n, int C, const int32_t* __restrict__ seg,
-                  uint16_t* __restrict__ srcA, uint16_t* __restrict__ dstB)
+                  const int32_t* __restrict__ pre, uint32_t* __restrict__ packA, uint16_t* __restrict__ dstB)
 {
     constexpr int TILE = 1024;
     __shared__ int32_t tile[TILE];
@@ -475,7 +458,11 @@ __global__ void __launch_bounds__(512)
     const int co = (int)(blockIdx.x % C);
     const int ci = threadIdx.x;
     const int32_t* pc = perm + e * n + (int64_t)co * RG::n;
-    int64_t pos = ci < C ? e * n + (int64_t)ci * RG::n + seg[(e * C + ci) * (C + 1) + co] : 0;
+    int64_t qa = 0, pb = 0;
+    if (ci < C) {
+        qa = e * n + (int64_t)ci * RG::n + seg[(e * C + ci) * C + co];
+        pb = e * n + (int64_t)co * RG::n + pre[(e * C + co) * C + ci];
+    }
     for (int base = 0; base < RG::n; base += TILE) {
         __syncthreads();
         for (int j = threadIdx.x; j < TILE; j += blockDim.x)
@@ -485,9 +472,8 @@ __global__ void __launch_bounds__(512)
             for (int j = 0; j < TILE; ++j) {
                 const int32_t src = tile[j];
                 if ((src >> kRowM) == ci) {
-                    srcA[pos] = (uint16_t)(src & (RG::n - 1));
-                    dstB[pos] = (uint16_t)(base + j);
-                    ++pos;
+                    packA[qa++] = ((uint32_t)co << kRowM) | (uint32_t)(src & (RG::n - 1));
+                    dstB[pb++] = (uint16_t)(base + j);
                 }
             }
         }
@@ -507,7 +493,7 @@ hipError_t launch_fwht_long(int M, float* data, int64_t batch, bool vec, hipStre
     if (M <= kRowM || M > 24)
         return hipErrorInvalidValue;
     const int64_t n = int64_t(1) << M;
-    RowArgs a{data, data, batch, n >> kRowM, nullptr, nullptr, nullptr, nullptr, nullptr};
+    const RowArgs a{data, data, batch, n >> kRowM, nullptr, nullptr, nullptr, nullptr};
     hipError_t err = row_pass<kInRow, kOutRow>(vec, a, s);
     if (err != hipSuccess)
         return err;
@@ -515,13 +501,13 @@ hipError_t launch_fwht_long(int M, float* data, int64_t batch, bool vec, hipStre
 }
 
 hipError_t launch_forward_long(int M, bool vec, int xt, int yt, const void* x, int64_t batch, int d, int64_t E,
-                               const float* B, const uint16_t* srcA, const uint16_t* dstB, const int32_t* bpre,
-                               const int32_t* bdelta, const float* G, const float* Sh, float cs, void* phi, float* u,
-                               float* w, hipStream_t s)
+                               const float* B, const uint32_t* packA, const uint16_t* dstB, const int32_t* pdelta,
+                               const float* G, const float* Sh, float cs, void* phi, float* u, float* w,
+                               hipStream_t s)
 {
     if (M <= kRowM || M > 24)
         return hipErrorInvalidValue;
-#define MCK_FL_ARGS M, vec, x, batch, d, E, B, srcA, dstB, bpre, bdelta, G, Sh, cs, phi, u, w, s
+#define MCK_FL_ARGS M, vec, x, batch, d, E, B, packA, dstB, pdelta, G, Sh, cs, phi, u, w, s
     if (xt == kF32 && yt == kF32)
         return forward_long<kF32, kF32>(MCK_FL_ARGS);
     if (xt == kF32 && yt == kBF16)
@@ -536,22 +522,23 @@ hipError_t launch_forward_long(int M, bool vec, int xt, int yt, const void* x, i
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_buckets(int M, int64_t E, const int32_t* perm, uint16_t* srcA, uint16_t* dstB, int32_t* bpre,
-                          int32_t* bdelta, int32_t* scratch, hipStream_t s)
+hipError_t launch_buckets(int M, int64_t E, const int32_t* perm, uint32_t* packA, uint16_t* dstB, int32_t* pdelta,
+                          int32_t* scratch, hipStream_t s)
 {
     if (M <= kRowM || M > 24)
         return hipErrorInvalidValue;
     const int64_t n = int64_t(1) << M;
     const int C = (int)(n >> kRowM);
     int32_t* counts = scratch;
-    int32_t* seg = scratch + E * C * C;
+    int32_t* seg = counts + E * C * C;
+    int32_t* pre = seg + E * C * C;
     const unsigned blocks = (unsigned)(E * C);
     k_bucket_count<<<dim3(blocks), dim3(1024), 0, s>>>(perm, n, C, counts);
     const unsigned tb = (unsigned)((E * C + 255) / 256);
     k_bucket_seg<<<dim3(tb), dim3(256), 0, s>>>(counts, E, C, seg);
-    k_bucket_pre<<<dim3(tb), dim3(256), 0, s>>>(counts, seg, E, C, bpre, bdelta);
+    k_bucket_pre<<<dim3(tb), dim3(256), 0, s>>>(counts, seg, E, C, pre, pdelta);
     const int threads = C < 64 ? 64 : C;
-    k_bucket_fill<<<dim3(blocks), dim3((unsigned)threads), 0, s>>>(perm, n, C, seg, srcA, dstB);
+    k_bucket_fill<<<dim3(blocks), dim3((unsigned)threads), 0, s>>>(perm, n, C, seg, pre, packA, dstB);
     return hipGetLastError();
 }
 

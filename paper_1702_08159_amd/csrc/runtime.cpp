@@ -134,11 +134,10 @@ struct Plan {
     float* Sh = nullptr;        // S / (2 pi)
     // n > MCK_MAX_N: Pi as buckets between 2^15-element source and
     // destination chunks (C = n / 2^15 of each, layout in launch.hpp)
-    uint16_t* srcA = nullptr;
+    uint32_t* packA = nullptr;
     uint16_t* dstB = nullptr;
-    int32_t* bpre = nullptr;
-    int32_t* bdelta = nullptr;
-    int32_t* bscratch = nullptr;  // build scratch: segment starts and counts
+    int32_t* pdelta = nullptr;
+    int32_t* bscratch = nullptr;  // build scratch
 };
 
 std::mutex g_mutex;
@@ -190,12 +189,12 @@ mck_status get_plan(uint32_t seed, int64_t n, int64_t E, double sigma, int calib
     int64_t gf = 0, gb = 0;
     mck::plan_elems(log2i(n), &gf, &gb);
     const size_t C = n > MCK_MAX_N ? (size_t)(n / MCK_MAX_N) : 0;
-    const size_t ec1 = (size_t)E * C * (C + 1) * 4, ecc = (size_t)E * C * C * 4;
-    size_t off[16], total = 0;
-    const size_t sz[16] = {en * 4, en * 4, en * 4, en * 8, en * 4, (size_t)E * 8,
+    const size_t ecc = (size_t)E * C * C * 4;
+    size_t off[15], total = 0;
+    const size_t sz[15] = {en * 4, en * 4, en * 4, en * 8, en * 4, (size_t)E * 8,
                            (size_t)gf * E * 4, en * 4, (size_t)gb * E * 4, en * 4, en * 4,
-                           C ? en * 2 : 0, C ? en * 2 : 0, ec1, ecc, ec1 + ecc};
-    for (int i = 0; i < 16; ++i) {
+                           C ? en * 4 : 0, C ? en * 2 : 0, ecc, 3 * ecc + (size_t)E * C * 8};
+    for (int i = 0; i < 15; ++i) {
         off[i] = total;
         total += align_up(sz[i]);
     }
@@ -230,11 +229,10 @@ mck_status get_plan(uint32_t seed, int64_t n, int64_t E, double sigma, int calib
     p.GkB = reinterpret_cast<float*>(b + off[9]);
     p.Sh = reinterpret_cast<float*>(b + off[10]);
     if (C) {
-        p.srcA = reinterpret_cast<uint16_t*>(b + off[11]);
+        p.packA = reinterpret_cast<uint32_t*>(b + off[11]);
         p.dstB = reinterpret_cast<uint16_t*>(b + off[12]);
-        p.bpre = reinterpret_cast<int32_t*>(b + off[13]);
-        p.bdelta = reinterpret_cast<int32_t*>(b + off[14]);
-        p.bscratch = reinterpret_cast<int32_t*>(b + off[15]);
+        p.pdelta = reinterpret_cast<int32_t*>(b + off[13]);
+        p.bscratch = reinterpret_cast<int32_t*>(b + off[14]);
     }
     int matern_t = 0;
     {
@@ -250,7 +248,7 @@ mck_status get_plan(uint32_t seed, int64_t n, int64_t E, double sigma, int calib
                             : mck::launch_derive(log2i(n), E, p.perm, p.G, p.S64, p.S32, p.goffF, p.GsF, p.goffB,
                                                  p.GkB, p.Sh, stream);
     if (err == hipSuccess && n > MCK_MAX_N)
-        err = mck::launch_buckets(log2i(n), E, p.perm, p.srcA, p.dstB, p.bpre, p.bdelta, p.bscratch, stream);
+        err = mck::launch_buckets(log2i(n), E, p.perm, p.packA, p.dstB, p.pdelta, p.bscratch, stream);
     if (err == hipSuccess)
         err = hipStreamSynchronize(stream);  // the plan may be used from other streams next
     if (err != hipSuccess) {
@@ -426,9 +424,10 @@ mck_status mck_fastfood_params(uint32_t seed, int64_t n, int64_t E, double sigma
     return err == hipSuccess ? MCK_OK : hip_fail(err, "mck_fastfood_params copy");
 }
 
-// Feature map for n > MCK_MAX_N: row chunks sized so that one chunk's phi
-// range stays below 2^31 bytes and each FP32 scratch buffer below 2^27
-// floats; the scratch is stream-ordered.
+// Feature map for n > MCK_MAX_N.  The kernels address phi, x and the
+// scratch per row, so only a row of phi must stay below 2^31 bytes; rows go
+// in equal chunks of at most 2^27 floats per FP32 scratch buffer (u, w,
+// stream-ordered).
 static mck_status forward_long(const Plan* p, const void* x, int xt, int64_t batch, int64_t d, int64_t n, int64_t E,
                                void* phi, int yt, hipStream_t s)
 {
@@ -436,10 +435,11 @@ static mck_status forward_long(const Plan* p, const void* x, int xt, int64_t bat
     const int64_t row_phi = 2 * n * E * yb;
     if (row_phi > (int64_t(1) << 31) - 4096)
         return fail(MCK_ERR_UNSUPPORTED, "one row of phi exceeds 2^31 bytes");
-    int64_t rows_per = ((int64_t(1) << 31) - 4096) / row_phi;
-    const int64_t scratch_rows = ((int64_t)1 << 27) / n;
-    rows_per = rows_per > scratch_rows ? scratch_rows : rows_per;
-    rows_per = rows_per > batch ? batch : (rows_per < 1 ? 1 : rows_per);
+    if (batch == 0)
+        return MCK_OK;
+    const int64_t max_rows = ((int64_t)1 << 27) / n;
+    const int64_t nchunks = (batch + max_rows - 1) / max_rows;
+    const int64_t rows_per = (batch + nchunks - 1) / nchunks;
     float* u = nullptr;
     hipError_t err = hipMallocAsync(reinterpret_cast<void**>(&u), (size_t)(2 * rows_per * n) * sizeof(float), s);
     if (err != hipSuccess)
@@ -451,7 +451,7 @@ static mck_status forward_long(const Plan* p, const void* x, int xt, int64_t bat
     for (int64_t r0 = 0; r0 < batch && err == hipSuccess; r0 += rows_per) {
         const int64_t rows = batch - r0 < rows_per ? batch - r0 : rows_per;
         err = mck::launch_forward_long(log2i(n), vec, xt, yt, static_cast<const char*>(x) + r0 * d * xb, rows,
-                                       (int)d, E, p->B, p->srcA, p->dstB, p->bpre, p->bdelta, p->G, p->Sh, cs,
+                                       (int)d, E, p->B, p->packA, p->dstB, p->pdelta, p->G, p->Sh, cs,
                                        static_cast<char*>(phi) + r0 * row_phi, u, w, s);
     }
     (void)hipFreeAsync(u, s);
