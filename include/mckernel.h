@@ -232,6 +232,53 @@ mck_status mck_softmax_xent(const float* logits, const int32_t* labels, int64_t 
                             float* dlogits, float* db, mck_stream stream);
 
 /*
+ * The two products of the same head (section "Empirical Analysis and
+ * Experiments") on F = 2nE features, for C in [1, 16] classes:
+ *
+ *   mck_head_logits:   logits[r][c] = b[c] + sum_j W[c][j] phi[r][j]
+ *   mck_head_backward: dphi[r][j] = sum_c dlogits[r][c] W[c][j] and
+ *                      dW[c][j] = sum_r dlogits[r][c] phi[r][j]
+ *
+ * phi, dphi: batch x F row-major; W, dW: C x F row-major; logits, dlogits:
+ * batch x C.  F must be a multiple of 4 and phi, W, dphi, dW 16-byte
+ * aligned (MCK_ERR_INVALID_ARG otherwise); C F < 2^29 (MCK_ERR_UNSUPPORTED
+ * otherwise).  b may be NULL (no bias); dphi or dW may be NULL (not
+ * computed).  Every sum runs in a fixed order, so results are
+ * deterministic.  Partial sums live in scratch allocated on `stream`
+ * (stream-ordered): batch C F / 4096 floats for the logits, at most 32 C F
+ * for dW.  An empty batch gives dW = 0.
+ */
+mck_status mck_head_logits(const float* phi, const float* W, const float* b, int64_t batch, int64_t F, int64_t C,
+                           float* logits, mck_stream stream);
+mck_status mck_head_backward(const float* phi, const float* dlogits, const float* W, int64_t batch, int64_t F,
+                             int64_t C, float* dphi, float* dW, mck_stream stream);
+
+/*
+ * One training step of the classifier softmax(W phi(x) + b) with
+ * cross-entropy (section "Empirical Analysis and Experiments") on the
+ * features of explicit diagonals B, perm, G, S (as for
+ * mck_fastfood_forward_p; n = mck_padded_dim(d) <= 2^15, F = 2nE), minimised
+ * by SGD (section "Large-scale Machine Learning"):
+ *
+ *   phi = phi(x); logits = phi W^T + b; *loss = mean cross-entropy;
+ *   dW, db, dB, dG, dS (and dx if non-NULL) = gradients of the mean loss;
+ *   with lr != 0, W -= lr dW, b -= lr db, B -= lr dB, G -= lr dG,
+ *   S -= lr dS in place afterwards (perm stays fixed).
+ *
+ * labels: batch int32 in [0, C) (a label outside makes the loss NaN);
+ * logits (batch x C) is written when non-NULL; W, dW: C x F, 16-byte
+ * aligned; C in [1, 16]; batch >= 1.  The gradients are those of the
+ * parameters before the update.  One plan derivation serves the forward
+ * and the adjoint; scratch (2 batch F floats for phi and dphi, plus
+ * partial sums) is allocated on `stream` (stream-ordered).  Every sum has
+ * a fixed order: the step is deterministic.
+ */
+mck_status mck_fastfood_train_step(const float* x, const int32_t* labels, int64_t batch, int64_t d, int64_t n,
+                                   int64_t E, int64_t C, float* W, float* b, float* B, const int32_t* perm, float* G,
+                                   float* S, float lr, float* loss, float* logits, float* dW, float* db, float* dB,
+                                   float* dG, float* dS, float* dx, mck_stream stream);
+
+/*
  * y += alpha x over `count` floats (the SGD update w <- w - gamma grad of
  * section "Large-scale Machine Learning", with alpha = -gamma).  y and x
  * must not overlap unless equal.

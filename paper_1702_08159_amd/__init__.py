@@ -323,25 +323,72 @@ def axpy_(y: torch.Tensor, x: torch.Tensor, alpha: float) -> torch.Tensor:
     return y
 
 
+def head_logits(phi: torch.Tensor, W: torch.Tensor, b=None) -> torch.Tensor:
+    """logits = phi W^T + b for C <= 16 classes (phi: batch x F, W: C x F)."""
+    _check(phi, "phi")
+    _check(W, "W")
+    if b is not None:
+        _check(b, "b")
+    batch, F = phi.shape
+    C = W.shape[0]
+    if W.shape != (C, F) or (b is not None and b.shape != (C,)):
+        raise ValueError("W must be C x F and b of length C")
+    logits = torch.empty((batch, C), dtype=torch.float32, device=phi.device)
+    with torch.cuda.device(phi.device):
+        _lib.call("mck_head_logits", _ptr(phi), _ptr(W), _ptr(b) if b is not None else None, batch, F, C,
+                  _ptr(logits), _stream(phi))
+    return logits
+
+
+def head_backward(phi: torch.Tensor, dlogits: torch.Tensor, W: torch.Tensor, need_dphi=True, need_dW=True):
+    """(dphi, dW) = (dlogits W, dlogits^T phi); either may be skipped (None)."""
+    _check(phi, "phi")
+    _check(dlogits, "dlogits")
+    _check(W, "W")
+    batch, F = phi.shape
+    C = W.shape[0]
+    if W.shape != (C, F) or dlogits.shape != (batch, C):
+        raise ValueError("W must be C x F and dlogits batch x C")
+    dphi = torch.empty_like(phi) if need_dphi else None
+    dW = torch.empty_like(W) if need_dW else None
+    with torch.cuda.device(phi.device):
+        _lib.call("mck_head_backward", _ptr(phi), _ptr(dlogits), _ptr(W), batch, F, C,
+                  _ptr(dphi) if dphi is not None else None, _ptr(dW) if dW is not None else None, _stream(phi))
+    return dphi, dW
+
+
 def train_step(x, labels, W, b, B, perm, G, S, lr=None, need_dx=False):
     """One step of the classifier softmax(W phi(x) + b) with cross-entropy on
-    the features of explicit diagonals B, G, S (perm fixed): the feature map
-    and its adjoint run in this library's kernels, the three dense products
-    (logits, dW, dphi) in the BLAS library.  Returns the loss and the
-    gradients with respect to W, b, B, G, S (and x if need_dx); with lr given,
-    applies the SGD update to W, b, B, G, S in place."""
-    for t, nm in ((W, "W"), (b, "b")):
+    the features of explicit diagonals B, G, S (perm fixed), as one library
+    call: feature map, logits, softmax cross-entropy, the head's products and
+    the feature map's adjoint all run in this library's kernels.  Returns the
+    loss and the gradients with respect to W, b, B, G, S (and x if need_dx);
+    with lr given, applies the SGD update to W, b, B, G, S in place."""
+    _check(x, "x")
+    _check(labels, "labels", torch.int32)
+    for t, nm in ((W, "W"), (b, "b"), (B, "B"), (G, "G"), (S, "S")):
         _check(t, nm)
-    phi = forward_p(x, B, perm, G, S)
-    logits = torch.addmm(b, phi, W.t())
-    loss, dlogits, db = softmax_xent(logits, labels)
-    dW = torch.mm(dlogits.t(), phi)
-    dphi = torch.mm(dlogits, W)
-    dx, dB, dG, dS = backward_p(x, dphi, B, perm, G, S, need_dx=need_dx, need_params=True)
-    if lr is not None:
-        for prm, grd in ((W, dW), (b, db), (B, dB), (G, dG), (S, dS)):
-            axpy_(prm, grd, -float(lr))
-    return {"loss": loss, "dW": dW, "db": db, "dx": dx, "dB": dB, "dG": dG, "dS": dS, "logits": logits}
+    _check(perm, "perm", torch.int32)
+    batch, d = _rows(x)
+    E, n = B.shape
+    C = W.shape[0]
+    if W.shape != (C, 2 * n * E) or b.shape != (C,) or labels.shape != (batch,):
+        raise ValueError("W must be C x 2nE, b of length C and labels of length batch")
+    for t in (perm, G, S):
+        if t.shape != (E, n):
+            raise ValueError("B, perm, G and S must all be E x n")
+    dev = x.device
+    out = {"loss": torch.empty((), dtype=torch.float32, device=dev),
+           "logits": torch.empty((batch, C), dtype=torch.float32, device=dev),
+           "dW": torch.empty_like(W), "db": torch.empty_like(b), "dB": torch.empty_like(B),
+           "dG": torch.empty_like(G), "dS": torch.empty_like(S),
+           "dx": torch.empty((batch, d), dtype=torch.float32, device=dev) if need_dx else None}
+    with torch.cuda.device(dev):
+        _lib.call("mck_fastfood_train_step", _ptr(x), _ptr(labels), batch, d, n, E, C, _ptr(W), _ptr(b), _ptr(B),
+                  _ptr(perm), _ptr(G), _ptr(S), float(lr) if lr is not None else 0.0, _ptr(out["loss"]),
+                  _ptr(out["logits"]), _ptr(out["dW"]), _ptr(out["db"]), _ptr(out["dB"]), _ptr(out["dG"]),
+                  _ptr(out["dS"]), _ptr(out["dx"]), _stream(x))
+    return out
 
 
 def shutdown() -> None:

@@ -40,6 +40,10 @@ SIGNATURES = {
     "mck_gen_boxmuller": (_int, [_vp, _vp, _i64, _vp, _vp, _vp]),
     "mck_softmax_xent": (_int, [_vp, _vp, _i64, _i64, _vp, _vp, _vp, _vp]),
     "mck_axpy": (_int, [_vp, _vp, _i64, ctypes.c_float, _vp]),
+    "mck_head_logits": (_int, [_vp, _vp, _vp, _i64, _i64, _i64, _vp, _vp]),
+    "mck_head_backward": (_int, [_vp, _vp, _vp, _i64, _i64, _i64, _vp, _vp, _vp]),
+    "mck_fastfood_train_step": (_int, [_vp, _vp, _i64, _i64, _i64, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp,
+                                        ctypes.c_float, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "mck_shutdown": (None, []),
 }
 

@@ -6,13 +6,19 @@
 //                   gradient of the mean loss, (softmax(l_r) - onehot(y)) / batch
 //   k_head_sums     fixed-order sums over rows: the mean loss and db
 //   k_axpy          y += alpha x (the SGD update with alpha = -learning rate)
-//
-// The logits and the weight gradients are plain GEMMs (phi W^T, dlogits^T
-// phi, dlogits W) left to the BLAS library; these kernels hold the rest.
+//   k_head_logits   logits = phi W^T + b for C <= 16 classes: the W rows of a
+//                   column live in VGPRs, phi streams once from HBM
+//   k_head_bwd      dphi = dlogits W and per-row-group partials of
+//                   dW = dlogits^T phi (one pass over phi)
+//   k_sum_groups    the row-group partials summed in a fixed order
+// The products are skinny (C rows against 2nE columns), so each is one
+// streaming pass over phi rather than a GEMM tiling; every sum has a fixed
+// order, so the results are deterministic.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
 
+#include "engine.hpp"
 #include "launch.hpp"
 
 namespace mck {
@@ -53,34 +59,33 @@ __global__ void __launch_bounds__(kHeadThreads)
     }
 }
 
-// One block: thread k sums rows k, k + 256, ... of the column in order, then
-// a fixed binary tree over the 256 partial sums.  Column C is the row loss
-// (scaled by 1/batch), columns 0..C-1 are dlogits (db).
+// Block col (C + 1 of them): thread k sums rows k, k + 256, ... of the
+// column in order, then a fixed binary tree over the 256 partial sums.
+// Column C is the row loss (scaled by 1/batch), columns 0..C-1 are dlogits
+// (db).
 __global__ void __launch_bounds__(kHeadThreads)
     k_head_sums(const float* __restrict__ row_loss, const float* __restrict__ dlogits, int64_t batch, int C,
                 float inv_batch, float* __restrict__ loss, float* __restrict__ db)
 {
     __shared__ float part[kHeadThreads];
-    for (int col = 0; col <= C; ++col) {
-        float s = 0.f;
-        for (int64_t r = threadIdx.x; r < batch; r += kHeadThreads)
-            s += col == C ? row_loss[r] : dlogits[r * C + col];
-        part[threadIdx.x] = s;
+    const int col = blockIdx.x;
+    float s = 0.f;
+    for (int64_t r = threadIdx.x; r < batch; r += kHeadThreads)
+        s += col == C ? row_loss[r] : dlogits[r * C + col];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kHeadThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            part[threadIdx.x] += part[threadIdx.x + w];
         __syncthreads();
-        for (int w = kHeadThreads / 2; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w)
-                part[threadIdx.x] += part[threadIdx.x + w];
-            __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (col == C) {
+            if (loss)
+                *loss = part[0] * inv_batch;
+        } else if (db) {
+            db[col] = part[0];
         }
-        if (threadIdx.x == 0) {
-            if (col == C) {
-                if (loss)
-                    *loss = part[0] * inv_batch;
-            } else if (db) {
-                db[col] = part[0];
-            }
-        }
-        __syncthreads();
     }
 }
 
@@ -92,7 +97,272 @@ __global__ void __launch_bounds__(kHeadThreads)
         y[i] += alpha * x[i];
 }
 
+// Block (row group, slab): rows r0 .. r0 + R - 1 against the slab's 4 x 1024
+// columns; thread t takes float4 columns 1024 slab + t + 256 i, i < 4.  Each
+// of the R C sums is reduced over the wave (xor butterfly) and the four
+// waves (fixed order) into part[slab][r][c].  Rows past the batch read zero
+// (empty range) and are not written.
+constexpr int kLogitRows = 4;
+constexpr int kLogitSlab4 = 1024;  // float4 columns per slab
+
+template <int C, int R>
+__global__ void __launch_bounds__(kHeadThreads)
+    k_head_logits(const float* __restrict__ phi, const float* __restrict__ W, int64_t batch, int64_t F,
+                  int64_t slabs, float* __restrict__ part)
+{
+    const int64_t slab = blockIdx.x % slabs;
+    const int64_t r0 = (int64_t)(blockIdx.x / slabs) * R;
+    const uint32_t t = threadIdx.x;
+    const int64_t F4 = F / 4;
+    const rsrc_t rw = make_rsrc(W, (uint32_t)(C * F * 4));
+    rsrc_t rp[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        rp[r] = make_rsrc(phi + (r0 + r) * F, r0 + r < batch ? (uint32_t)(F * 4) : 0u);
+    float acc[R][C];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int k = 0; k < C; ++k)
+            acc[r][k] = 0.f;
+    const int64_t q0 = slab * kLogitSlab4 + t;
+#pragma unroll 2
+    for (int i = 0; i < kLogitSlab4 / kHeadThreads; ++i) {
+        const int64_t q = q0 + i * kHeadThreads;
+        if (q >= F4)
+            break;
+        float p[R][4];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            bload4<2>(p[r], rp[r], (uint32_t)(16 * q), 0u);
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            float w[4];
+            bload4(w, rw, (uint32_t)(16 * (k * F4 + q)), 0u);
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                acc[r][k] += p[r][0] * w[0] + p[r][1] * w[1] + p[r][2] * w[2] + p[r][3] * w[3];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int k = 0; k < C; ++k)
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1)
+                acc[r][k] += __shfl_xor(acc[r][k], o);
+    __shared__ float red[kHeadThreads / 64][R * C];
+    const uint32_t wave = t / 64u;
+    if (t % 64u == 0) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int k = 0; k < C; ++k)
+                red[wave][r * C + k] = acc[r][k];
+    }
+    __syncthreads();
+    if (t < (uint32_t)(R * C)) {
+        const int r = (int)t / C;
+        if (r0 + r < batch)
+            part[(slab * batch + r0) * C + t] = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
+    }
+}
+
+// logits[r][c] = b[c] + sum over slabs of part[slab][r][c], slabs ascending.
+__global__ void __launch_bounds__(kHeadThreads)
+    k_logits_finish(const float* __restrict__ part, const float* __restrict__ bias, int64_t slabs, int64_t batch,
+                    int C, float* __restrict__ logits)
+{
+    const int64_t i = (int64_t)blockIdx.x * kHeadThreads + threadIdx.x;
+    if (i >= batch * C)
+        return;
+    float s = 0.f;
+    for (int64_t sl = 0; sl < slabs; ++sl)
+        s += part[sl * batch * C + i];
+    logits[i] = (bias ? bias[i % C] : 0.f) + s;
+}
+
+// Block (slab, group): thread t owns float4 column q = 256 slab + t and runs
+// over the group's rows r: dphi[r][q] = sum_k dl[r][k] W[k][q] and
+// acc[k][q] += dl[r][k] phi[r][q]; acc goes to part (group g at g C F).
+template <int C>
+__global__ void __launch_bounds__(kHeadThreads)
+    k_head_bwd(const float* __restrict__ phi, const float* __restrict__ dl, const float* __restrict__ W,
+               int64_t batch, int64_t F, int64_t slabs, int64_t rows_per_group, float* __restrict__ dphi,
+               float* __restrict__ part)
+{
+    const int64_t F4 = F / 4;
+    const int64_t slab = blockIdx.x % slabs, g = blockIdx.x / slabs;
+    const int64_t q = slab * kHeadThreads + threadIdx.x;
+    if (q >= F4)
+        return;
+    const int64_t rb = g * rows_per_group;
+    const int64_t re = rb + rows_per_group < batch ? rb + rows_per_group : batch;
+    const rsrc_t rw = make_rsrc(W, (uint32_t)(C * F * 4));
+    float wq[C][4], acc[C][4];
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        bload4(wq[k], rw, (uint32_t)(16 * (k * F4 + q)), 0u);
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            acc[k][m] = 0.f;
+    }
+#pragma unroll 8
+    for (int64_t r = rb; r < re; ++r) {
+        float dlr[C];
+#pragma unroll
+        for (int k = 0; k < C; ++k)
+            dlr[k] = dl[r * C + k];
+        if (part != nullptr) {
+            float p[4];
+            bload4<2>(p, make_rsrc(phi + r * F, (uint32_t)(F * 4)), (uint32_t)(16 * q), 0u);
+#pragma unroll
+            for (int k = 0; k < C; ++k)
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+                    acc[k][m] += dlr[k] * p[m];
+        }
+        if (dphi != nullptr) {
+            float o[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int k = 0; k < C; ++k)
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+                    o[m] += dlr[k] * wq[k][m];
+            bstore4_nt(make_rsrc(dphi + r * F, (uint32_t)(F * 4)), (uint32_t)(16 * q), o[0], o[1], o[2], o[3]);
+        }
+    }
+    if (part != nullptr) {
+        const rsrc_t ro = make_rsrc(part + g * C * F, (uint32_t)(C * F * 4));
+#pragma unroll
+        for (int k = 0; k < C; ++k)
+            bstore4(ro, (uint32_t)(16 * (k * F4 + q)), acc[k][0], acc[k][1], acc[k][2], acc[k][3]);
+    }
+}
+
+// out[i] = sum over g of part[g count + i], g ascending (zero for no groups).
+__global__ void __launch_bounds__(kHeadThreads)
+    k_sum_groups(const float* __restrict__ part, int64_t groups, int64_t count, float* __restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * kHeadThreads + threadIdx.x;
+    if (i >= count)
+        return;
+    float s = 0.f;
+    for (int64_t g = 0; g < groups; ++g)
+        s += part[g * count + i];
+    out[i] = s;
+}
+
+template <int C>
+hipError_t head_logits_c(const float* phi, const float* W, int64_t batch, int64_t F, int64_t slabs, float* part,
+                         hipStream_t s)
+{
+    const int64_t groups = (batch + kLogitRows - 1) / kLogitRows;
+    k_head_logits<C, kLogitRows><<<dim3((unsigned)(groups * slabs)), dim3(kHeadThreads), 0, s>>>(phi, W, batch, F,
+                                                                                                 slabs, part);
+    return hipGetLastError();
+}
+
+template <int C>
+hipError_t head_bwd_c(const float* phi, const float* dl, const float* W, int64_t batch, int64_t F, int64_t slabs,
+                      int64_t groups, int64_t rows_per_group, float* dphi, float* part, hipStream_t s)
+{
+    k_head_bwd<C><<<dim3((unsigned)(slabs * groups)), dim3(kHeadThreads), 0, s>>>(phi, dl, W, batch, F, slabs,
+                                                                                   rows_per_group, dphi, part);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+int64_t head_logit_slabs(int64_t F) { return (F / 4 + kLogitSlab4 - 1) / kLogitSlab4; }
+
+hipError_t launch_head_logits(const float* phi, const float* W, const float* b, int64_t batch, int64_t F, int C,
+                              float* part, float* logits, hipStream_t s)
+{
+    const int64_t slabs = head_logit_slabs(F);
+    hipError_t err;
+#define MCK_LOGITS(K) err = head_logits_c<K>(phi, W, batch, F, slabs, part, s); break
+    switch (C) {
+    case 1: MCK_LOGITS(1);
+    case 2: MCK_LOGITS(2);
+    case 3: MCK_LOGITS(3);
+    case 4: MCK_LOGITS(4);
+    case 5: MCK_LOGITS(5);
+    case 6: MCK_LOGITS(6);
+    case 7: MCK_LOGITS(7);
+    case 8: MCK_LOGITS(8);
+    case 9: MCK_LOGITS(9);
+    case 10: MCK_LOGITS(10);
+    case 11: MCK_LOGITS(11);
+    case 12: MCK_LOGITS(12);
+    case 13: MCK_LOGITS(13);
+    case 14: MCK_LOGITS(14);
+    case 15: MCK_LOGITS(15);
+    case 16: MCK_LOGITS(16);
+    default: return hipErrorInvalidValue;
+    }
+#undef MCK_LOGITS
+    if (err != hipSuccess)
+        return err;
+    const unsigned blocks = (unsigned)((batch * C + kHeadThreads - 1) / kHeadThreads);
+    k_logits_finish<<<dim3(blocks), dim3(kHeadThreads), 0, s>>>(part, b, slabs, batch, C, logits);
+    return hipGetLastError();
+}
+
+void head_bwd_geometry(int64_t batch, int64_t F, bool need_dW, int64_t* slabs, int64_t* groups, int64_t* rows_per_group)
+{
+    const int64_t F4 = F / 4;
+    *slabs = (F4 + kHeadThreads - 1) / kHeadThreads;
+    // about 512 blocks; with dW each group adds C F floats of partials, so at
+    // most 32 groups
+    int64_t g = (512 + *slabs - 1) / *slabs;
+    if (need_dW && g > 32)
+        g = 32;
+    if (g > batch)
+        g = batch;
+    if (g < 1)
+        g = 1;
+    *rows_per_group = batch > 0 ? (batch + g - 1) / g : 1;
+    *groups = batch > 0 ? (batch + *rows_per_group - 1) / *rows_per_group : 0;
+}
+
+hipError_t launch_head_bwd(const float* phi, const float* dl, const float* W, int64_t batch, int64_t F, int C,
+                           int64_t slabs, int64_t groups, int64_t rows_per_group, float* dphi, float* part,
+                           hipStream_t s)
+{
+    if (groups == 0)
+        return hipSuccess;
+#define MCK_HBWD(K) head_bwd_c<K>(phi, dl, W, batch, F, slabs, groups, rows_per_group, dphi, part, s)
+    switch (C) {
+    case 1: return MCK_HBWD(1);
+    case 2: return MCK_HBWD(2);
+    case 3: return MCK_HBWD(3);
+    case 4: return MCK_HBWD(4);
+    case 5: return MCK_HBWD(5);
+    case 6: return MCK_HBWD(6);
+    case 7: return MCK_HBWD(7);
+    case 8: return MCK_HBWD(8);
+    case 9: return MCK_HBWD(9);
+    case 10: return MCK_HBWD(10);
+    case 11: return MCK_HBWD(11);
+    case 12: return MCK_HBWD(12);
+    case 13: return MCK_HBWD(13);
+    case 14: return MCK_HBWD(14);
+    case 15: return MCK_HBWD(15);
+    case 16: return MCK_HBWD(16);
+    default: return hipErrorInvalidValue;
+    }
+#undef MCK_HBWD
+}
+
+hipError_t launch_sum_groups(const float* part, int64_t groups, int64_t count, float* out, hipStream_t s)
+{
+    if (count == 0)
+        return hipSuccess;
+    const unsigned blocks = (unsigned)((count + kHeadThreads - 1) / kHeadThreads);
+    k_sum_groups<<<dim3(blocks), dim3(kHeadThreads), 0, s>>>(part, groups, count, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_softmax_xent(const float* logits, const int32_t* labels, int64_t batch, int C, float* row_loss,
                                float* dlogits, float* loss, float* db, hipStream_t s)
@@ -103,7 +373,7 @@ hipError_t launch_softmax_xent(const float* logits, const int32_t* labels, int64
     hipError_t err = hipGetLastError();
     if (err != hipSuccess)
         return err;
-    k_head_sums<<<dim3(1), dim3(kHeadThreads), 0, s>>>(row_loss, dlogits, batch, C, inv, loss, db);
+    k_head_sums<<<dim3((unsigned)(C + 1)), dim3(kHeadThreads), 0, s>>>(row_loss, dlogits, batch, C, inv, loss, db);
     return hipGetLastError();
 }
 

@@ -303,12 +303,16 @@ __global__ void __launch_bounds__(BwdGeo<M>::THREADS)
                     uint32_t dphi_bytes, int64_t batch, int d, int E, const float* __restrict__ B,
                     const uint32_t* __restrict__ goff, const float* __restrict__ Gk, const float* __restrict__ S32,
                     const float* __restrict__ Sh, float cs, float* __restrict__ dx, float* __restrict__ partial,
-                    int passes)
+                    int passes, int esplit, int64_t rowblocks, int64_t dx_group_stride)
 {
     using bg = BwdGeo<M>;
     constexpr int P = bg::P;
     using g = Geo<M, P>;
     static_assert(!g::kMulti, "rows of one wave or less");
+    // block = (row block rb, expansion group eg): expansions [e0, e1)
+    const int64_t rb = (int64_t)blockIdx.x % rowblocks;
+    const int eg = (int)((int64_t)blockIdx.x / rowblocks);
+    const int e0 = (int)((int64_t)eg * E / esplit), e1 = (int)((int64_t)(eg + 1) * E / esplit);
     constexpr int EPL = g::EPL, n = g::n, K = g::K, NQ = EPL / 4 > 0 ? EPL / 4 : 1;
     constexpr int GOFF_E = g::RPB * n;  // gather offsets per expansion (all row groups of a wave)
     // parameter stage: B, S, S/(2 pi) in natural order; G and the gather
@@ -331,18 +335,18 @@ __global__ void __launch_bounds__(BwdGeo<M>::THREADS)
     const uint32_t nE = (uint32_t)n * (uint32_t)E;
     const uint32_t ct = tpart<M, P, 0>(t);
     const rsrc_t rx = make_rsrc(x, x_bytes), rD = make_rsrc(dphi, dphi_bytes);
-    const int64_t row_base = (int64_t)blockIdx.x * passes * bg::ROWS + wave * g::RPB + grp;
+    const int64_t row_base = rb * passes * bg::ROWS + wave * g::RPB + grp;
 
     // dphi of the next (row, expansion), prefetched
     float cn[EPL], sn[EPL];
     auto prefetch = [&](int e, int p) {
         const int64_t row = row_base + (int64_t)p * bg::ROWS;
-        const bool valid = e < E && row < batch;
+        const bool valid = e < e1 && row < batch;
         const uint32_t doff = valid ? (uint32_t)(row * 2 * (int64_t)nE) * 4u + 4u * (uint32_t)e * n : 0u;
         bload_row<M, P, VEC, 2>(cn, rD, doff, n, t, valid);
         bload_row<M, P, VEC, 2>(sn, rD, doff + 4u * nE, n, t, valid);
     };
-    prefetch(0, 0);
+    prefetch(e0, 0);
 
     auto ld_nat = [&](float (&v)[EPL], int base) {  // natural-order parameter, coalesced layout
         const float* b0 = prm + base + ct;
@@ -378,7 +382,7 @@ __global__ void __launch_bounds__(BwdGeo<M>::THREADS)
         }
     };
 
-    for (int e = 0; e < E; ++e) {
+    for (int e = e0; e < e1; ++e) {
         // stage the expansion's parameters (all earlier readers are done:
         // the previous expansion ended with a block barrier)
         {
@@ -499,7 +503,7 @@ __global__ void __launch_bounds__(BwdGeo<M>::THREADS)
                 if constexpr (VEC && EPL >= 4) {
                     // all reads first (from a clamped, always-valid address),
                     // then the adds and the masked writes: one LDS round trip
-                    if (e > 0) {
+                    if (e > e0) {
                         float4 o[NQ];
 #pragma unroll
                         for (int j = 0; j < EPL / 4; ++j) {
@@ -527,25 +531,27 @@ __global__ void __launch_bounds__(BwdGeo<M>::THREADS)
                     for (int k = 0; k < EPL; ++k) {
                         const uint32_t i = ct | rpart(M, P, 0, k);
                         if (valid && (int)i < d)
-                            drow[i] = e > 0 ? drow[i] + v[k] : v[k];
+                            drow[i] = e > e0 ? drow[i] + v[k] : v[k];
                     }
                 }
             }
         }
         if constexpr (PARAMS)
-            block_partials<M>(lds, aS, aG, aB, partial + (((int64_t)blockIdx.x * E + e) * 3) * n, wave, grp, t, cs);
+            block_partials<M>(lds, aS, aG, aB, partial + ((rb * E + e) * 3) * n, wave, grp, t, cs);
         else
             __syncthreads();  // the parameter stage is rewritten next
     }
     if (dx != nullptr) {
-        // every wave has added its last expansion: copy the rows out
+        // every wave has added its last expansion: copy the rows out (to
+        // the group's slice when the expansions are split)
         __syncthreads();
-        const int64_t row0 = (int64_t)blockIdx.x * passes * bg::ROWS;
+        const int64_t row0 = rb * passes * bg::ROWS;
         const int64_t left = batch - row0;
         const int nrows = left < (int64_t)passes * bg::ROWS ? (int)left : passes * bg::ROWS;
+        float* dxg = dx + eg * dx_group_stride;
         for (int r = 0; r < nrows; ++r)
             for (int i = threadIdx.x; i < d; i += bg::THREADS)
-                dx[(row0 + r) * d + i] = dxl[r * d4 + i];
+                dxg[(row0 + r) * d + i] = dxl[r * d4 + i];
     }
 }
 
@@ -703,7 +709,8 @@ struct RunBackward {
         };
 #define MCK_BWD_ARGS x, xb, dphi, db, batch, d, Ei, B, goff, Gk, S32, Sh, par_bytes, goff_bytes, cs, dx, partial, \
                      geo.passes
-#define MCK_BWDR_ARGS x, xb, dphi, db, batch, d, Ei, B, goff, Gk, S32, Sh, cs, dx, partial, geo.passes
+#define MCK_BWDR_ARGS x, xb, dphi, db, batch, d, Ei, B, goff, Gk, S32, Sh, cs, dx, partial, geo.passes, geo.esplit, \
+                      geo.rowblocks, (int64_t)batch * d
         hipError_t err;
         if constexpr (bg::XRES) {
             if (vec && M >= 2)
@@ -728,7 +735,7 @@ struct RunBackward {
 
 template <int M>
 struct RunGeometry {
-    static hipError_t run(int64_t batch, int d, BwdGeometry* out)
+    static hipError_t run(int64_t batch, int d, int64_t E, BwdGeometry* out)
     {
         using bg = BwdGeo<M>;
         // Blocks own contiguous runs of rows.  With the dx rows in LDS, one
@@ -749,6 +756,16 @@ struct RunGeometry {
         out->blocks = (units + passes - 1) / passes;
         if (out->blocks < 1)
             out->blocks = 1;
+        out->rowblocks = out->blocks;
+        out->esplit = 1;
+        if (bg::XRES && out->blocks < 256 && E > 1) {
+            // too few row blocks to fill the CUs: split the expansions over
+            // several block groups (each group's dx summed afterwards)
+            int64_t es = (256 + out->blocks - 1) / out->blocks;
+            es = es > E ? E : (es > 8 ? 8 : es);
+            out->esplit = (int)es;
+            out->blocks = out->rowblocks * es;
+        }
         out->block_threads = bg::THREADS;
         return hipSuccess;
     }
@@ -857,10 +874,10 @@ hipError_t launch_forward_group(int M, bool vec, const GroupInst* inst, int coun
     return dispatch_m<RunGroup>(M, vec, inst, count, s);
 }
 
-BwdGeometry backward_geometry(int M, int64_t batch, int d)
+BwdGeometry backward_geometry(int M, int64_t batch, int d, int64_t E)
 {
-    BwdGeometry g{1, 1, 64};
-    (void)dispatch_m<RunGeometry>(M, batch, d, &g);
+    BwdGeometry g{1, 1, 64, 1, 1};
+    (void)dispatch_m<RunGeometry>(M, batch, d, E, &g);
     return g;
 }
 

@@ -83,15 +83,22 @@ struct GroupInst {
 hipError_t launch_forward_group(int M, bool vec, const GroupInst* inst, int count, hipStream_t s);
 
 // Backward geometry: blocks, passes per block.
+// Backward launch shape: rowblocks blocks of passes x rows; for n <= 1024
+// with few row blocks the expansions are split over esplit block groups
+// (blocks = rowblocks x esplit), and group g writes its share of dx to
+// dx + g batch d (the caller sums the esplit slices).
 struct BwdGeometry {
     int64_t blocks;
     int passes;
     int block_threads;
+    int esplit;
+    int64_t rowblocks;
 };
-BwdGeometry backward_geometry(int M, int64_t batch, int d);
+BwdGeometry backward_geometry(int M, int64_t batch, int d, int64_t E);
 
-// Backward: dx (nullable) and, when partial != null, per-block partial sums
-// of dS, dG, dB (blocks x E x 3 x n) reduced afterwards by launch_reduce.
+// Backward: dx (nullable) and, when partial != null, per-row-block partial
+// sums of dS, dG, dB (rowblocks x E x 3 x n) reduced afterwards by
+// launch_reduce.
 hipError_t launch_backward(int M, bool vec, const float* x, const float* dphi, int64_t batch, int d, int64_t E,
                            const float* B, const uint32_t* goff, const float* Gk, const float* S32,
                            const float* Sh, float cs, float* dx, float* partial,
@@ -111,5 +118,20 @@ hipError_t launch_softmax_xent(const float* logits, const int32_t* labels, int64
 
 // y += alpha x over count floats.
 hipError_t launch_axpy(float* y, const float* x, int64_t count, float alpha, hipStream_t s);
+// Classifier head products, C in [1, 16] classes, F a multiple of 4, phi,
+// W, dphi 16-byte aligned, C F 4 < 2^31.
+// part: head_logit_slabs(F) x batch x C floats of scratch.
+int64_t head_logit_slabs(int64_t F);
+hipError_t launch_head_logits(const float* phi, const float* W, const float* b, int64_t batch, int64_t F, int C,
+                              float* part, float* logits, hipStream_t s);
+// Launch shape of launch_head_bwd: slabs of 1024 columns x groups of rows;
+// dW then needs groups x C x F floats of partials (summed by
+// launch_sum_groups) unless groups == 1.
+void head_bwd_geometry(int64_t batch, int64_t F, bool need_dW, int64_t* slabs, int64_t* groups,
+                       int64_t* rows_per_group);
+hipError_t launch_head_bwd(const float* phi, const float* dl, const float* W, int64_t batch, int64_t F, int C,
+                           int64_t slabs, int64_t groups, int64_t rows_per_group, float* dphi, float* part,
+                           hipStream_t s);
+hipError_t launch_sum_groups(const float* part, int64_t groups, int64_t count, float* out, hipStream_t s);
 
 }  // namespace mck

@@ -314,7 +314,7 @@ mck_status run_backward(const float* x, const float* dphi, int64_t batch, int64_
     const int64_t rows_per = lim / row_bytes < 1 ? 1 : lim / row_bytes;
     int64_t total_blocks = 0;
     for (int64_t r0 = 0; r0 < batch; r0 += rows_per)
-        total_blocks += mck::backward_geometry(M, batch - r0 < rows_per ? batch - r0 : rows_per, (int)d).blocks;
+        total_blocks += mck::backward_geometry(M, batch - r0 < rows_per ? batch - r0 : rows_per, (int)d, E).rowblocks;
     float* partial = nullptr;
     hipError_t err;
     if (want_params) {
@@ -328,11 +328,23 @@ mck_status run_backward(const float* x, const float* dphi, int64_t batch, int64_
     int64_t done_blocks = 0;
     for (int64_t r0 = 0; r0 < batch && err == hipSuccess; r0 += rows_per) {
         const int64_t rows = batch - r0 < rows_per ? batch - r0 : rows_per;
-        const mck::BwdGeometry geo = mck::backward_geometry(M, rows, (int)d);
+        const mck::BwdGeometry geo = mck::backward_geometry(M, rows, (int)d, E);
         float* part = partial ? partial + (size_t)done_blocks * E * 3 * n : nullptr;
-        err = mck::launch_backward(M, vec, x + r0 * d, dphi + r0 * 2 * n * E, rows, (int)d, E, B, goff, Gk, S32, Sh,
-                                   cs, dx ? dx + r0 * d : nullptr, part, geo, s);
-        done_blocks += geo.blocks;
+        float* dxr = dx ? dx + r0 * d : nullptr;
+        float* dxs = nullptr;  // per expansion group dx slices
+        if (dx && geo.esplit > 1) {
+            err = hipMallocAsync(reinterpret_cast<void**>(&dxs), (size_t)(geo.esplit * rows * d) * sizeof(float), s);
+            if (err != hipSuccess)
+                break;
+        }
+        err = mck::launch_backward(M, vec && (dxs == nullptr || aligned16(dxs)), x + r0 * d, dphi + r0 * 2 * n * E,
+                                   rows, (int)d, E, B, goff, Gk, S32, Sh, cs, dxs ? dxs : dxr, part, geo, s);
+        if (dxs) {
+            if (err == hipSuccess)
+                err = mck::launch_sum_groups(dxs, geo.esplit, rows * d, dxr, s);
+            (void)hipFreeAsync(dxs, s);
+        }
+        done_blocks += geo.rowblocks;
     }
     if (err == hipSuccess && want_params)
         err = mck::launch_reduce(partial, total_blocks, E, n, dS, dG, dB, s);
@@ -719,7 +731,7 @@ mck_status mck_fastfood_backward_p(const float* x, const float* dphi, int64_t ba
         hipError_t err = hipSuccess;
         for (float* o : {dB, dG, dS})
             if (o && err == hipSuccess)
-                err = hipMemsetAsync(o, 0, (size_t)(n * E) * sizeof(float), s);
+                err = mck::launch_sum_groups(nullptr, 0, n * E, o, s);  // a fill kernel: zeros
         return err == hipSuccess ? MCK_OK : hip_fail(err, "zero gradients");
     }
     TempPlan tp;
@@ -729,6 +741,90 @@ mck_status mck_fastfood_backward_p(const float* x, const float* dphi, int64_t ba
     st = run_backward(x, dphi, batch, d, n, E, B, tp.goffB, tp.GkB, S, tp.Sh, dx, dB, dG, dS, s);
     (void)hipFreeAsync(tp.block, s);
     return st;
+}
+
+static mck_status check_head(int64_t batch, int64_t F, int64_t C);
+
+mck_status mck_fastfood_train_step(const float* x, const int32_t* labels, int64_t batch, int64_t d, int64_t n,
+                                   int64_t E, int64_t C, float* W, float* b, float* B, const int32_t* perm, float* G,
+                                   float* S, float lr, float* loss, float* logits, float* dW, float* db, float* dB,
+                                   float* dG, float* dS, float* dx, mck_stream stream)
+{
+    mck_status st = check_explicit(batch, d, n, E, B, perm, G, S);
+    if (st != MCK_OK)
+        return st;
+    if (batch < 1)
+        return fail(MCK_ERR_INVALID_ARG, "batch must be >= 1 (the loss is a mean over rows)");
+    const int64_t F = 2 * n * E;
+    st = check_head(batch, F, C);
+    if (st != MCK_OK)
+        return st;
+    if (!x || !labels || !W || !b || !loss || !dW || !db || !dB || !dG || !dS)
+        return fail(MCK_ERR_INVALID_ARG, "x, labels, W, b, loss or a parameter gradient is NULL");
+    if (!aligned16(W) || !aligned16(dW))
+        return fail(MCK_ERR_INVALID_ARG, "W and dW must be 16-byte aligned");
+    if (!std::isfinite(lr))
+        return fail(MCK_ERR_INVALID_ARG, "lr must be finite");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // scratch: phi, dphi, logits (when the caller passes none), dlogits, row
+    // losses, head partials
+    int64_t slabs = 0, groups = 0, rpg = 0;
+    mck::head_bwd_geometry(batch, F, true, &slabs, &groups, &rpg);
+    const int64_t lpart = mck::head_logit_slabs(F) * batch * C;
+    const int64_t hpart = groups > 1 ? groups * C * F : 0;
+    const size_t zf = align_up((size_t)(batch * F) * 4), zl = align_up((size_t)(batch * C) * 4),
+                 zr = align_up((size_t)batch * 4), zp = align_up((size_t)(lpart > hpart ? lpart : hpart) * 4);
+    void* block = nullptr;
+    hipError_t err = hipMallocAsync(&block, 2 * zf + 2 * zl + zr + zp, s);
+    if (err != hipSuccess)
+        return fail(MCK_ERR_NO_MEMORY, std::string("training step scratch: ") + hipGetErrorString(err));
+    char* base = static_cast<char*>(block);
+    float* phi = reinterpret_cast<float*>(base);
+    float* dphi = reinterpret_cast<float*>(base + zf);
+    float* lg = logits ? logits : reinterpret_cast<float*>(base + 2 * zf);
+    float* dl = reinterpret_cast<float*>(base + 2 * zf + zl);
+    float* row_loss = reinterpret_cast<float*>(base + 2 * zf + 2 * zl);
+    float* part = reinterpret_cast<float*>(base + 2 * zf + 2 * zl + zr);
+    TempPlan tp;
+    st = make_temp_plan(n, E, perm, G, S, s, &tp);
+    if (st != MCK_OK) {
+        (void)hipFreeAsync(block, s);
+        return st;
+    }
+    const int M = log2i(n);
+    err = mck::launch_forward(M, vec_ok(x, phi, d, n), true, x, batch, (int)d, E, B, tp.goffF, tp.GsF, tp.Sh,
+                              feature_scale(n, E), phi, s);
+    if (err == hipSuccess)
+        err = mck::launch_head_logits(phi, W, b, batch, F, (int)C, part, lg, s);
+    if (err == hipSuccess)
+        err = mck::launch_softmax_xent(lg, labels, batch, (int)C, row_loss, dl, loss, db, s);
+    if (err == hipSuccess)
+        err = mck::launch_head_bwd(phi, dl, W, batch, F, (int)C, slabs, groups, rpg, dphi, groups > 1 ? part : dW, s);
+    if (err == hipSuccess && groups > 1)
+        err = mck::launch_sum_groups(part, groups, C * F, dW, s);
+    if (err == hipSuccess) {
+        st = run_backward(x, dphi, batch, d, n, E, B, tp.goffB, tp.GkB, S, tp.Sh, dx, dB, dG, dS, s);
+        if (st != MCK_OK) {
+            (void)hipFreeAsync(tp.block, s);
+            (void)hipFreeAsync(block, s);
+            return st;
+        }
+    }
+    if (err == hipSuccess && lr != 0.f) {
+        const float a = -lr;
+        err = mck::launch_axpy(W, dW, C * F, a, s);
+        if (err == hipSuccess)
+            err = mck::launch_axpy(b, db, C, a, s);
+        if (err == hipSuccess)
+            err = mck::launch_axpy(B, dB, n * E, a, s);
+        if (err == hipSuccess)
+            err = mck::launch_axpy(G, dG, n * E, a, s);
+        if (err == hipSuccess)
+            err = mck::launch_axpy(S, dS, n * E, a, s);
+    }
+    (void)hipFreeAsync(tp.block, s);
+    (void)hipFreeAsync(block, s);
+    return err == hipSuccess ? MCK_OK : hip_fail(err, "training step launch");
 }
 
 mck_status mck_gen_boxmuller(const uint32_t* a, const uint32_t* b, int64_t count, float* g0, float* g1,
@@ -763,6 +859,77 @@ mck_status mck_softmax_xent(const float* logits, const int32_t* labels, int64_t 
     if (err != hipSuccess)
         return hip_fail(err, "softmax cross-entropy launch");
     return MCK_OK;
+}
+
+static mck_status check_head(int64_t batch, int64_t F, int64_t C)
+{
+    if (batch < 0)
+        return fail(MCK_ERR_INVALID_ARG, "batch must be >= 0");
+    if (F < 4 || F % 4 != 0)
+        return fail(MCK_ERR_INVALID_ARG, "F must be a positive multiple of 4");
+    if (C < 1 || C > 16)
+        return fail(C < 1 ? MCK_ERR_INVALID_ARG : MCK_ERR_UNSUPPORTED, "C must be in [1, 16]");
+    if (C * F > (int64_t(1) << 29) - 1024)
+        return fail(MCK_ERR_UNSUPPORTED, "C * F must stay below 2^29 (W within 2 GiB)");
+    return MCK_OK;
+}
+
+mck_status mck_head_logits(const float* phi, const float* W, const float* b, int64_t batch, int64_t F, int64_t C,
+                           float* logits, mck_stream stream)
+{
+    mck_status st = check_head(batch, F, C);
+    if (st != MCK_OK)
+        return st;
+    if (batch == 0)
+        return MCK_OK;
+    if (!phi || !W || !logits)
+        return fail(MCK_ERR_INVALID_ARG, "phi, W or logits is NULL");
+    if (!aligned16(phi) || !aligned16(W))
+        return fail(MCK_ERR_INVALID_ARG, "phi and W must be 16-byte aligned");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    float* part = nullptr;
+    hipError_t err = hipMallocAsync(reinterpret_cast<void**>(&part),
+                                    (size_t)(mck::head_logit_slabs(F) * batch * C) * sizeof(float), s);
+    if (err != hipSuccess)
+        return fail(MCK_ERR_NO_MEMORY, std::string("head logits partials: ") + hipGetErrorString(err));
+    err = mck::launch_head_logits(phi, W, b, batch, F, (int)C, part, logits, s);
+    (void)hipFreeAsync(part, s);
+    return err == hipSuccess ? MCK_OK : hip_fail(err, "head logits launch");
+}
+
+mck_status mck_head_backward(const float* phi, const float* dlogits, const float* W, int64_t batch, int64_t F,
+                             int64_t C, float* dphi, float* dW, mck_stream stream)
+{
+    mck_status st = check_head(batch, F, C);
+    if (st != MCK_OK)
+        return st;
+    if (!dphi && !dW)
+        return MCK_OK;
+    if ((batch > 0 && !dlogits) || (dphi && !W) || (dW && batch > 0 && !phi))
+        return fail(MCK_ERR_INVALID_ARG, "dlogits, W or phi is NULL");
+    if ((dphi && (!aligned16(dphi) || !aligned16(W))) || (dW && (!aligned16(dW) || (batch > 0 && !aligned16(phi)))))
+        return fail(MCK_ERR_INVALID_ARG, "phi, W, dphi and dW must be 16-byte aligned");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int64_t slabs = 0, groups = 0, rpg = 0;
+    mck::head_bwd_geometry(batch, F, dW != nullptr, &slabs, &groups, &rpg);
+    if (dW && groups != 1) {
+        // partials per row group, then a fixed-order sum (zeros for an empty batch)
+        float* part = nullptr;
+        hipError_t err = hipSuccess;
+        if (groups > 0) {
+            err = hipMallocAsync(reinterpret_cast<void**>(&part), (size_t)(groups * C * F) * sizeof(float), s);
+            if (err != hipSuccess)
+                return fail(MCK_ERR_NO_MEMORY, std::string("head partials: ") + hipGetErrorString(err));
+        }
+        err = mck::launch_head_bwd(phi, dlogits, W, batch, F, (int)C, slabs, groups, rpg, dphi, part, s);
+        if (err == hipSuccess)
+            err = mck::launch_sum_groups(part, groups, C * F, dW, s);
+        if (part)
+            (void)hipFreeAsync(part, s);
+        return err == hipSuccess ? MCK_OK : hip_fail(err, "head backward launch");
+    }
+    const hipError_t err = mck::launch_head_bwd(phi, dlogits, W, batch, F, (int)C, slabs, groups, rpg, dphi, dW, s);
+    return err == hipSuccess ? MCK_OK : hip_fail(err, "head backward launch");
 }
 
 mck_status mck_axpy(float* y, const float* x, int64_t count, float alpha, mck_stream stream)

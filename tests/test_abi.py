@@ -100,6 +100,26 @@ def test_validation_without_gpu(lib):
     assert _st(lib, prm, 1, 8, 1, 0.0, 0, null, null, null, null, null, null) == 1
     assert _st(lib, prm, 1, 8, 1, 1.0, 9, null, null, null, null, null, null) == 1
     assert _st(lib, prm, 1, 4096, 1, 1.0, 1, null, null, null, null, null, null) == 2
+    # head products: F not a multiple of 4, too many classes, NULL pointers,
+    # nothing requested is a no-op
+    p16 = ctypes.c_void_p(16)
+    assert _st(lib, "mck_head_logits", p16, p16, null, 2, 6, 10, p16, null) == 1
+    assert _st(lib, "mck_head_logits", p16, p16, null, 2, 8, 17, p16, null) == 2
+    assert _st(lib, "mck_head_logits", p16, p16, null, 2, 8, 0, p16, null) == 1
+    assert _st(lib, "mck_head_logits", null, p16, null, 2, 8, 10, p16, null) == 1
+    assert _st(lib, "mck_head_logits", p16, ctypes.c_void_p(20), null, 2, 8, 10, p16, null) == 1
+    assert _st(lib, "mck_head_logits", null, null, null, 0, 8, 10, null, null) == 0
+    assert _st(lib, "mck_head_backward", p16, null, p16, 2, 8, 10, p16, p16, null) == 1
+    assert _st(lib, "mck_head_backward", null, null, null, 2, 8, 10, null, null, null) == 0
+    assert _st(lib, "mck_head_backward", p16, p16, p16, 2, 8, 10, ctypes.c_void_p(24), null, null) == 1
+    # training step: empty batch, too many classes, NULL gradients, bad lr
+    ts = "mck_fastfood_train_step"
+    args = lambda batch, C, dW, lr: (p16, p16, batch, 8, 8, 1, C, p16, p16, p16, p16, p16, p16, ctypes.c_float(lr),
+                                     p16, null, dW, p16, p16, p16, p16, null, null)
+    assert _st(lib, ts, *args(0, 10, p16, 0.1)) == 1
+    assert _st(lib, ts, *args(4, 17, p16, 0.1)) == 2
+    assert _st(lib, ts, *args(4, 10, null, 0.1)) == 1
+    assert _st(lib, ts, *args(4, 10, p16, float("nan"))) == 1
     # generator self-check: negative count, NULL pointers
     assert _st(lib, "mck_gen_boxmuller", null, null, -1, null, null, null) == 1
     assert _st(lib, "mck_gen_boxmuller", null, null, 5, null, null, null) == 1

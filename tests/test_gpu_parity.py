@@ -213,7 +213,8 @@ def _oracle_grads(orc, x, dphi, E, seed, sigma):
 
 @pytest.mark.parametrize("d,E,batch,sigma", [(784, 1, 64, 1.0), (784, 3, 37, 2.0), (5, 2, 70, 1.0),
                                              (32, 2, 33, 4.0), (300, 2, 50, 10.0), (1024, 2, 19, 2.0),
-                                             (2048, 1, 9, 30.0), (4096, 1, 5, 50.0), (32768, 1, 2, 180.0)])
+                                             (2048, 1, 9, 30.0), (4096, 1, 5, 50.0), (32768, 1, 2, 180.0),
+                                             (784, 5, 1000, 2.0)])
 def test_backward_parity(mk, torch_mod, orc, d, E, batch, sigma):
     torch = torch_mod
     n = mk.padded_dim(d)
