@@ -311,6 +311,7 @@ __global__ void __launch_bounds__(kPermChunk) k_gen_perm(uint32_t seed, int64_t 
 }
 
 constexpr int kNormThreads = 256;
+constexpr int kNormLevels = 24 - 8 + 1;  // n <= 2^24 over 256 lanes
 
 // ||G_e||^2 as the canonical pairwise sum of the squares in index order:
 // each lane sums an aligned power-of-two chunk with the same tree (binary
@@ -323,7 +324,8 @@ __global__ void __launch_bounds__(kNormThreads) k_gen_norm2(int64_t n, const flo
     const int64_t chunk = n / lanes;
     const float* g = G + (int64_t)blockIdx.x * n;
     if ((int64_t)threadIdx.x < lanes) {
-        double stack[16];
+        // a chunk of 2^L elements needs levels 0..L; L <= 24 - 8 here
+        double stack[kNormLevels];
         const float* c = g + threadIdx.x * chunk;
         for (int64_t k = 0; k < chunk; ++k) {
             double cur = (double)c[k] * (double)c[k];
@@ -467,6 +469,8 @@ hipError_t launch_generate(uint32_t seed, int64_t n, int64_t E, double sigma, in
 {
     if (matern_t > 0 && n > kMaternThreads * kMaternMaxCnt)
         return hipErrorInvalidValue;
+    if (n > (int64_t(1) << (kNormLevels - 1 + 8)))
+        return hipErrorInvalidValue;  // beyond the pairwise stack of k_gen_norm2
     const int64_t pairs = (n / 2) * E;
     k_gen_bg<<<dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, s>>>(seed, n, E, B, G);
     const int use_lds = n * 4 <= 128 * 1024 ? 1 : 0;

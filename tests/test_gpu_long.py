@@ -52,7 +52,18 @@ def test_fwht_long_float(mk, orc, m):
     assert rowwise_rel(got, ref).max() <= 1e-6
 
 
-@pytest.mark.parametrize("d,E,batch", [(40000, 2, 3), (1 << 17, 1, 2), (70001, 3, 9)])
+@pytest.mark.parametrize("m", [16, 20, 24])
+def test_long_params_bit_exact(mk, orc, m):
+    # the generator at the largest sizes: 2^16 elements per norm lane at 2^24
+    n = 1 << m
+    p = mk.params(4242, n, 1, float(np.sqrt(n)))
+    ref = orc.params(4242, n, 1, float(np.sqrt(n)))
+    for k, r in (("B", "B"), ("perm", "perm"), ("G", "G"), ("S", "S32"), ("S64", "S64")):
+        assert np.array_equal(p[k].cpu().numpy(), ref[r]), k
+
+
+@pytest.mark.parametrize("d,E,batch", [(40000, 2, 3), (1 << 17, 1, 2), (70001, 3, 9), ((1 << 20) + 3, 1, 2),
+                                       (1 << 24, 1, 1)])
 def test_forward_long_matches_oracle(mk, orc, d, E, batch):
     import torch
 
@@ -107,6 +118,20 @@ def test_long_x16_input(mk, orc):
     phi = mk.forward(x, E, 1, 256.0, out_dtype=torch.bfloat16)
     ref, _, _ = orc.forward(x.float().cpu().numpy().astype(np.float64), E, 1, 256.0)
     assert rowwise_rel(phi.float().cpu().numpy(), ref).max() <= 2.5e-3
+
+
+@pytest.mark.parametrize("name", ["bfloat16", "float16"])
+def test_long_x16_ragged_input(mk, orc, name):
+    # d not a multiple of 4: element-wise 16-bit loads in the first column pass
+    import torch
+
+    dt = getattr(torch, name)
+    d, E = 40001, 2
+    x = torch.from_numpy(workloads.normal(3, d, seed=4)).cuda().to(dt)
+    phi = mk.forward(x, E, 3, 200.0, out_dtype=dt)
+    ref, _, _ = orc.forward(x.float().cpu().numpy().astype(np.float64), E, 3, 200.0)
+    tol = {"bfloat16": 2.5e-3, "float16": 3e-4}[name]
+    assert rowwise_rel(phi.float().cpu().numpy(), ref).max() <= tol
 
 
 def test_long_single_pass_only_calls_refuse(mk):
