@@ -47,7 +47,7 @@ hipError_t launch_forward_t(int M, bool vec, int xt, int yt, const void* x, int6
 hipError_t launch_fwht_long(int M, float* data, int64_t batch, bool vec, hipStream_t s);
 hipError_t launch_forward_long(int M, bool vec, int xt, int yt, const void* x, int64_t batch, int d, int64_t E,
                                const float* B, const uint32_t* packA, const uint16_t* dstB, const int32_t* pdelta,
-                               const float* G, const float* Sh, float cs, void* phi, float* u, float* w,
+                               const float* Gx, const float* Sh, float cs, void* phi, float* u, float* w,
                                hipStream_t s);
 // Pi (destination i takes source perm[i]) of each expansion as an exchange
 // between the C = n / 2^15 chunks of 2^15 elements.  The exchange buffer T
@@ -59,10 +59,11 @@ hipError_t launch_forward_long(int M, bool vec, int xt, int yt, const void* x, i
 //       element s and goes to destination chunk co;
 //   pdelta [ci C + co]: its position in T is q + pdelta[ci][co];
 //   dstB [co 2^15 + p]: T position co 2^15 + p lands at element dstB of
-//       destination chunk co.
+//       destination chunk co;
+//   Gx [co 2^15 + p]: G of that element (G in T order).
 // scratch: E C (3C + 2) ints.
-hipError_t launch_buckets(int M, int64_t E, const int32_t* perm, uint32_t* packA, uint16_t* dstB, int32_t* pdelta,
-                          int32_t* scratch, hipStream_t s);
+hipError_t launch_buckets(int M, int64_t E, const int32_t* perm, const float* G, uint32_t* packA, uint16_t* dstB,
+                          int32_t* pdelta, float* Gx, int32_t* scratch, hipStream_t s);
 hipError_t launch_sh(const double* S64, float* Sh, int64_t count, hipStream_t s);
 
 // Grouped forward (FP32 x and phi, n = 2^M <= 2^15): several feature maps

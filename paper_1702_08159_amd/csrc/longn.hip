@@ -50,109 +50,152 @@ struct RowArgs {
     float* dst;
     const float* src;
     int64_t rows, chunks;
-    const float* G;          // kInBucket: G of the expansion
+    const float* Gx;         // kInBucket: G of the expansion in exchange order
     const uint32_t* packA;   // kOutBucket
     const int32_t* pdelta;   // kOutBucket
     const uint16_t* dstB;    // kInBucket
 };
 
-// XCD-aware (row, chunk) of a row-pass block: blocks are dealt to the 8 XCDs
-// round robin; XCD x takes rows x, x + 8, ... one after another, all chunks
-// of a row together.
-__device__ __forceinline__ void row_chunk(int64_t rows, int64_t chunks, int64_t& r, int64_t& c)
+// XCD-aware (row slot, chunk) of a row-pass block: blocks are dealt to the
+// 8 XCDs round robin; XCD x takes slots x, x + 8, ... one after another, all
+// chunks of a slot together.
+__device__ __forceinline__ void slot_chunk(int64_t chunks, int64_t& slot, int64_t& c)
 {
     const int64_t b = blockIdx.x;
     const int64_t xcd = b % kXcds, q = b / kXcds;
-    r = (q / chunks) * kXcds + xcd;
+    slot = (q / chunks) * kXcds + xcd;
     c = q % chunks;
 }
 
-// One 2^15 chunk per block: H_{2^15} of the chunk's input, output to dst
-// (rows of length n = chunks 2^15).
+// One 2^15 chunk c of RB consecutive rows per block: H_{2^15} of each row's
+// chunk input, output to dst (rows of length n = chunks 2^15).
 //   kInRow:    the chunk of src (natural order)
 //   kInBucket: G o (the elements Pi sends to this chunk), read from the
-//              chunk's part of the exchange buffer src
+//              chunk's part of the exchange buffer src and scaled by G in
+//              the same order before they are placed in LDS
 //   kOutRow:    natural order
 //   kOutBucket: every element to its place in the exchange buffer dst
-template <int IN, int OUT, bool VEC>
+// The chunk's dstB is loaded once per block, and the
+// next row's input is loaded into registers while the current row is
+// transformed and stored: one block fills a CU's LDS, so this is where its
+// HBM latency hides.
+template <int IN, int OUT, bool VEC, int RB>
 __global__ void __launch_bounds__(RG::BLOCK) k_rows(RowArgs a)
 {
     constexpr int M = kRowM, P = kRowP, EPL = RG::EPL, K = RG::K, BLOCK = RG::BLOCK, NQ = EPL / 4;
     constexpr int64_t CH = RG::n;
     __shared__ float lds[RG::LDS_FLOATS];
-    int64_t r, c;
-    row_chunk(a.rows, a.chunks, r, c);
-    if (r >= a.rows)
+    int64_t slot, c;
+    slot_chunk(a.chunks, slot, c);
+    const int64_t r0 = slot * RB;
+    if (r0 >= a.rows)
         return;  // uniform per block
+    const int nr = a.rows - r0 < RB ? (int)(a.rows - r0) : RB;
     const int64_t n = a.chunks * CH;
     const uint32_t t = threadIdx.x;
     const uint32_t tb = tpart<M, P, 0>(t);
-    float v[EPL];
-    if constexpr (IN == kInRow) {
-        bload_row<M, P, VEC>(v, make_rsrc(a.src + r * n + c * CH, (uint32_t)(CH * 4)), 0u, (int)CH, t, true);
-    } else {
-        // lane t holds exchange positions 4 (j BLOCK + t) + {0..3}
-        const rsrc_t rs = make_rsrc(a.src + r * n + c * CH, (uint32_t)(CH * 4));
+
+    // the chunk's plan data: dstB stays in VGPRs for all rows; G (in
+    // exchange order) and packA are re-read per row (L2) to leave room for
+    // the prefetched row
+    [[maybe_unused]] u32x2_t di[NQ];
+    if constexpr (IN == kInBucket) {
         const rsrc_t rd = make_rsrc(a.dstB + c * CH, (uint32_t)(CH * 2));
-        float val[NQ][4];
-        u32x2_t di[NQ];
 #pragma unroll
-        for (int j = 0; j < NQ; ++j) {
-            bload4(val[j], rs, 16u * (j * BLOCK + t), 0u);
+        for (int j = 0; j < NQ; ++j)
             di[j] = __builtin_bit_cast(u32x2_t, __builtin_amdgcn_raw_buffer_load_b64(rd, (int)(8u * (j * BLOCK + t)), 0, 0));
-        }
-        float gq[EPL];
-        bload_coal<M, P>(gq, make_rsrc(a.G + c * CH, (uint32_t)(CH * 4)), 0u, t);
-#pragma unroll
-        for (int j = 0; j < NQ; ++j) {
-            lds[phys<P>(di[j].x & 0x7fffu)] = val[j][0];
-            lds[phys<P>((di[j].x >> 16) & 0x7fffu)] = val[j][1];
-            lds[phys<P>(di[j].y & 0x7fffu)] = val[j][2];
-            lds[phys<P>((di[j].y >> 16) & 0x7fffu)] = val[j][3];
-        }
-        __syncthreads();
-        lds_get<M, P, 0>(lds, t, v);
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < EPL; ++k)
-            v[k] *= gq[k];
     }
+    __shared__ int32_t sdel[OUT == kOutBucket ? kMaxChunks : 1];
     if constexpr (OUT == kOutBucket) {
-        // lane t sends source-order positions q = 4 (j BLOCK + t) + {0..3}
-        __shared__ int32_t sdel[kMaxChunks];
         const int C = (int)a.chunks;
         for (int i = (int)t; i < C; i += BLOCK)
             sdel[i] = a.pdelta[c * C + i];
-        const rsrc_t ra = make_rsrc(a.packA + c * CH, (uint32_t)(CH * 4));
-        uint32_t pk[NQ][4];
-#pragma unroll
-        for (int j = 0; j < NQ; ++j)
-            bload4u(pk[j], ra, 16u * (j * BLOCK + t), 0u);
-        fwht_up<M, P>(v, lds, t);
-        lds_put<M, P, K>(lds, t, v);
-        __syncthreads();
-        const rsrc_t ro = make_rsrc(a.dst + r * n, (uint32_t)(n * 4));
-#pragma unroll
-        for (int j = 0; j < NQ; ++j)
-#pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                const uint32_t q = 4u * (j * BLOCK + t) + m;
-                const uint32_t w = pk[j][m];
-                const int32_t pos = (int32_t)q + sdel[(w >> kRowM) & (kMaxChunks - 1)];
-                bstore1(ro, 4u * (uint32_t)pos, 0u, lds[phys<P>(w & 0x7fffu)]);
-            }
-    } else {
-        const rsrc_t ro = make_rsrc(a.dst + r * n + c * CH, (uint32_t)(CH * 4));
-        fwht_up<M, P>(v, lds, t);
-        relayout<M, P, K, 0>(v, lds, t);
-        if constexpr (VEC || IN != kInRow) {
-#pragma unroll
-            for (int j = 0; j < EPL / 4; ++j)
-                bstore4(ro, 4u * (tb | rpart(M, P, 0, 4 * j)), v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]);
+    }
+
+    // the row input: layout 0 (kInRow) or exchange order, 4 per float4 (kInBucket)
+    float nxt[EPL];
+    auto load_input = [&](int64_t r) {
+        const rsrc_t rs = make_rsrc(a.src + r * n + c * CH, (uint32_t)(CH * 4));
+        if constexpr (IN == kInRow) {
+            bload_row<M, P, VEC>(nxt, rs, 0u, (int)CH, t, true);
         } else {
 #pragma unroll
-            for (int k = 0; k < EPL; ++k)
-                bstore1(ro, 4u * tb, 4u * rpart(M, P, 0, k), v[k]);
+            for (int j = 0; j < NQ; ++j)
+                bload4(&nxt[4 * j], rs, 16u * (j * BLOCK + t), 0u);
+        }
+    };
+    load_input(r0);
+
+    for (int k = 0; k < nr; ++k) {
+        const int64_t r = r0 + k;
+        if (k > 0)
+            __syncthreads();  // the previous row's last LDS reads are done
+        float v[EPL];
+        if constexpr (IN == kInBucket) {
+            {
+                const rsrc_t rg = make_rsrc(a.Gx + c * CH, (uint32_t)(CH * 4));
+#pragma unroll
+                for (int j = 0; j < NQ; ++j) {
+                    float gx[4];
+                    bload4(gx, rg, 16u * (j * BLOCK + t), 0u);
+#pragma unroll
+                    for (int m = 0; m < 4; ++m)
+                        nxt[4 * j + m] *= gx[m];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < NQ; ++j) {
+                lds[phys<P>(di[j].x & 0x7fffu)] = nxt[4 * j];
+                lds[phys<P>((di[j].x >> 16) & 0x7fffu)] = nxt[4 * j + 1];
+                lds[phys<P>(di[j].y & 0x7fffu)] = nxt[4 * j + 2];
+                lds[phys<P>((di[j].y >> 16) & 0x7fffu)] = nxt[4 * j + 3];
+            }
+            if (k + 1 < nr)
+                load_input(r + 1);
+            __syncthreads();
+            lds_get<M, P, 0>(lds, t, v);
+            __syncthreads();
+        } else {
+#pragma unroll
+            for (int q = 0; q < EPL; ++q)
+                v[q] = nxt[q];
+            if (k + 1 < nr)
+                load_input(r + 1);
+        }
+        [[maybe_unused]] uint32_t pk[NQ][4];
+        if constexpr (OUT == kOutBucket) {
+            const rsrc_t ra = make_rsrc(a.packA + c * CH, (uint32_t)(CH * 4));
+#pragma unroll
+            for (int j = 0; j < NQ; ++j)
+                bload4u(pk[j], ra, 16u * (j * BLOCK + t), 0u);
+        }
+        fwht_up<M, P>(v, lds, t);
+        if constexpr (OUT == kOutBucket) {
+            lds_put<M, P, K>(lds, t, v);
+            __syncthreads();
+            const rsrc_t ro = make_rsrc(a.dst + r * n, (uint32_t)(n * 4));
+#pragma unroll
+            for (int j = 0; j < NQ; ++j)
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const uint32_t q = 4u * (j * BLOCK + t) + m;
+                    const uint32_t w = pk[j][m];
+                    const int32_t pos = (int32_t)q + sdel[(w >> kRowM) & (kMaxChunks - 1)];
+                    bstore1(ro, 4u * (uint32_t)pos, 0u, lds[phys<P>(w & 0x7fffu)]);
+                }
+        } else {
+            const rsrc_t ro = make_rsrc(a.dst + r * n + c * CH, (uint32_t)(CH * 4));
+            relayout<M, P, K, 0>(v, lds, t);
+            if constexpr (VEC || IN != kInRow) {
+#pragma unroll
+                for (int j = 0; j < EPL / 4; ++j)
+                    bstore4(ro, 4u * (tb | rpart(M, P, 0, 4 * j)), v[4 * j], v[4 * j + 1], v[4 * j + 2],
+                            v[4 * j + 3]);
+            } else {
+#pragma unroll
+                for (int q = 0; q < EPL; ++q)
+                    bstore1(ro, 4u * tb, 4u * rpart(M, P, 0, q), v[q]);
+            }
         }
     }
 }
@@ -355,21 +398,36 @@ hipError_t col_passes(int M, float* data, int64_t rows, const void* x, int d, co
     return hipSuccess;
 }
 
+// Rows per row-pass block: as many as keep at least 512 blocks (two per CU).
 template <int IN, int OUT>
 hipError_t row_pass(bool vec, const RowArgs& a, hipStream_t st)
 {
-    const int64_t blocks = ((a.rows + kXcds - 1) / kXcds) * kXcds * a.chunks;
+    const int rb = a.rows * a.chunks >= 2048 ? 4 : (a.rows * a.chunks >= 1024 ? 2 : 1);
+    const int64_t slots = (a.rows + rb - 1) / rb;
+    const int64_t blocks = ((slots + kXcds - 1) / kXcds) * kXcds * a.chunks;
     const dim3 grid((unsigned)blocks), blk(RG::BLOCK);
-    if (vec)
-        k_rows<IN, OUT, true><<<grid, blk, 0, st>>>(a);
+#define MCK_ROWS(RBV)                                                                                              \
+    do {                                                                                                          \
+        if constexpr (IN != kInRow || OUT != kOutRow)                                                             \
+            k_rows<IN, OUT, true, RBV><<<grid, blk, 0, st>>>(a); /* exchange buffers are aligned */               \
+        else if (vec)                                                                                             \
+            k_rows<IN, OUT, true, RBV><<<grid, blk, 0, st>>>(a);                                                  \
+        else                                                                                                      \
+            k_rows<IN, OUT, false, RBV><<<grid, blk, 0, st>>>(a);                                                 \
+    } while (0)
+    if (rb == 4)
+        MCK_ROWS(4);
+    else if (rb == 2)
+        MCK_ROWS(2);
     else
-        k_rows<IN, OUT, false><<<grid, blk, 0, st>>>(a);
+        MCK_ROWS(1);
+#undef MCK_ROWS
     return hipGetLastError();
 }
 
 template <int XT, int YT>
 hipError_t forward_long(int M, bool vec, const void* x, int64_t batch, int d, int64_t E, const float* B,
-                        const uint32_t* packA, const uint16_t* dstB, const int32_t* pdelta, const float* G,
+                        const uint32_t* packA, const uint16_t* dstB, const int32_t* pdelta, const float* Gx,
                         const float* Sh, float cs, void* phi, float* u, float* w, hipStream_t st)
 {
     const int64_t n = int64_t(1) << M, C = n >> kRowM;
@@ -381,7 +439,7 @@ hipError_t forward_long(int M, bool vec, const void* x, int64_t batch, int d, in
         const RowArgs a{w, u, batch, C, nullptr, packA + e * n, pdelta + e * C * C, nullptr};
         if (err == hipSuccess)
             err = row_pass<kInRow, kOutBucket>(true, a, st);
-        const RowArgs b{u, w, batch, C, G + e * n, nullptr, nullptr, dstB + e * n};
+        const RowArgs b{u, w, batch, C, Gx + e * n, nullptr, nullptr, dstB + e * n};
         if (err == hipSuccess)
             err = row_pass<kInBucket, kOutRow>(true, b, st);
         if (err == hipSuccess)
@@ -480,6 +538,16 @@ __global__ void __launch_bounds__(512)
     }
 }
 
+// Gx[e][co 2^15 + p] = G[e][co 2^15 + dstB[e][co 2^15 + p]]: G in the
+// order the receiving row pass reads the exchange buffer.
+__global__ void k_bucket_gx(const float* __restrict__ G, const uint16_t* __restrict__ dstB, int64_t count,
+                            float* __restrict__ Gx)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count)
+        Gx[i] = G[(i & ~(int64_t)(RG::n - 1)) + dstB[i]];
+}
+
 }  // namespace
 
 hipError_t launch_sh(const double* S64, float* Sh, int64_t count, hipStream_t s)
@@ -502,12 +570,12 @@ hipError_t launch_fwht_long(int M, float* data, int64_t batch, bool vec, hipStre
 
 hipError_t launch_forward_long(int M, bool vec, int xt, int yt, const void* x, int64_t batch, int d, int64_t E,
                                const float* B, const uint32_t* packA, const uint16_t* dstB, const int32_t* pdelta,
-                               const float* G, const float* Sh, float cs, void* phi, float* u, float* w,
+                               const float* Gx, const float* Sh, float cs, void* phi, float* u, float* w,
                                hipStream_t s)
 {
     if (M <= kRowM || M > 24)
         return hipErrorInvalidValue;
-#define MCK_FL_ARGS M, vec, x, batch, d, E, B, packA, dstB, pdelta, G, Sh, cs, phi, u, w, s
+#define MCK_FL_ARGS M, vec, x, batch, d, E, B, packA, dstB, pdelta, Gx, Sh, cs, phi, u, w, s
     if (xt == kF32 && yt == kF32)
         return forward_long<kF32, kF32>(MCK_FL_ARGS);
     if (xt == kF32 && yt == kBF16)
@@ -522,8 +590,8 @@ hipError_t launch_forward_long(int M, bool vec, int xt, int yt, const void* x, i
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_buckets(int M, int64_t E, const int32_t* perm, uint32_t* packA, uint16_t* dstB, int32_t* pdelta,
-                          int32_t* scratch, hipStream_t s)
+hipError_t launch_buckets(int M, int64_t E, const int32_t* perm, const float* G, uint32_t* packA, uint16_t* dstB,
+                          int32_t* pdelta, float* Gx, int32_t* scratch, hipStream_t s)
 {
     if (M <= kRowM || M > 24)
         return hipErrorInvalidValue;
@@ -539,6 +607,7 @@ hipError_t launch_buckets(int M, int64_t E, const int32_t* perm, uint32_t* packA
     k_bucket_pre<<<dim3(tb), dim3(256), 0, s>>>(counts, seg, E, C, pre, pdelta);
     const int threads = C < 64 ? 64 : C;
     k_bucket_fill<<<dim3(blocks), dim3((unsigned)threads), 0, s>>>(perm, n, C, seg, pre, packA, dstB);
+    k_bucket_gx<<<dim3((unsigned)((n * E + 255) / 256)), dim3(256), 0, s>>>(G, dstB, n * E, Gx);
     return hipGetLastError();
 }
 

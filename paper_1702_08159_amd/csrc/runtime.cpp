@@ -137,6 +137,7 @@ struct Plan {
     uint32_t* packA = nullptr;
     uint16_t* dstB = nullptr;
     int32_t* pdelta = nullptr;
+    float* Gx = nullptr;
     int32_t* bscratch = nullptr;  // build scratch
 };
 
@@ -190,11 +191,11 @@ mck_status get_plan(uint32_t seed, int64_t n, int64_t E, double sigma, int calib
     mck::plan_elems(log2i(n), &gf, &gb);
     const size_t C = n > MCK_MAX_N ? (size_t)(n / MCK_MAX_N) : 0;
     const size_t ecc = (size_t)E * C * C * 4;
-    size_t off[15], total = 0;
-    const size_t sz[15] = {en * 4, en * 4, en * 4, en * 8, en * 4, (size_t)E * 8,
+    size_t off[16], total = 0;
+    const size_t sz[16] = {en * 4, en * 4, en * 4, en * 8, en * 4, (size_t)E * 8,
                            (size_t)gf * E * 4, en * 4, (size_t)gb * E * 4, en * 4, en * 4,
-                           C ? en * 4 : 0, C ? en * 2 : 0, ecc, 3 * ecc + (size_t)E * C * 8};
-    for (int i = 0; i < 15; ++i) {
+                           C ? en * 4 : 0, C ? en * 2 : 0, ecc, 3 * ecc + (size_t)E * C * 8, C ? en * 4 : 0};
+    for (int i = 0; i < 16; ++i) {
         off[i] = total;
         total += align_up(sz[i]);
     }
@@ -233,6 +234,7 @@ mck_status get_plan(uint32_t seed, int64_t n, int64_t E, double sigma, int calib
         p.dstB = reinterpret_cast<uint16_t*>(b + off[12]);
         p.pdelta = reinterpret_cast<int32_t*>(b + off[13]);
         p.bscratch = reinterpret_cast<int32_t*>(b + off[14]);
+        p.Gx = reinterpret_cast<float*>(b + off[15]);
     }
     int matern_t = 0;
     {
@@ -248,7 +250,7 @@ mck_status get_plan(uint32_t seed, int64_t n, int64_t E, double sigma, int calib
                             : mck::launch_derive(log2i(n), E, p.perm, p.G, p.S64, p.S32, p.goffF, p.GsF, p.goffB,
                                                  p.GkB, p.Sh, stream);
     if (err == hipSuccess && n > MCK_MAX_N)
-        err = mck::launch_buckets(log2i(n), E, p.perm, p.packA, p.dstB, p.pdelta, p.bscratch, stream);
+        err = mck::launch_buckets(log2i(n), E, p.perm, p.G, p.packA, p.dstB, p.pdelta, p.Gx, p.bscratch, stream);
     if (err == hipSuccess)
         err = hipStreamSynchronize(stream);  // the plan may be used from other streams next
     if (err != hipSuccess) {
@@ -463,7 +465,7 @@ static mck_status forward_long(const Plan* p, const void* x, int xt, int64_t bat
     for (int64_t r0 = 0; r0 < batch && err == hipSuccess; r0 += rows_per) {
         const int64_t rows = batch - r0 < rows_per ? batch - r0 : rows_per;
         err = mck::launch_forward_long(log2i(n), vec, xt, yt, static_cast<const char*>(x) + r0 * d * xb, rows,
-                                       (int)d, E, p->B, p->packA, p->dstB, p->pdelta, p->G, p->Sh, cs,
+                                       (int)d, E, p->B, p->packA, p->dstB, p->pdelta, p->Gx, p->Sh, cs,
                                        static_cast<char*>(phi) + r0 * row_phi, u, w, s);
     }
     (void)hipFreeAsync(u, s);
