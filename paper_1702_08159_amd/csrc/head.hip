@@ -102,7 +102,7 @@ __global__ void __launch_bounds__(kHeadThreads)
 // of the R C sums is reduced over the wave (xor butterfly) and the four
 // waves (fixed order) into part[slab][r][c].  Rows past the batch read zero
 // (empty range) and are not written.
-constexpr int kLogitRows = 4;
+constexpr int kLogitRows = 8;
 constexpr int kLogitSlab4 = 1024;  // float4 columns per slab
 
 template <int C, int R>
@@ -207,29 +207,43 @@ __global__ void __launch_bounds__(kHeadThreads)
         for (int m = 0; m < 4; ++m)
             acc[k][m] = 0.f;
     }
-#pragma unroll 8
-    for (int64_t r = rb; r < re; ++r) {
-        float dlr[C];
-#pragma unroll
-        for (int k = 0; k < C; ++k)
-            dlr[k] = dl[r * C + k];
+    // eight rows at a time, all loads issued before any store (the compiler
+    // does not move buffer loads across buffer stores); rows past the group
+    // read zero and are not stored
+    constexpr int U = 8;
+    for (int64_t r = rb; r < re; r += U) {
+        float p[U][4];
         if (part != nullptr) {
-            float p[4];
-            bload4<2>(p, make_rsrc(phi + r * F, (uint32_t)(F * 4)), (uint32_t)(16 * q), 0u);
 #pragma unroll
-            for (int k = 0; k < C; ++k)
-#pragma unroll
-                for (int m = 0; m < 4; ++m)
-                    acc[k][m] += dlr[k] * p[m];
+            for (int u = 0; u < U; ++u)
+                bload4<2>(p[u], make_rsrc(phi + (r + u) * F, r + u < re ? (uint32_t)(F * 4) : 0u), (uint32_t)(16 * q),
+                          0u);
         }
-        if (dphi != nullptr) {
-            float o[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (r + u >= re)
+                break;
+            float dlr[C];
 #pragma unroll
             for (int k = 0; k < C; ++k)
+                dlr[k] = dl[(r + u) * C + k];
+            if (part != nullptr) {
 #pragma unroll
-                for (int m = 0; m < 4; ++m)
-                    o[m] += dlr[k] * wq[k][m];
-            bstore4_nt(make_rsrc(dphi + r * F, (uint32_t)(F * 4)), (uint32_t)(16 * q), o[0], o[1], o[2], o[3]);
+                for (int k = 0; k < C; ++k)
+#pragma unroll
+                    for (int m = 0; m < 4; ++m)
+                        acc[k][m] += dlr[k] * p[u][m];
+            }
+            if (dphi != nullptr) {
+                float o[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int k = 0; k < C; ++k)
+#pragma unroll
+                    for (int m = 0; m < 4; ++m)
+                        o[m] += dlr[k] * wq[k][m];
+                bstore4_nt(make_rsrc(dphi + (r + u) * F, (uint32_t)(F * 4)), (uint32_t)(16 * q), o[0], o[1], o[2],
+                           o[3]);
+            }
         }
     }
     if (part != nullptr) {
