@@ -43,12 +43,14 @@ METRIC = "Fastfood vectors/s + %HBM peak at n=1024 E=16, fwd and fwd+bwd vs orac
 # this workload, scaled by what the same counters read for a 1 GiB device
 # copy (FETCH_SIZE reads half the bytes copied, WRITE_SIZE all of them).
 # Keyed by a hash of the kernel sources; any change to them voids the entry.
-KERNEL_SOURCES = ("paper_1702_08159_amd/csrc/kernels.hip", "paper_1702_08159_amd/csrc/engine.hpp",
+# the sources that define the dominant kernel (k_forward): the counters below
+# are valid only while these are unchanged
+KERNEL_SOURCES = ("paper_1702_08159_amd/csrc/forward.hpp", "paper_1702_08159_amd/csrc/engine.hpp",
                   "paper_1702_08159_amd/csrc/layout.hpp")
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 TRAFFIC_KIB = {
     # sha1 of the kernel sources: (FETCH_SIZE KiB, WRITE_SIZE KiB) per launch
-    "fc8cf48079665303b388639ea95c1a92fc583094": (13863.0, 1048579.1),
+    "554d2d83cf70e2959412dd0d1de13ce21b02b03b": (13863.0, 1048622.9),
 }
 
 

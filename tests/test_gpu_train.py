@@ -95,6 +95,10 @@ def test_train_step_matches_oracle(mk, orc, batch, E):
     assert abs(float(out["loss"]) - ref["loss"]) <= TOL * abs(ref["loss"])
     for k in ("logits", "dW", "db", "dx", "dB", "dG", "dS"):
         assert rel(out[k].cpu().numpy(), ref[k]) <= TOL, k
+    # every sum has a fixed order: a second call repeats bit for bit
+    again = mk.train_step(dev(x), dev(y), dev(W), dev(b), B, perm, G, S, need_dx=True)
+    for k in ("loss", "logits", "dW", "db", "dx", "dB", "dG", "dS"):
+        assert torch.equal(out[k], again[k]), k
 
 
 def test_sgd_steps_reduce_loss(mk, orc):
@@ -107,7 +111,10 @@ def test_sgd_steps_reduce_loss(mk, orc):
     losses = [float(mk.train_step(xs, ys, Wt, bt, B, perm, G, S, lr=0.5)["loss"]) for _ in range(5)]
     assert all(np.isfinite(losses))
     assert losses[-1] < losses[0]
-    # the update is exactly w - lr * grad: check W after one more step
-    W0 = Wt.clone()
+    # the update is w - lr * grad for all five parameters (grad taken
+    # before the update): check them after one more step
+    before = {k: t.clone() for k, t in (("W", Wt), ("b", bt), ("B", B), ("G", G), ("S", S))}
     out = mk.train_step(xs, ys, Wt, bt, B, perm, G, S, lr=0.5)
-    np.testing.assert_allclose(Wt.cpu().numpy(), (W0 - 0.5 * out["dW"]).cpu().numpy(), rtol=0, atol=1e-6)
+    for k, t in (("W", Wt), ("b", bt), ("B", B), ("G", G), ("S", S)):
+        want = (before[k] - 0.5 * out["d" + k]).cpu().numpy()
+        np.testing.assert_allclose(t.cpu().numpy(), want, rtol=0, atol=1e-6 * max(1.0, np.abs(want).max()))
