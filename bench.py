@@ -85,7 +85,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the Fastfood map has no cross-GPU step "
-              "(rows shard with zero communication), and this build runs on a single GPU", file=sys.stderr)
+              "(rows shard with zero communication); run it with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -50,7 +50,7 @@ extern "C" {
 typedef enum mck_status {
     MCK_OK = 0,
     MCK_ERR_INVALID_ARG = 1, /* bad size, pointer, sigma, ... (nothing enqueued) */
-    MCK_ERR_UNSUPPORTED = 2, /* valid request this build does not implement */
+    MCK_ERR_UNSUPPORTED = 2, /* valid request the library does not implement */
     MCK_ERR_HIP = 3,         /* a HIP runtime call or kernel launch failed */
     MCK_ERR_NO_MEMORY = 4    /* device allocation failed */
 } mck_status;
