@@ -141,13 +141,17 @@ __device__ __forceinline__ void forward_body(const void* __restrict__ x, uint32_
             bload_row_t<M, P, VEC, XT>(xn, rx, xoff, d, t, valid);
             bload_coal<M, P>(v, rB, eo4, t);
             bload_lane<M, P, float>(gs, rG, eo4, t);
-            bload_lane<M, P, uint32_t>(off, rO, 4u * (uint32_t)e * kGoffE, lane);
 #pragma unroll
             for (int r = 0; r < EPL; ++r)
                 v[r] *= xn[r];
         }
 
         fwht_up<M, P>(v, buf, t);
+        // without the pipeline (P = 5: 32 values per lane) the gather offsets
+        // are loaded only now, which keeps the transform within 128 VGPRs
+        // (loaded with the rest they spilled and cost a quarter of the speed)
+        if constexpr (!PIPE)
+            bload_lane<M, P, uint32_t>(off, rO, 4u * (uint32_t)e * kGoffE, lane);
 
         // G Pi v1 = Pi (G' v1) with G' = G in source order: scale, write v1 to
         // LDS in natural order, gather v1[perm[i]]
