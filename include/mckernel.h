@@ -243,7 +243,8 @@ mck_status mck_softmax_xent(const float* logits, const int32_t* labels, int64_t 
  * batch x C.  F must be a multiple of 4 and phi, W, dphi, dW 16-byte
  * aligned (MCK_ERR_INVALID_ARG otherwise); C F < 2^29 (MCK_ERR_UNSUPPORTED
  * otherwise).  b may be NULL (no bias); dphi or dW may be NULL (not
- * computed).  Every sum runs in a fixed order, so results are
+ * computed); for a non-empty batch W and dlogits must be valid, and phi
+ * when dW is requested.  Every sum runs in a fixed order, so results are
  * deterministic.  Partial sums live in scratch allocated on `stream`
  * (stream-ordered): batch C F / 4096 floats for the logits, at most 32 C F
  * for dW.  An empty batch gives dW = 0.

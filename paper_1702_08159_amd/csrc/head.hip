@@ -198,8 +198,8 @@ __global__ void __launch_bounds__(kHeadThreads)
         return;
     const int64_t rb = g * rows_per_group;
     const int64_t re = rb + rows_per_group < batch ? rb + rows_per_group : batch;
-    const rsrc_t rw = make_rsrc(W, (uint32_t)(C * F * 4));
     float wq[C][4], acc[C][4];
+    const rsrc_t rw = make_rsrc(W, dphi != nullptr ? (uint32_t)(C * F * 4) : 0u);  // W only for dphi
 #pragma unroll
     for (int k = 0; k < C; ++k) {
         bload4(wq[k], rw, (uint32_t)(16 * (k * F4 + q)), 0u);

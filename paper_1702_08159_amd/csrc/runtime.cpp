@@ -336,8 +336,11 @@ mck_status run_backward(const float* x, const float* dphi, int64_t batch, int64_
         float* dxs = nullptr;  // per expansion group dx slices
         if (dx && geo.esplit > 1) {
             err = hipMallocAsync(reinterpret_cast<void**>(&dxs), (size_t)(geo.esplit * rows * d) * sizeof(float), s);
-            if (err != hipSuccess)
-                break;
+            if (err != hipSuccess) {
+                if (partial)
+                    (void)hipFreeAsync(partial, s);
+                return fail(MCK_ERR_NO_MEMORY, std::string("backward dx slices: ") + hipGetErrorString(err));
+            }
         }
         err = mck::launch_backward(M, vec && (dxs == nullptr || aligned16(dxs)), x + r0 * d, dphi + r0 * 2 * n * E,
                                    rows, (int)d, E, B, goff, Gk, S32, Sh, cs, dxs ? dxs : dxr, part, geo, s);
@@ -907,7 +910,7 @@ mck_status mck_head_backward(const float* phi, const float* dlogits, const float
         return st;
     if (!dphi && !dW)
         return MCK_OK;
-    if ((batch > 0 && !dlogits) || (dphi && !W) || (dW && batch > 0 && !phi))
+    if (batch > 0 && (!dlogits || !W || (dW && !phi)))
         return fail(MCK_ERR_INVALID_ARG, "dlogits, W or phi is NULL");
     if ((dphi && (!aligned16(dphi) || !aligned16(W))) || (dW && (!aligned16(dW) || (batch > 0 && !aligned16(phi)))))
         return fail(MCK_ERR_INVALID_ARG, "phi, W, dphi and dW must be 16-byte aligned");

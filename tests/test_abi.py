@@ -111,6 +111,7 @@ def test_validation_without_gpu(lib):
     assert _st(lib, "mck_head_logits", null, null, null, 0, 8, 10, null, null) == 0
     assert _st(lib, "mck_head_backward", p16, null, p16, 2, 8, 10, p16, p16, null) == 1
     assert _st(lib, "mck_head_backward", null, null, null, 2, 8, 10, null, null, null) == 0
+    assert _st(lib, "mck_head_backward", p16, p16, null, 2, 8, 10, null, p16, null) == 1  # dW only, W NULL
     assert _st(lib, "mck_head_backward", p16, p16, p16, 2, 8, 10, ctypes.c_void_p(24), null, null) == 1
     # training step: empty batch, too many classes, NULL gradients, bad lr
     ts = "mck_fastfood_train_step"
