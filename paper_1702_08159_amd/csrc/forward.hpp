@@ -18,7 +18,9 @@ constexpr int kXcds = 8;
 // 128-VGPR budget of 4 waves per SIMD only at 16 elements per lane; the
 // transform kernel has no such pipeline and uses 32.  n = 2^15 needs 32 so
 // that one row fits in a 1024-thread workgroup.
-constexpr int fwd_p(int M) { return M >= 15 ? 5 : 4; }
+// register bits per layout: 4 (16 values per lane) up to 2^13; 5 from 2^14,
+// where rows span 8 (2^14) or 16 (2^15) waves and fewer relayouts win
+constexpr int fwd_p(int M) { return M >= 14 ? 5 : 4; }
 constexpr int bwd_p(int M) { return M >= 15 ? 5 : 4; }
 constexpr int kFwhtP = 5;
 
@@ -212,8 +214,18 @@ __device__ __forceinline__ void forward_body(const void* __restrict__ x, uint32_
     }
 }
 
+// Minimum blocks per CU passed to the compiler: 4 for rows of one wave or
+// less; 4 for the 512-lane blocks of n = 2^14, which holds that kernel at
+// 128 VGPRs (a hint of 2 gave 129 and three waves per SIMD), so two blocks
+// share a CU (their LDS fits); otherwise 1.
+template <int M, int P>
+constexpr int fwd_min_blocks()
+{
+    return !Geo<M, P>::kMulti ? 4 : (P == 5 && Geo<M, P>::BLOCK < 1024 ? 4 : 1);
+}
+
 template <int M, int P, bool VEC, bool TRIG, int XT = kF32, int YT = kF32>
-__global__ void __launch_bounds__((Geo<M, P>::BLOCK), (Geo<M, P>::kMulti ? 1 : 4))
+__global__ void __launch_bounds__((Geo<M, P>::BLOCK), (fwd_min_blocks<M, P>()))
     k_forward(const void* __restrict__ x, uint32_t x_bytes, int64_t batch, int d, int E, int echunk, int nchunks,
               const float* __restrict__ B, const uint32_t* __restrict__ goff, const float* __restrict__ Gs,
               const float* __restrict__ Sx, uint32_t par_bytes, uint32_t goff_bytes, float cs,
@@ -249,7 +261,7 @@ struct FwdGroup {
 };
 
 template <int M, int P, bool VEC>
-__global__ void __launch_bounds__((Geo<M, P>::BLOCK), (Geo<M, P>::kMulti ? 1 : 4)) k_forward_group(FwdGroup grp)
+__global__ void __launch_bounds__((Geo<M, P>::BLOCK), (fwd_min_blocks<M, P>())) k_forward_group(FwdGroup grp)
 {
     __shared__ float lds[Geo<M, P>::LDS_FLOATS];
     const int64_t b = blockIdx.x;
