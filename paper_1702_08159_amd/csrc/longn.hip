@@ -98,13 +98,7 @@ __global__ void __launch_bounds__(RG::BLOCK) k_rows(RowArgs a)
     // the chunk's plan data: dstB stays in VGPRs for all rows; G (in
     // exchange order) and packA are re-read per row (L2) to leave room for
     // the prefetched row
-    [[maybe_unused]] u32x2_t di[NQ];
-    if constexpr (IN == kInBucket) {
-        const rsrc_t rd = make_rsrc(a.dstB + c * CH, (uint32_t)(CH * 2));
-#pragma unroll
-        for (int j = 0; j < NQ; ++j)
-            di[j] = __builtin_bit_cast(u32x2_t, __builtin_amdgcn_raw_buffer_load_b64(rd, (int)(8u * (j * BLOCK + t)), 0, 0));
-    }
+    [[maybe_unused]] const rsrc_t rd = make_rsrc(a.dstB + c * CH, (uint32_t)(CH * 2));
     __shared__ int32_t sdel[OUT == kOutBucket ? kMaxChunks : 1];
     if constexpr (OUT == kOutBucket) {
         const int C = (int)a.chunks;
@@ -132,6 +126,11 @@ __global__ void __launch_bounds__(RG::BLOCK) k_rows(RowArgs a)
             __syncthreads();  // the previous row's last LDS reads are done
         float v[EPL];
         if constexpr (IN == kInBucket) {
+            u32x2_t di[NQ];
+#pragma unroll
+            for (int j = 0; j < NQ; ++j)
+                di[j] = __builtin_bit_cast(u32x2_t,
+                                           __builtin_amdgcn_raw_buffer_load_b64(rd, (int)(8u * (j * BLOCK + t)), 0, 0));
             {
                 const rsrc_t rg = make_rsrc(a.Gx + c * CH, (uint32_t)(CH * 4));
 #pragma unroll
