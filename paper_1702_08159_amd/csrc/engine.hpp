@@ -71,7 +71,7 @@ __device__ __forceinline__ void stages(LaneArr<float, M, P>& v)
 // float4 LDS access is used for the coalesced layout when row regions are
 // 16-byte aligned.
 template <int M, int P, int ID>
-constexpr bool lds_vec() { return ID == 0 && M > P; }
+constexpr bool lds_vec() { return (ID == 0 || ID == kSW) && M > P; }
 
 template <int M, int P, int ID>
 __device__ __forceinline__ void lds_put(float* buf, uint32_t t, const LaneArr<float, M, P>& v)
@@ -122,11 +122,59 @@ __device__ __forceinline__ void relayout(LaneArr<float, M, P>& v, float* buf, ui
     lds_sync<M, P>();
 }
 
-// H v, starting in layout 0 and ending in the last chunk layout.
+// Exchange register bits P-2 and P-1 with lane bits 4 and 5 (layout 0 <->
+// layout kSW).  v_permlane16_swap(a, b) swaps the odd 16-lane rows of a with
+// the even rows of b; applied to the registers (r, r + 2^k) it transposes
+// register bit k with lane bit 4, and v_permlane32_swap does the same with
+// lane bit 5 (halves of the wave).  Each is its own inverse.
+template <int M, int P>
+__device__ __forceinline__ void swap_hi(LaneArr<float, M, P>& v)
+{
+    constexpr int EPL = Geo<M, P>::EPL;
+    static_assert(Geo<M, P>::kSwap, "swapped layout needs one vector per 64 lanes");
+#pragma unroll
+    for (int r = 0; r < EPL; ++r) {
+        if (r & (1 << (P - 2)))
+            continue;
+        const auto q = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[r]), __float_as_uint(v[r | (1 << (P - 2))]),
+                                                        false, false);
+        v[r] = __uint_as_float(q[0]);
+        v[r | (1 << (P - 2))] = __uint_as_float(q[1]);
+    }
+#pragma unroll
+    for (int r = 0; r < EPL; ++r) {
+        if (r & (1 << (P - 1)))
+            continue;
+        const auto q = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[r]), __float_as_uint(v[r | (1 << (P - 1))]),
+                                                        false, false);
+        v[r] = __uint_as_float(q[0]);
+        v[r | (1 << (P - 1))] = __uint_as_float(q[1]);
+    }
+}
+
+// bits visited by the swapped transform: layout 0, kSW, chunk 1
+template <int M, int P>
+constexpr bool swap_covers()
+{
+    return (reg_mask(M, P, 0) | reg_mask(M, P, kSW) | reg_mask(M, P, 1)) == (1u << M) - 1u;
+}
+
+// H v, starting in layout 0 and ending in layout GL (the last chunk layout,
+// or chunk 1 in the swapped geometry).
 template <int M, int P>
 __device__ __forceinline__ void fwht_up(LaneArr<float, M, P>& v, float* buf, uint32_t t)
 {
     constexpr int K = Geo<M, P>::K;
+    if constexpr (Geo<M, P>::kSwap) {
+        static_assert(swap_covers<M, P>(), "layouts 0, kSW and 1 must cover every bit");
+        constexpr uint32_t m0 = reg_mask(M, P, 0), ms = reg_mask(M, P, kSW);
+        stages<M, P, 0, m0>(v);
+        swap_hi<M, P>(v);
+        stages<M, P, kSW, ms & ~m0>(v);
+        relayout<M, P, kSW, 1>(v, buf, t);
+        stages<M, P, 1, reg_mask(M, P, 1) & ~(m0 | ms)>(v);
+        return;
+    }
     stages<M, P, 0, up_new_bits(M, P, 0)>(v);
     if constexpr (K >= 1) {
         relayout<M, P, 0, 1>(v, buf, t);
@@ -143,11 +191,20 @@ __device__ __forceinline__ void fwht_up(LaneArr<float, M, P>& v, float* buf, uin
     static_assert(K <= 3, "at most three chunk layouts");
 }
 
-// H v, starting in the last chunk layout and ending in layout 0.
+// H v, starting in layout GL and ending in layout 0.
 template <int M, int P>
 __device__ __forceinline__ void fwht_down(LaneArr<float, M, P>& v, float* buf, uint32_t t)
 {
     constexpr int K = Geo<M, P>::K;
+    if constexpr (Geo<M, P>::kSwap) {
+        constexpr uint32_t m1 = reg_mask(M, P, 1), ms = reg_mask(M, P, kSW);
+        stages<M, P, 1, m1>(v);
+        relayout<M, P, 1, kSW>(v, buf, t);
+        stages<M, P, kSW, ms & ~m1>(v);
+        swap_hi<M, P>(v);
+        stages<M, P, 0, reg_mask(M, P, 0) & ~(m1 | ms)>(v);
+        return;
+    }
     if constexpr (K >= 3) {
         stages<M, P, 3, down_new_bits(M, P, K, 3)>(v);
         relayout<M, P, 3, 2>(v, buf, t);

@@ -160,7 +160,7 @@ __device__ __forceinline__ void forward_body(const void* __restrict__ x, uint32_
 #pragma unroll
         for (int r = 0; r < EPL; ++r)
             v[r] *= gs[r];
-        lds_put<M, P, K>(buf, t, v);
+        lds_put<M, P, g::GL>(buf, t, v);
         lds_sync<M, P>();
 #pragma unroll
         for (int r = 0; r < EPL; ++r)

@@ -46,7 +46,7 @@ __global__ void __launch_bounds__((Geo<M, kFwhtP>::BLOCK))
     bload_row<M, P, VEC>(v, r, rowoff, g::n, t, valid);
     fwht_up<M, P>(v, buf, t);
     if constexpr (K >= 1)
-        relayout<M, P, K, 0>(v, buf, t);
+        relayout<M, P, g::GL, 0>(v, buf, t);
     const uint32_t tb4 = 4u * tpart<M, P, 0>(t);
     if constexpr (VEC) {
 #pragma unroll
@@ -102,14 +102,14 @@ __device__ __forceinline__ void block_partials(float* lds, const LaneArr<float, 
     using g = Geo<M, P>;
     constexpr int EPL = g::EPL, n = g::n, K = g::K, SLOTS = bg::NW * g::RPB;
     float* slot = lds + (wave * g::RPB + grp) * n;
-    const uint32_t ct = tpart<M, P, 0>(t), tk = tpart<M, P, K>(t);
+    const uint32_t ct = tpart<M, P, 0>(t), tk = tpart<M, P, g::GL>(t);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         __syncthreads();
         if (a == 1) {
 #pragma unroll
             for (int r = 0; r < EPL; ++r)
-                slot[tk | rpart(M, P, K, r)] = aG[r];
+                slot[tk | rpart(M, P, g::GL, r)] = aG[r];
         } else {
             const float* acc = a == 0 ? aS : aB;
 #pragma unroll
@@ -183,7 +183,7 @@ __global__ void __launch_bounds__(BwdGeo<M>::THREADS)
             uint32_t off[EPL];
             bload_lane<M, P, uint32_t>(off, rO, go4, lane);
             fwht_up<M, P>(v, buf, t);
-            lds_put<M, P, K>(buf, t, v);
+            lds_put<M, P, g::GL>(buf, t, v);
             lds_sync<M, P>();
             float w[EPL];
 #pragma unroll
@@ -237,7 +237,7 @@ __global__ void __launch_bounds__(BwdGeo<M>::THREADS)
             for (int r = 0; r < EPL; ++r)
                 *reinterpret_cast<float*>(lbytes + off[r]) = v[r];
             lds_sync<M, P>();
-            lds_get<M, P, K>(buf, t, v);
+            lds_get<M, P, g::GL>(buf, t, v);
             lds_sync<M, P>();
             // g0 = H g1 (ends in the coalesced layout); dB += g0 xhat; dx += B g0
             fwht_down<M, P>(v, buf, t);
@@ -426,7 +426,7 @@ __global__ void __launch_bounds__(BwdGeo<M>::THREADS)
             for (int r = 0; r < EPL; ++r)
                 v[r] = xh[r] * q[r];
             fwht_up<M, P>(v, buf, t);
-            lds_put<M, P, K>(buf, t, v);
+            lds_put<M, P, g::GL>(buf, t, v);
             lds_sync<M, P>();
             float w[EPL];
             {
@@ -487,7 +487,7 @@ __global__ void __launch_bounds__(BwdGeo<M>::THREADS)
                     *reinterpret_cast<float*>(lbytes + __float_as_uint(of[r])) = v[r];
             }
             lds_sync<M, P>();
-            lds_get<M, P, K>(buf, t, v);
+            lds_get<M, P, g::GL>(buf, t, v);
             lds_sync<M, P>();
             // g0 = H g1 (coalesced layout); dB += g0 xhat; dx += B g0
             fwht_down<M, P>(v, buf, t);
@@ -614,12 +614,12 @@ template <int M, int P>
 __device__ __forceinline__ uint32_t lane_major_slot(uint32_t i)
 {
     using g = Geo<M, P>;
-    constexpr int K = g::K;
+    constexpr int L = g::GL;
     uint32_t r = 0, t = 0;
     for (int b = 0; b < g::Q; ++b)
-        r |= ((i >> reg_bit(M, P, K, b)) & 1u) << b;
+        r |= ((i >> reg_bit(M, P, L, b)) & 1u) << b;
     for (int b = 0; b < g::T; ++b)
-        t |= ((i >> thr_bit(M, P, K, b)) & 1u) << b;
+        t |= ((i >> thr_bit(M, P, L, b)) & 1u) << b;
     return t * g::EPL + r;
 }
 
@@ -640,12 +640,12 @@ __global__ void k_derive(int64_t E, const int32_t* __restrict__ perm, const floa
     const int r = (int)(q % EPL);
     const uint32_t grp = g::kMulti ? 0u : lane / g::LPR;
     const uint32_t t = g::kMulti ? lane : lane % g::LPR;
-    const uint32_t i = tpart<M, P, K>(t) | rpart(M, P, K, r);
+    const uint32_t i = tpart<M, P, g::GL>(t) | rpart(M, P, g::GL, r);
     const uint32_t src = (uint32_t)perm[e * n + i] & (uint32_t)(n - 1);
     goff[idx] = 4u * (grp * (uint32_t)g::STRIDE + phys<P>(src));
     if (q < (uint32_t)n) {
         const uint32_t tq = q / EPL;
-        const uint32_t iq = tpart<M, P, K>(tq) | rpart(M, P, K, (int)(q % EPL));
+        const uint32_t iq = tpart<M, P, g::GL>(tq) | rpart(M, P, g::GL, (int)(q % EPL));
         if (Gk)
             Gk[e * n + q] = G[e * n + iq];
         if (Gs) {

@@ -18,6 +18,12 @@
 //   layout k >= 1 ("chunk k"): register bits = the Q consecutive bits ending
 //     at min(Qk+1, M-Q+1) (clamped at bit 0); the chunks together cover bits
 //     2 .. M-Q+1.
+//   layout kSW ("swapped"), only when one vector fills exactly the 64 lanes
+//     of a wave (M - Q = 6): layout 0 with its two top register bits
+//     exchanged for lane bits 4 and 5 (index bits 6 and 7) by the cross-lane
+//     swaps v_permlane16_swap / v_permlane32_swap, which move data between
+//     the lanes of a wave without LDS.  A transform then visits layout 0,
+//     kSW and chunk 1 with a single LDS round trip.
 // For M <= P every bit is a register bit (one lane per vector).
 #pragma once
 
@@ -34,6 +40,11 @@ constexpr int cmin(int a, int b) { return a < b ? a : b; }
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
 constexpr int nreg_bits(int M, int P) { return M < P ? M : P; }
+
+constexpr int kSW = 7;  // id of the swapped layout
+
+// one vector per wave over all 64 lanes: the swapped layout applies
+constexpr bool swap_geo(int M, int P) { return M > P && M - P == 6; }
 
 // LDS position of index i: 4 floats of padding after every 2^(P+2).  The
 // lanes of one wave-half then hit 32 distinct banks in every layout, float4
@@ -59,6 +70,10 @@ struct Geo {
     static constexpr int BLOCK = kMulti ? LPR : 64;
     static constexpr int RPB = kMulti ? 1 : 64 / LPR;  // vectors (rows) per wave
     static constexpr int K = M > P ? (M - P + P - 1) / P : 0;  // chunk layouts
+    // The forward transform ("up") ends, and the inverse-order one
+    // ("down") starts, in layout GL: the layout of the Pi gather/scatter.
+    static constexpr bool kSwap = swap_geo(M, P);
+    static constexpr int GL = kSwap ? 1 : K;
     // LDS footprint of one vector, and of one row region including padding
     // that spreads the row groups of one wave over banks (and keeps float4
     // alignment where float4 access is used)
@@ -75,6 +90,8 @@ constexpr int reg_bit(int M, int P, int id, int b)
         return b;
     if (id == 0)
         return b < 2 ? b : M - P + b;
+    if (id == kSW)  // layout 0 with register bits P-2, P-1 <-> lane bits 4, 5 (index bits 6, 7)
+        return b < P - 2 ? reg_bit(M, P, 0, b) : 6 + (b - (P - 2));
     int top = cmin(P * id + 1, M - P + 1);
     int lo = cmax(top - P + 1, 0);
     return lo + b;
@@ -96,9 +113,13 @@ constexpr uint32_t reg_mask(int M, int P, int id)
     return m;
 }
 
-// index bit held by lane bit b in layout `id` (non-register bits, ascending)
+// index bit held by lane bit b in layout `id` (non-register bits, ascending;
+// in the swapped layout lane bits 4 and 5 hold layout 0's two top register
+// bits)
 constexpr int thr_bit(int M, int P, int id, int b)
 {
+    if (id == kSW && M > P && b >= 4)
+        return b < 6 ? reg_bit(M, P, 0, P - 2 + (b - 4)) : -1;
     int cnt = 0;
     for (int k = 0; k < M; ++k)
         if (!is_reg_bit(M, P, id, k)) {

@@ -170,7 +170,7 @@ __global__ void __launch_bounds__(RG::BLOCK) k_rows(RowArgs a)
         }
         fwht_up<M, P>(v, lds, t);
         if constexpr (OUT == kOutBucket) {
-            lds_put<M, P, K>(lds, t, v);
+            lds_put<M, P, RG::GL>(lds, t, v);
             __syncthreads();
             const rsrc_t ro = make_rsrc(a.dst + r * n, (uint32_t)(n * 4));
 #pragma unroll
@@ -184,7 +184,7 @@ __global__ void __launch_bounds__(RG::BLOCK) k_rows(RowArgs a)
                 }
         } else {
             const rsrc_t ro = make_rsrc(a.dst + r * n + c * CH, (uint32_t)(CH * 4));
-            relayout<M, P, K, 0>(v, lds, t);
+            relayout<M, P, RG::GL, 0>(v, lds, t);
             if constexpr (VEC || IN != kInRow) {
 #pragma unroll
                 for (int j = 0; j < EPL / 4; ++j)
