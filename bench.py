@@ -249,10 +249,31 @@ def main():
             torch.cuda.synchronize()
             res[name] = t0.elapsed_time(t1) / args.batched_steps
             log("32 uneven maps, %s: %.3f ms" % (name, res[name]))
+        # the autotuner picks a register split and grid target per n on this
+        # set; then the batched call again
+        tt = time.perf_counter()
+        chosen = mk.autotune_batched(maps, outs=outs, reps=2)
+        tune_s = time.perf_counter() - tt
+        log("autotuner: %.1f s, %s" % (tune_s, chosen))
+        run_batched()
+        torch.cuda.synchronize()
+        t0.record(stream)
+        for _ in range(args.batched_steps):
+            run_batched()
+        t1.record(stream)
+        torch.cuda.synchronize()
+        res["tuned"] = t0.elapsed_time(t1) / args.batched_steps
+        log("32 uneven maps, batched after tuning: %.3f ms" % res["tuned"])
+        for n_k in chosen:
+            mk.set_forward_tuning(n_k)  # the other legs run the defaults
         batched = {"maps": 32, "phi_GB": sum(o.numel() for o in outs) * 4 / 1e9,
                    "batched_ms": res["batched"], "one_call_per_map_ms": res["one_call_per_map"],
                    "speedup": res["one_call_per_map"] / res["batched"],
-                   "achieved_GBs": alg / (res["batched"] * 1e-3) / 1e9}
+                   "achieved_GBs": alg / (res["batched"] * 1e-3) / 1e9,
+                   "tuned_ms": res["tuned"],
+                   "tuned_speedup_vs_one_call_per_map": res["one_call_per_map"] / res["tuned"],
+                   "tuned_achieved_GBs": alg / (res["tuned"] * 1e-3) / 1e9,
+                   "autotune_s": tune_s, "tuning": {str(k): list(v) for k, v in sorted(chosen.items())}}
         del maps, outs
         torch.cuda.empty_cache()
     if args.only in ("bwd", "all"):

@@ -178,6 +178,47 @@ typedef struct mck_instance {
  */
 mck_status mck_fastfood_forward_batched(const mck_instance* inst, int64_t count, mck_stream stream);
 
+/*
+ * Launch choice of the single-pass forward for one n (2 <= n <= MCK_MAX_N,
+ * a power of two).  The operation is fixed by equation "mckernel" of section
+ * "McKernel"; these two numbers only choose how the kernel covers it:
+ *   split  register bits per lane layout of the transform: 4 (16 values per
+ *          lane) or 5 (32).  Both are compiled for 2^9 <= n <= 2^14; other
+ *          n have one split.  The split decides which index bits are
+ *          butterflied in registers and which through LDS, so the two can
+ *          differ in the last bits of phi (both within the FP32 tolerance).
+ *   waves  grid target: the E expansions of a map are cut into chunks until
+ *          the grid holds about this many 64-lane waves (64 <= waves <= 2^20).
+ * The table is per device and process; every forward of that n (plain,
+ * 16-bit, batched, explicit-parameter and training step) launches with the
+ * current entry.  Changing it while a forward of that n is being enqueued
+ * on another thread is a race on which choice that call uses, nothing more.
+ */
+typedef struct mck_forward_tuning {
+    int32_t split;
+    int32_t waves;
+} mck_forward_tuning;
+
+/* Current choice for n (the built-in default when none was set). */
+mck_status mck_forward_tuning_get(int64_t n, mck_forward_tuning* out);
+/* Sets the choice for n; t = NULL restores the default.  MCK_ERR_UNSUPPORTED
+ * for a split not compiled for n. */
+mck_status mck_forward_tuning_set(int64_t n, const mck_forward_tuning* t);
+
+/*
+ * Autotuner.  For every n <= MCK_MAX_N present in `inst` (the arguments of
+ * mck_fastfood_forward_batched), times the launches that
+ * mck_fastfood_forward_batched makes for the maps of that n under each
+ * compiled split and each grid target in {2048, 4096, ..., 65536} waves
+ * (one untimed launch, then `reps` timed ones, 1 <= reps <= 1000, HIP events
+ * on `stream`), and stores the fastest in the table above; a choice other
+ * than the current best is taken only when it is at least 2 % faster.  Maps
+ * with n > MCK_MAX_N are not timed.  The call writes every timed map's phi
+ * (with a valid feature map) and synchronizes `stream`; it must not be
+ * called while `stream` is being captured into a graph (MCK_ERR_INVALID_ARG).
+ */
+mck_status mck_autotune_forward_batched(const mck_instance* inst, int64_t count, int32_t reps, mck_stream stream);
+
 /* z = Z xhat without the trigonometric map: batch x (n E), expansion-major. */
 mck_status mck_fastfood_project(const float* x, int64_t batch, int64_t d, int64_t E, uint32_t seed,
                                 double sigma, mck_calibration calib, float* z, mck_stream stream);

@@ -38,7 +38,8 @@ MAX_N = 32768
 
 __all__ = ["padded_dim", "fwht", "fwht_", "params", "forward", "project", "backward", "forward_p",
            "backward_p", "fastfood", "FastfoodFunction", "FastfoodExplicit", "gen_boxmuller", "shutdown",
-           "MckError", "PAPER_SEED", "MAX_N"]
+           "MckError", "PAPER_SEED", "MAX_N", "forward_batched", "autotune_batched", "forward_tuning",
+           "set_forward_tuning"]
 
 
 def _stream(t: torch.Tensor):
@@ -138,13 +139,9 @@ def _forward_t(x, E, seed, sigma, out, out_dtype, matern_t=0):
     return out
 
 
-def forward_batched(maps, outs=None):
-    """Several independent feature maps in one call: `maps` is a list of
-    (x, E, seed, sigma) or (x, E, seed, sigma, matern_t); returns the list of
-    phi (FP32).  Maps of the same n share one grouped launch."""
-    maps = list(maps)
-    if not maps:
-        return []
+def _instances(maps, outs):
+    """mck_instance array, the phi list and the device of a batched call."""
+    arr = (_lib.Instance * len(maps))()
     arr = (_lib.Instance * len(maps))()
     res = []
     dev = None
@@ -165,10 +162,53 @@ def forward_batched(maps, outs=None):
             raise ValueError("phi must be batch x 2nE")
         arr[k] = _lib.Instance(_ptr(x), batch, d, E, seed & 0xFFFFFFFF, float(sigma), calibration(mt), _ptr(phi))
         res.append(phi)
+    return arr, res, dev
+
+
+def forward_batched(maps, outs=None):
+    """Several independent feature maps in one call: `maps` is a list of
+    (x, E, seed, sigma) or (x, E, seed, sigma, matern_t); returns the list of
+    phi (FP32).  Maps of the same n share one grouped launch."""
+    maps = list(maps)
+    if not maps:
+        return []
+    arr, res, dev = _instances(maps, outs)
     with torch.cuda.device(dev):
         _lib.call("mck_fastfood_forward_batched", ctypes.cast(arr, ctypes.c_void_p), len(maps),
                   _stream(maps[0][0]))
     return res
+
+
+def autotune_batched(maps, outs=None, reps: int = 3):
+    """Times the launch choices for every n <= 2^15 among `maps` (as for
+    forward_batched) and keeps the fastest per n; returns {n: (split, waves)}.
+    Synchronizes the current stream; writes phi of the timed maps."""
+    maps = list(maps)
+    if not maps:
+        return {}
+    arr, res, dev = _instances(maps, outs)
+    with torch.cuda.device(dev):
+        _lib.call("mck_autotune_forward_batched", ctypes.cast(arr, ctypes.c_void_p), len(maps), int(reps),
+                  _stream(maps[0][0]))
+        ns = sorted({r.shape[1] // (2 * m[1]) for r, m in zip(res, maps)})
+        return {n: forward_tuning(n) for n in ns if n <= MAX_N}
+
+
+def forward_tuning(n: int):
+    """(split, waves) the forward of length n launches with on the current device."""
+    t = _lib.ForwardTuning()
+    _lib.call("mck_forward_tuning_get", int(n), ctypes.byref(t))
+    return (t.split, t.waves)
+
+
+def set_forward_tuning(n: int, split=None, waves=None):
+    """Sets the launch choice for n; split=None and waves=None restore the default."""
+    if split is None and waves is None:
+        _lib.call("mck_forward_tuning_set", int(n), None)
+        return
+    cur = forward_tuning(n)
+    t = _lib.ForwardTuning(int(split if split is not None else cur[0]), int(waves if waves is not None else cur[1]))
+    _lib.call("mck_forward_tuning_set", int(n), ctypes.byref(t))
 
 
 def project(x: torch.Tensor, E: int, seed: int = PAPER_SEED, sigma: float = 1.0, matern_t: int = 0) -> torch.Tensor:

@@ -33,6 +33,9 @@ SIGNATURES = {
     "mck_fastfood_project": (_int, [_vp, _i64, _i64, _i64, _u32, _f64, _int, _vp, _vp]),
     "mck_fastfood_forward_t": (_int, [_vp, _int, _i64, _i64, _i64, _u32, _f64, _int, _vp, _int, _vp]),
     "mck_fastfood_forward_batched": (_int, [_vp, _i64, _vp]),
+    "mck_forward_tuning_get": (_int, [_i64, _vp]),
+    "mck_forward_tuning_set": (_int, [_i64, _vp]),
+    "mck_autotune_forward_batched": (_int, [_vp, _i64, ctypes.c_int32, _vp]),
     "mck_fastfood_backward": (_int, [_vp, _vp, _i64, _i64, _i64, _u32, _f64, _int, _vp, _vp, _vp, _vp, _vp]),
     "mck_fastfood_forward_p": (_int, [_vp, _i64, _i64, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
     "mck_fastfood_backward_p": (_int, [_vp, _vp, _i64, _i64, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
@@ -52,6 +55,11 @@ class Instance(ctypes.Structure):
     """mck_instance of the C interface."""
     _fields_ = [("x", _vp), ("batch", _i64), ("d", _i64), ("E", _i64), ("seed", _u32), ("sigma", _f64),
                 ("calib", _int), ("phi", _vp)]
+
+
+class ForwardTuning(ctypes.Structure):
+    """mck_forward_tuning of the C interface."""
+    _fields_ = [("split", ctypes.c_int32), ("waves", ctypes.c_int32)]
 
 
 class MckError(RuntimeError):

@@ -24,6 +24,17 @@ constexpr int fwd_p(int M) { return M >= 14 ? 5 : 4; }
 constexpr int bwd_p(int M) { return M >= 15 ? 5 : 4; }
 constexpr int kFwhtP = 5;
 
+// The forward is also compiled with the other register split for
+// 2^9 <= n <= 2^14, where both fit (P = 4 stops at 2^14: a 2^15 row would
+// need 2048 lanes); the autotuner picks one per n.
+constexpr bool fwd_p_tunable(int M) { return M >= 9 && M <= 14; }
+constexpr int fwd_p_alt(int M) { return fwd_p(M) == 4 ? 5 : 4; }
+constexpr bool fwd_p_ok(int M, int P) { return P == fwd_p(M) || (fwd_p_tunable(M) && P == fwd_p_alt(M)); }
+
+// Default grid target of the forward: the expansions are split into chunks
+// until the grid holds about this many waves.
+constexpr int kFwdWaves = 16384;
+
 // Every buffer range a launch uses stays below 2^31 bytes.
 constexpr int64_t kRangeLimit = (int64_t(1) << 31) - 4096;
 
@@ -279,12 +290,25 @@ template <int XT, int YT>
 struct RunForwardT {
     template <int M>
     struct Run {
-    static hipError_t run(bool vec, bool trig, const void* x, int64_t batch, int d, int64_t E, const float* B,
-                          const uint32_t* goff, const float* Gs, const float* Sx, float cs, void* out,
-                          hipStream_t s)
+    // P: register bits (a compiled split for this n), waves: grid target
+    static hipError_t run(int P, int waves, bool vec, bool trig, const void* x, int64_t batch, int d, int64_t E,
+                          const float* B, const uint32_t* goff, const float* Gs, const float* Sx, float cs,
+                          void* out, hipStream_t s)
+    {
+        if (P == fwd_p(M))
+            return run_p<fwd_p(M)>(waves, vec, trig, x, batch, d, E, B, goff, Gs, Sx, cs, out, s);
+        if constexpr (fwd_p_tunable(M))
+            if (P == fwd_p_alt(M))
+                return run_p<fwd_p_alt(M)>(waves, vec, trig, x, batch, d, E, B, goff, Gs, Sx, cs, out, s);
+        return hipErrorInvalidValue;
+    }
+
+    template <int P>
+    static hipError_t run_p(int waves, bool vec, bool trig, const void* x, int64_t batch, int d, int64_t E,
+                            const float* B, const uint32_t* goff, const float* Gs, const float* Sx, float cs,
+                            void* out, hipStream_t s)
     {
         constexpr int64_t XB = elem_bytes<XT>(), YB = elem_bytes<YT>();
-        constexpr int P = fwd_p(M);
         using g = Geo<M, P>;
         const int64_t n = g::n;
         const int64_t out_row = (trig ? 2 : 1) * n * E;
@@ -296,9 +320,9 @@ struct RunForwardT {
         for (int64_t r0 = 0; r0 < batch; r0 += rows_per) {
             const int64_t rows = batch - r0 < rows_per ? batch - r0 : rows_per;
             const int64_t groups = (rows + g::RPB - 1) / g::RPB;
-            // split the expansions so that the grid holds >= ~16k waves
+            // split the expansions so that the grid holds >= `waves` waves
             const int64_t waves_per_group = g::BLOCK / 64;
-            int64_t nchunks = (16384 + groups * waves_per_group - 1) / (groups * waves_per_group);
+            int64_t nchunks = (waves + groups * waves_per_group - 1) / (groups * waves_per_group);
             nchunks = nchunks > E ? E : (nchunks < 1 ? 1 : nchunks);
             const int64_t echunk = (E + nchunks - 1) / nchunks;
             nchunks = (E + echunk - 1) / echunk;

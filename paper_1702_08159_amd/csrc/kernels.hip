@@ -775,25 +775,68 @@ template <int M>
 struct RunPlanElems {
     static hipError_t run(int64_t* fwd_goff, int64_t* bwd_goff)
     {
-        *fwd_goff = (int64_t)Geo<M, fwd_p(M)>::RPB * Geo<M, fwd_p(M)>::n;
+        int64_t f = (int64_t)Geo<M, fwd_p(M)>::RPB * Geo<M, fwd_p(M)>::n;
+        if constexpr (fwd_p_tunable(M)) {
+            const int64_t a = (int64_t)Geo<M, fwd_p_alt(M)>::RPB * Geo<M, fwd_p_alt(M)>::n;
+            f = a > f ? a : f;
+        }
+        *fwd_goff = f;
         *bwd_goff = (int64_t)Geo<M, bwd_p(M)>::RPB * Geo<M, bwd_p(M)>::n;
         return hipSuccess;
     }
 };
 
+template <int M, int P>
+hipError_t derive_one(int64_t E, const int32_t* perm, const float* G, const double* S64, const float* S32,
+                      uint32_t* goff, float* Gk, float* Gs, float* Sh, hipStream_t s)
+{
+    const int64_t t = E * Geo<M, P>::RPB * Geo<M, P>::n;
+    k_derive<M, P><<<dim3((unsigned)((t + 255) / 256)), dim3(256), 0, s>>>(E, perm, G, S64, S32, goff, Gk, Gs, Sh);
+    return hipGetLastError();
+}
+
+// forward arrays (and Sh when given) for register split PF
+template <int M>
+hipError_t derive_fwd(int PF, int64_t E, const int32_t* perm, const float* G, const double* S64, const float* S32,
+                      uint32_t* goff_f, float* Gs_f, float* Sh, hipStream_t s)
+{
+    if (PF == fwd_p(M))
+        return derive_one<M, fwd_p(M)>(E, perm, G, S64, S32, goff_f, nullptr, Gs_f, Sh, s);
+    if constexpr (fwd_p_tunable(M))
+        if (PF == fwd_p_alt(M))
+            return derive_one<M, fwd_p_alt(M)>(E, perm, G, S64, S32, goff_f, nullptr, Gs_f, Sh, s);
+    return hipErrorInvalidValue;
+}
+
 template <int M>
 struct RunDerive {
-    static hipError_t run(int64_t E, const int32_t* perm, const float* G, const double* S64, const float* S32,
-                          uint32_t* goff_f, float* Gs_f, uint32_t* goff_b, float* Gk_b, float* Sh, hipStream_t s)
+    static hipError_t run(int PF, int64_t E, const int32_t* perm, const float* G, const double* S64,
+                          const float* S32, uint32_t* goff_f, float* Gs_f, uint32_t* goff_b, float* Gk_b, float* Sh,
+                          hipStream_t s)
     {
-        constexpr int PF = fwd_p(M), PB = bwd_p(M);
-        const int64_t tf = E * Geo<M, PF>::RPB * Geo<M, PF>::n;
-        k_derive<M, PF><<<dim3((unsigned)((tf + 255) / 256)), dim3(256), 0, s>>>(E, perm, G, S64, S32, goff_f,
-                                                                                  nullptr, Gs_f, Sh);
-        const int64_t tb = E * Geo<M, PB>::RPB * Geo<M, PB>::n;
-        k_derive<M, PB><<<dim3((unsigned)((tb + 255) / 256)), dim3(256), 0, s>>>(E, perm, G, S64, S32, goff_b,
-                                                                                  Gk_b, nullptr, nullptr);
-        return hipGetLastError();
+        const hipError_t err = derive_fwd<M>(PF, E, perm, G, S64, S32, goff_f, Gs_f, Sh, s);
+        if (err != hipSuccess)
+            return err;
+        return derive_one<M, bwd_p(M)>(E, perm, G, S64, S32, goff_b, Gk_b, nullptr, nullptr, s);
+    }
+};
+
+template <int M>
+struct RunDeriveFwd {
+    static hipError_t run(int PF, int64_t E, const int32_t* perm, const float* G, uint32_t* goff_f, float* Gs_f,
+                          hipStream_t s)
+    {
+        return derive_fwd<M>(PF, E, perm, G, nullptr, nullptr, goff_f, Gs_f, nullptr, s);
+    }
+};
+
+template <int M>
+struct RunSplit {
+    static hipError_t run(int P, bool* ok, int* def)
+    {
+        *ok = fwd_p_ok(M, P);
+        *def = fwd_p(M);
+        return hipSuccess;
     }
 };
 
@@ -804,26 +847,52 @@ hipError_t launch_fwht(int M, float* data, int64_t batch, bool vec, hipStream_t 
     return dispatch_m<RunFwht>(M, data, batch, vec, s);
 }
 
-hipError_t launch_forward(int M, bool vec, bool trig, const float* x, int64_t batch, int d, int64_t E,
-                          const float* B, const uint32_t* goff, const float* Gs, const float* Sx,
+hipError_t launch_forward(int M, int P, int waves, bool vec, bool trig, const float* x, int64_t batch, int d,
+                          int64_t E, const float* B, const uint32_t* goff, const float* Gs, const float* Sx,
                           float cs, float* out, hipStream_t s)
 {
-    return dispatch_m<RunForwardT<kF32, kF32>::Run>(M, vec, trig, x, batch, d, E, B, goff, Gs, Sx, cs, out, s);
+    return dispatch_m<RunForwardT<kF32, kF32>::Run>(M, P, waves, vec, trig, x, batch, d, E, B, goff, Gs, Sx, cs,
+                                                    out, s);
+}
+
+bool fwd_split_ok(int M, int P)
+{
+    bool ok = false;
+    int def = 0;
+    return dispatch_m<RunSplit>(M, P, &ok, &def) == hipSuccess && ok;
+}
+
+int fwd_split_default(int M)
+{
+    bool ok = false;
+    int def = 0;
+    (void)dispatch_m<RunSplit>(M, 0, &ok, &def);
+    return def;
 }
 
 namespace {
 
 template <int M>
 struct RunGroup {
-    static hipError_t run(bool vec, const GroupInst* inst, int count, hipStream_t s)
+    static hipError_t run(int P, int waves, bool vec, const GroupInst* inst, int count, hipStream_t s)
     {
-        constexpr int P = fwd_p(M);
+        if (P == fwd_p(M))
+            return run_p<fwd_p(M)>(waves, vec, inst, count, s);
+        if constexpr (fwd_p_tunable(M))
+            if (P == fwd_p_alt(M))
+                return run_p<fwd_p_alt(M)>(waves, vec, inst, count, s);
+        return hipErrorInvalidValue;
+    }
+
+    template <int P>
+    static hipError_t run_p(int waves, bool vec, const GroupInst* inst, int count, hipStream_t s)
+    {
         using g = Geo<M, P>;
-        // split expansions so that the whole group holds >= ~16k waves
+        // split expansions so that the whole group holds >= `waves` waves
         int64_t base_waves = 0;
         for (int i = 0; i < count; ++i)
             base_waves += (inst[i].batch + g::RPB - 1) / g::RPB * (g::BLOCK / 64);
-        const int64_t factor = base_waves > 0 ? (16384 + base_waves - 1) / base_waves : 1;
+        const int64_t factor = base_waves > 0 ? (waves + base_waves - 1) / base_waves : 1;
         for (int i0 = 0; i0 < count; i0 += kGroupMax) {
             FwdGroup grp;
             grp.count = count - i0 < kGroupMax ? count - i0 : kGroupMax;
@@ -869,9 +938,9 @@ struct RunGroup {
 
 }  // namespace
 
-hipError_t launch_forward_group(int M, bool vec, const GroupInst* inst, int count, hipStream_t s)
+hipError_t launch_forward_group(int M, int P, int waves, bool vec, const GroupInst* inst, int count, hipStream_t s)
 {
-    return dispatch_m<RunGroup>(M, vec, inst, count, s);
+    return dispatch_m<RunGroup>(M, P, waves, vec, inst, count, s);
 }
 
 BwdGeometry backward_geometry(int M, int64_t batch, int d, int64_t E)
@@ -904,10 +973,17 @@ void plan_elems(int M, int64_t* fwd_goff, int64_t* bwd_goff)
     (void)dispatch_m<RunPlanElems>(M, fwd_goff, bwd_goff);
 }
 
-hipError_t launch_derive(int M, int64_t E, const int32_t* perm, const float* G, const double* S64, const float* S32,
-                         uint32_t* goff_f, float* Gs_f, uint32_t* goff_b, float* Gk_b, float* Sh, hipStream_t s)
+hipError_t launch_derive(int M, int PF, int64_t E, const int32_t* perm, const float* G, const double* S64,
+                         const float* S32, uint32_t* goff_f, float* Gs_f, uint32_t* goff_b, float* Gk_b, float* Sh,
+                         hipStream_t s)
 {
-    return dispatch_m<RunDerive>(M, E, perm, G, S64, S32, goff_f, Gs_f, goff_b, Gk_b, Sh, s);
+    return dispatch_m<RunDerive>(M, PF, E, perm, G, S64, S32, goff_f, Gs_f, goff_b, Gk_b, Sh, s);
+}
+
+hipError_t launch_derive_fwd(int M, int PF, int64_t E, const int32_t* perm, const float* G, uint32_t* goff_f,
+                             float* Gs_f, hipStream_t s)
+{
+    return dispatch_m<RunDeriveFwd>(M, PF, E, perm, G, goff_f, Gs_f, s);
 }
 
 }  // namespace mck

@@ -23,23 +23,37 @@ hipError_t launch_boxmuller(const uint32_t* a, const uint32_t* b, int64_t count,
 // LDS of the source of each gathered element; plan_elems(M) of them per
 // expansion), G by source (Gs_f) and by destination (Gk_b), and S in half
 // turns (Sh, natural order).  S64 may be null (then S32 is used).
+// fwd_goff is the largest count over the forward's compiled register
+// splits, so that one allocation serves whichever split a plan uses.
 void plan_elems(int M, int64_t* fwd_goff, int64_t* bwd_goff);
-hipError_t launch_derive(int M, int64_t E, const int32_t* perm, const float* G, const double* S64, const float* S32,
-                         uint32_t* goff_f, float* Gs_f, uint32_t* goff_b, float* Gk_b, float* Sh, hipStream_t s);
+hipError_t launch_derive(int M, int PF, int64_t E, const int32_t* perm, const float* G, const double* S64,
+                         const float* S32, uint32_t* goff_f, float* Gs_f, uint32_t* goff_b, float* Gk_b, float* Sh,
+                         hipStream_t s);
+// The forward arrays alone (goff_f, Gs_f) for register split PF.
+hipError_t launch_derive_fwd(int M, int PF, int64_t E, const int32_t* perm, const float* G, uint32_t* goff_f,
+                             float* Gs_f, hipStream_t s);
+
+// Forward register splits (register bits per layout, 4 or 5) compiled for
+// n = 2^M, and the default one.
+bool fwd_split_ok(int M, int P);
+int fwd_split_default(int M);
+constexpr int kFwdWavesDefault = 16384;
 
 // In-place batched Walsh-Hadamard transform, n = 2^M, 1 <= M <= 15.
 hipError_t launch_fwht(int M, float* data, int64_t batch, bool vec, hipStream_t s);
 
-// Forward: phi (trig = true) or z = S H G Pi H B xhat (trig = false).
-hipError_t launch_forward(int M, bool vec, bool trig, const float* x, int64_t batch, int d, int64_t E,
-                          const float* B, const uint32_t* goff, const float* Gs, const float* Sx,
+// Forward: phi (trig = true) or z = S H G Pi H B xhat (trig = false).  P is
+// the register split the arrays goff, Gs were derived for; the expansions
+// are split into chunks until the grid holds about `waves` waves.
+hipError_t launch_forward(int M, int P, int waves, bool vec, bool trig, const float* x, int64_t batch, int d,
+                          int64_t E, const float* B, const uint32_t* goff, const float* Gs, const float* Sx,
                           float cs, float* out, hipStream_t s);
 
 // Forward with 16-bit storage (forward16.hip): xt, yt = 0 (FP32), 1 (bf16),
 // 2 (half); supported pairs (0,1), (0,2), (1,1), (2,2); the feature map only.
-hipError_t launch_forward_t(int M, bool vec, int xt, int yt, const void* x, int64_t batch, int d, int64_t E,
-                            const float* B, const uint32_t* goff, const float* Gs, const float* Sx, float cs,
-                            void* out, hipStream_t s);
+hipError_t launch_forward_t(int M, int P, int waves, bool vec, int xt, int yt, const void* x, int64_t batch, int d,
+                            int64_t E, const float* B, const uint32_t* goff, const float* Gs, const float* Sx,
+                            float cs, void* out, hipStream_t s);
 
 // n = 2^M > 2^15 (longn.hip): in-place H on 16-byte aligned rows, and the
 // feature map through FP32 scratch rows u, w (batch x n each).  Sh for such
@@ -81,7 +95,7 @@ struct GroupInst {
     float cs;
     float* phi;
 };
-hipError_t launch_forward_group(int M, bool vec, const GroupInst* inst, int count, hipStream_t s);
+hipError_t launch_forward_group(int M, int P, int waves, bool vec, const GroupInst* inst, int count, hipStream_t s);
 
 // Backward geometry: blocks, passes per block.
 // Backward launch shape: rowblocks blocks of passes x rows; for n <= 1024

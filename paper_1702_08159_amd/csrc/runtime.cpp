@@ -111,6 +111,33 @@ mck_status check_common(int64_t batch, int64_t d, int64_t E, int64_t* n_out)
     return MCK_OK;
 }
 
+// ------------------------------------------------------------------ forward tuning
+// Launch choice of the single-pass forward for n = 2^M: the register split P
+// (register bits per lane layout) and the grid target in waves.  One table
+// per device; every forward of that n (plain, 16-bit, grouped, explicit
+// parameters) launches with the current entry.
+struct FwdTune {
+    int P;
+    int waves;
+};
+
+std::mutex g_tune_mutex;
+std::map<std::pair<int, int>, FwdTune> g_tune;  // (device, M) -> choice; absent = default
+
+int alt_split(int M) { return mck::fwd_split_default(M) == 4 ? 5 : 4; }
+
+FwdTune default_tuning(int M) { return FwdTune{mck::fwd_split_default(M), mck::kFwdWavesDefault}; }
+
+FwdTune current_tuning(int M)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return default_tuning(M);
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    const auto it = g_tune.find({dev, M});
+    return it == g_tune.end() ? default_tuning(M) : it->second;
+}
+
 // ------------------------------------------------------------------ plan cache
 struct Plan {
     int pins = 0;  // > 0 while a batched call holds it: not evicted
@@ -127,8 +154,10 @@ struct Plan {
     double* S64 = nullptr;
     float* S32 = nullptr;
     double* norm2 = nullptr;
-    uint32_t* goffF = nullptr;  // forward gather offsets
+    uint32_t* goffF = nullptr;  // forward gather offsets (default register split)
     float* GsF = nullptr;       // G in source order, forward layout
+    uint32_t* goffF2 = nullptr; // the same for the other compiled split (null if none)
+    float* GsF2 = nullptr;
     uint32_t* goffB = nullptr;  // backward gather offsets
     float* GkB = nullptr;       // G in destination order, backward layout
     float* Sh = nullptr;        // S / (2 pi)
@@ -191,11 +220,14 @@ mck_status get_plan(uint32_t seed, int64_t n, int64_t E, double sigma, int calib
     mck::plan_elems(log2i(n), &gf, &gb);
     const size_t C = n > MCK_MAX_N ? (size_t)(n / MCK_MAX_N) : 0;
     const size_t ecc = (size_t)E * C * C * 4;
-    size_t off[16], total = 0;
-    const size_t sz[16] = {en * 4, en * 4, en * 4, en * 8, en * 4, (size_t)E * 8,
+    const int M = log2i(n);
+    const bool two = n <= MCK_MAX_N && mck::fwd_split_ok(M, alt_split(M));
+    size_t off[18], total = 0;
+    const size_t sz[18] = {en * 4, en * 4, en * 4, en * 8, en * 4, (size_t)E * 8,
                            (size_t)gf * E * 4, en * 4, (size_t)gb * E * 4, en * 4, en * 4,
-                           C ? en * 4 : 0, C ? en * 2 : 0, ecc, 3 * ecc + (size_t)E * C * 8, C ? en * 4 : 0};
-    for (int i = 0; i < 16; ++i) {
+                           C ? en * 4 : 0, C ? en * 2 : 0, ecc, 3 * ecc + (size_t)E * C * 8, C ? en * 4 : 0,
+                           two ? (size_t)gf * E * 4 : 0, two ? en * 4 : 0};
+    for (int i = 0; i < 18; ++i) {
         off[i] = total;
         total += align_up(sz[i]);
     }
@@ -236,6 +268,10 @@ mck_status get_plan(uint32_t seed, int64_t n, int64_t E, double sigma, int calib
         p.bscratch = reinterpret_cast<int32_t*>(b + off[14]);
         p.Gx = reinterpret_cast<float*>(b + off[15]);
     }
+    if (two) {
+        p.goffF2 = reinterpret_cast<uint32_t*>(b + off[16]);
+        p.GsF2 = reinterpret_cast<float*>(b + off[17]);
+    }
     int matern_t = 0;
     {
         const mck_status cst = check_calib(calib, n, &matern_t);
@@ -247,8 +283,10 @@ mck_status get_plan(uint32_t seed, int64_t n, int64_t E, double sigma, int calib
     err = mck::launch_generate(seed, n, E, sigma, matern_t, p.B, p.perm, p.G, p.S64, p.S32, p.norm2, stream);
     if (err == hipSuccess)
         err = n > MCK_MAX_N ? mck::launch_sh(p.S64, p.Sh, n * E, stream)
-                            : mck::launch_derive(log2i(n), E, p.perm, p.G, p.S64, p.S32, p.goffF, p.GsF, p.goffB,
-                                                 p.GkB, p.Sh, stream);
+                            : mck::launch_derive(M, mck::fwd_split_default(M), E, p.perm, p.G, p.S64, p.S32,
+                                                 p.goffF, p.GsF, p.goffB, p.GkB, p.Sh, stream);
+    if (err == hipSuccess && two)
+        err = mck::launch_derive_fwd(M, alt_split(M), E, p.perm, p.G, p.goffF2, p.GsF2, stream);
     if (err == hipSuccess && n > MCK_MAX_N)
         err = mck::launch_buckets(log2i(n), E, p.perm, p.G, p.packA, p.dstB, p.pdelta, p.Gx, p.bscratch, stream);
     if (err == hipSuccess)
@@ -264,7 +302,22 @@ mck_status get_plan(uint32_t seed, int64_t n, int64_t E, double sigma, int calib
     return MCK_OK;
 }
 
+struct FwdArrays {
+    const uint32_t* goff;
+    const float* Gs;
+};
+
+// The plan's forward arrays for register split P (the default split's when
+// the plan holds no others).
+FwdArrays fwd_arrays(const Plan* p, int P)
+{
+    if (P != mck::fwd_split_default(log2i(p->n)) && p->goffF2)
+        return FwdArrays{p->goffF2, p->GsF2};
+    return FwdArrays{p->goffF, p->GsF};
+}
+
 struct TempPlan {
+    int PF = 0;  // register split of goffF, GsF
     void* block = nullptr;
     uint32_t* goffF = nullptr;
     float* GsF = nullptr;
@@ -291,7 +344,9 @@ mck_status make_temp_plan(int64_t n, int64_t E, const int32_t* perm, const float
     tp->GsF = reinterpret_cast<float*>(b + af + ab);
     tp->GkB = reinterpret_cast<float*>(b + af + ab + a);
     tp->Sh = reinterpret_cast<float*>(b + af + ab + 2 * a);
-    err = mck::launch_derive(log2i(n), E, perm, G, nullptr, S, tp->goffF, tp->GsF, tp->goffB, tp->GkB, tp->Sh, s);
+    tp->PF = current_tuning(log2i(n)).P;
+    err = mck::launch_derive(log2i(n), tp->PF, E, perm, G, nullptr, S, tp->goffF, tp->GsF, tp->goffB, tp->GkB,
+                             tp->Sh, s);
     if (err != hipSuccess) {
         (void)hipFreeAsync(tp->block, s);
         return hip_fail(err, "derive kernel");
@@ -504,8 +559,10 @@ static mck_status forward_common(const float* x, int64_t batch, int64_t d, int64
         return st;
     if (n > MCK_MAX_N)
         return forward_long(p, x, 0, batch, d, n, E, out, 0, s);
-    const hipError_t err = mck::launch_forward(log2i(n), vec_ok(x, out, d, n), trig, x, batch, (int)d, E, p->B,
-                                               p->goffF, p->GsF, trig ? p->Sh : p->S32, feature_scale(n, E),
+    const FwdTune t = current_tuning(log2i(n));
+    const FwdArrays a = fwd_arrays(p, t.P);
+    const hipError_t err = mck::launch_forward(log2i(n), t.P, t.waves, vec_ok(x, out, d, n), trig, x, batch, (int)d,
+                                               E, p->B, a.goff, a.Gs, trig ? p->Sh : p->S32, feature_scale(n, E),
                                                out, s);
     return err == hipSuccess ? MCK_OK : hip_fail(err, "forward launch");
 }
@@ -557,12 +614,32 @@ mck_status mck_fastfood_forward_t(const void* x, mck_dtype x_type, int64_t batch
     const uintptr_t xa = 4u * (xt == 0 ? 4u : 2u), ya = 4u * (yt == 0 ? 4u : 2u);
     const bool vec = (reinterpret_cast<uintptr_t>(x) % xa == 0) && (reinterpret_cast<uintptr_t>(phi) % ya == 0) &&
                      d % 4 == 0 && n >= 4;
-    const hipError_t err = mck::launch_forward_t(log2i(n), vec, xt, yt, x, batch, (int)d, E, p->B, p->goffF, p->GsF,
-                                                 p->Sh, feature_scale(n, E), phi, s);
+    const FwdTune t = current_tuning(log2i(n));
+    const FwdArrays a = fwd_arrays(p, t.P);
+    const hipError_t err = mck::launch_forward_t(log2i(n), t.P, t.waves, vec, xt, yt, x, batch, (int)d, E, p->B,
+                                                 a.goff, a.Gs, p->Sh, feature_scale(n, E), phi, s);
     return err == hipSuccess ? MCK_OK : hip_fail(err, "forward launch");
 }
 
-mck_status mck_fastfood_forward_batched(const mck_instance* inst, int64_t count, mck_stream stream)
+namespace {
+
+// One instance of a batched call, validated, with its pinned plan.
+struct MapRef {
+    const mck_instance* q;
+    int64_t n;
+    const Plan* p;
+};
+
+void batched_unpin(const std::vector<MapRef>& maps)
+{
+    std::lock_guard<std::mutex> lock(g_mutex);
+    for (const MapRef& m : maps)
+        --const_cast<Plan*>(m.p)->pins;
+}
+
+// Validates every instance and pins the plans of the non-empty ones; on
+// failure nothing stays pinned.
+mck_status batched_setup(const mck_instance* inst, int64_t count, hipStream_t s, std::vector<MapRef>* maps)
 {
     if (count < 0 || (count > 0 && inst == nullptr))
         return fail(MCK_ERR_INVALID_ARG, "count must be >= 0 and inst non-NULL");
@@ -584,54 +661,218 @@ mck_status mck_fastfood_forward_batched(const mck_instance* inst, int64_t count,
             return st;
         }
     }
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    std::vector<Plan*> plans((size_t)count, nullptr);
-    auto unpin = [&]() {
-        std::lock_guard<std::mutex> lock(g_mutex);
-        for (Plan* p : plans)
-            if (p)
-                --p->pins;
-    };
+    maps->clear();
     mck_status st = MCK_OK;
-    for (int64_t i = 0; i < count && st == MCK_OK; ++i)
-        if (inst[i].batch > 0)
-            st = get_plan(inst[i].seed, ns[i], inst[i].E, inst[i].sigma, inst[i].calib, s, &plans[i], true);
-    if (st != MCK_OK) {
-        unpin();
-        return st;
-    }
-    // group the single-launch maps by (log2 n, vector path); the rest run alone
-    std::map<std::pair<int, bool>, std::vector<mck::GroupInst>> groups;
-    const int64_t lim = (int64_t(1) << 31) - 4096;
     for (int64_t i = 0; i < count && st == MCK_OK; ++i) {
-        const mck_instance& q = inst[i];
-        if (q.batch == 0)
+        if (inst[i].batch == 0)
             continue;
-        const int64_t n = ns[i];
-        const Plan* p = plans[i];
-        if (n <= MCK_MAX_N && 4 * q.batch * q.d <= lim && 4 * q.batch * 2 * n * q.E <= lim) {
-            groups[{log2i(n), vec_ok(q.x, q.phi, q.d, n)}].push_back(
-                {q.x, q.batch, (int)q.d, q.E, p->B, p->goffF, p->GsF, p->Sh, feature_scale(n, q.E), q.phi});
-        } else if (n > MCK_MAX_N) {
-            st = forward_long(p, q.x, 0, q.batch, q.d, n, q.E, q.phi, 0, s);
-        } else {
-            const hipError_t err = mck::launch_forward(log2i(n), vec_ok(q.x, q.phi, q.d, n), true, q.x, q.batch,
-                                                       (int)q.d, q.E, p->B, p->goffF, p->GsF, p->Sh,
-                                                       feature_scale(n, q.E), q.phi, s);
-            if (err != hipSuccess)
-                st = hip_fail(err, "forward launch");
+        Plan* p = nullptr;
+        st = get_plan(inst[i].seed, ns[i], inst[i].E, inst[i].sigma, inst[i].calib, s, &p, true);
+        if (st == MCK_OK)
+            maps->push_back(MapRef{&inst[i], ns[i], p});
+    }
+    if (st != MCK_OK)
+        batched_unpin(*maps);
+    return st;
+}
+
+// Launches the single-pass maps of one n with launch choice t: grouped by
+// vector path into k_forward_group grids, a map whose x or phi exceeds one
+// launch's 2^31-byte ranges alone.
+hipError_t launch_maps(int M, const FwdTune& t, const std::vector<MapRef>& maps, hipStream_t s)
+{
+    const int64_t lim = (int64_t(1) << 31) - 4096;
+    std::vector<mck::GroupInst> grp[2];
+    hipError_t err = hipSuccess;
+    for (const MapRef& m : maps) {
+        const mck_instance& q = *m.q;
+        const int64_t n = m.n;
+        const FwdArrays a = fwd_arrays(m.p, t.P);
+        const bool vec = vec_ok(q.x, q.phi, q.d, n);
+        if (4 * q.batch * q.d <= lim && 4 * q.batch * 2 * n * q.E <= lim) {
+            grp[vec ? 1 : 0].push_back(
+                {q.x, q.batch, (int)q.d, q.E, m.p->B, a.goff, a.Gs, m.p->Sh, feature_scale(n, q.E), q.phi});
+        } else if (err == hipSuccess) {
+            err = mck::launch_forward(M, t.P, t.waves, vec, true, q.x, q.batch, (int)q.d, q.E, m.p->B, a.goff, a.Gs,
+                                      m.p->Sh, feature_scale(n, q.E), q.phi, s);
         }
     }
-    for (auto& kv : groups) {
+    for (int v = 0; v < 2 && err == hipSuccess; ++v)
+        if (!grp[v].empty())
+            err = mck::launch_forward_group(M, t.P, t.waves, v == 1, grp[v].data(), (int)grp[v].size(), s);
+    return err;
+}
+
+// The single-pass maps by log2 n; long maps (n > MCK_MAX_N) are launched
+// here, each on the multi-pass path.
+mck_status split_maps(const std::vector<MapRef>& maps, hipStream_t s, bool run_long,
+                      std::map<int, std::vector<MapRef>>* by_m)
+{
+    for (const MapRef& m : maps) {
+        if (m.n <= MCK_MAX_N) {
+            (*by_m)[log2i(m.n)].push_back(m);
+        } else if (run_long) {
+            const mck_status st = forward_long(m.p, m.q->x, 0, m.q->batch, m.q->d, m.n, m.q->E, m.q->phi, 0, s);
+            if (st != MCK_OK)
+                return st;
+        }
+    }
+    return MCK_OK;
+}
+
+}  // namespace
+
+mck_status mck_fastfood_forward_batched(const mck_instance* inst, int64_t count, mck_stream stream)
+{
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<MapRef> maps;
+    mck_status st = batched_setup(inst, count, s, &maps);
+    if (st != MCK_OK)
+        return st;
+    std::map<int, std::vector<MapRef>> by_m;
+    st = split_maps(maps, s, true, &by_m);
+    for (const auto& kv : by_m) {
         if (st != MCK_OK)
             break;
-        const hipError_t err = mck::launch_forward_group(kv.first.first, kv.first.second, kv.second.data(),
-                                                         (int)kv.second.size(), s);
+        const hipError_t err = launch_maps(kv.first, current_tuning(kv.first), kv.second, s);
         if (err != hipSuccess)
-            st = hip_fail(err, "grouped forward launch");
+            st = hip_fail(err, "batched forward launch");
     }
-    unpin();
+    batched_unpin(maps);
     return st;
+}
+
+namespace {
+
+// Grid targets the tuner tries, in waves.
+constexpr int kTuneWaves[] = {2048, 4096, 8192, 16384, 32768, 65536};
+
+// Average time of `reps` launches of the maps of one n under choice t (one
+// untimed launch first).
+mck_status time_maps(int M, const FwdTune& t, const std::vector<MapRef>& maps, int reps, hipEvent_t e0,
+                     hipEvent_t e1, hipStream_t s, float* ms)
+{
+    hipError_t err = launch_maps(M, t, maps, s);
+    if (err == hipSuccess)
+        err = hipEventRecord(e0, s);
+    for (int r = 0; r < reps && err == hipSuccess; ++r)
+        err = launch_maps(M, t, maps, s);
+    if (err == hipSuccess)
+        err = hipEventRecord(e1, s);
+    if (err == hipSuccess)
+        err = hipEventSynchronize(e1);
+    float t_ms = 0.f;
+    if (err == hipSuccess)
+        err = hipEventElapsedTime(&t_ms, e0, e1);
+    if (err != hipSuccess)
+        return hip_fail(err, "autotune timing");
+    *ms = t_ms / (float)reps;
+    return MCK_OK;
+}
+
+}  // namespace
+
+mck_status mck_autotune_forward_batched(const mck_instance* inst, int64_t count, int32_t reps, mck_stream stream)
+{
+    if (reps < 1 || reps > 1000)
+        return fail(MCK_ERR_INVALID_ARG, "reps must be in [1, 1000]");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    hipError_t err = hipStreamIsCapturing(s, &cap);
+    if (err != hipSuccess)
+        return hip_fail(err, "hipStreamIsCapturing");
+    if (cap != hipStreamCaptureStatusNone)
+        return fail(MCK_ERR_INVALID_ARG, "the tuner times launches and cannot run under graph capture");
+    std::vector<MapRef> maps;
+    mck_status st = batched_setup(inst, count, s, &maps);
+    if (st != MCK_OK)
+        return st;
+    std::map<int, std::vector<MapRef>> by_m;
+    st = split_maps(maps, s, false, &by_m);
+    int dev = 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (st == MCK_OK) {
+        err = hipGetDevice(&dev);
+        if (err == hipSuccess)
+            err = hipEventCreate(&e0);
+        if (err == hipSuccess)
+            err = hipEventCreate(&e1);
+        if (err != hipSuccess)
+            st = hip_fail(err, "autotune events");
+    }
+    for (const auto& kv : by_m) {
+        if (st != MCK_OK)
+            break;
+        const int M = kv.first;
+        const FwdTune def = default_tuning(M);
+        FwdTune best = def;
+        float best_ms = 0.f;
+        st = time_maps(M, def, kv.second, reps, e0, e1, s, &best_ms);
+        const int splits[2] = {def.P, alt_split(M)};
+        for (int k = 0; k < 2 && st == MCK_OK; ++k) {
+            if (k == 1 && !mck::fwd_split_ok(M, splits[1]))
+                break;
+            for (int w : kTuneWaves) {
+                const FwdTune c{splits[k], w};
+                if (c.P == def.P && c.waves == def.waves)
+                    continue;
+                float ms = 0.f;
+                st = time_maps(M, c, kv.second, reps, e0, e1, s, &ms);
+                if (st != MCK_OK)
+                    break;
+                // move away from the current best only for a clear gain
+                if (ms < 0.98f * best_ms) {
+                    best = c;
+                    best_ms = ms;
+                }
+            }
+        }
+        if (st == MCK_OK) {
+            std::lock_guard<std::mutex> lock(g_tune_mutex);
+            g_tune[{dev, M}] = best;
+        }
+    }
+    if (e0)
+        (void)hipEventDestroy(e0);
+    if (e1)
+        (void)hipEventDestroy(e1);
+    batched_unpin(maps);
+    return st;
+}
+
+mck_status mck_forward_tuning_get(int64_t n, mck_forward_tuning* out)
+{
+    if (out == nullptr)
+        return fail(MCK_ERR_INVALID_ARG, "out is NULL");
+    if (!is_pow2(n) || n < 2 || n > MCK_MAX_N)
+        return fail(MCK_ERR_INVALID_ARG, "n must be a power of two in [2, MCK_MAX_N]");
+    const FwdTune t = current_tuning(log2i(n));
+    out->split = t.P;
+    out->waves = t.waves;
+    return MCK_OK;
+}
+
+mck_status mck_forward_tuning_set(int64_t n, const mck_forward_tuning* t)
+{
+    if (!is_pow2(n) || n < 2 || n > MCK_MAX_N)
+        return fail(MCK_ERR_INVALID_ARG, "n must be a power of two in [2, MCK_MAX_N]");
+    const int M = log2i(n);
+    if (t != nullptr) {
+        if (!mck::fwd_split_ok(M, t->split))
+            return fail(MCK_ERR_UNSUPPORTED, "register split not compiled for this n");
+        if (t->waves < 64 || t->waves > (1 << 20))
+            return fail(MCK_ERR_INVALID_ARG, "waves must be in [64, 2^20]");
+    }
+    int dev = 0;
+    const hipError_t err = hipGetDevice(&dev);
+    if (err != hipSuccess)
+        return hip_fail(err, "hipGetDevice");
+    std::lock_guard<std::mutex> lock(g_tune_mutex);
+    if (t == nullptr)
+        g_tune.erase({dev, M});
+    else
+        g_tune[{dev, M}] = FwdTune{t->split, t->waves};
+    return MCK_OK;
 }
 
 mck_status mck_fastfood_project(const float* x, int64_t batch, int64_t d, int64_t E, uint32_t seed, double sigma,
@@ -714,8 +955,8 @@ mck_status mck_fastfood_forward_p(const float* x, int64_t batch, int64_t d, int6
     st = make_temp_plan(n, E, perm, G, S, s, &tp);
     if (st != MCK_OK)
         return st;
-    hipError_t err = mck::launch_forward(log2i(n), vec_ok(x, phi, d, n), true, x, batch, (int)d, E, B, tp.goffF, tp.GsF,
-                                         tp.Sh, feature_scale(n, E), phi, s);
+    hipError_t err = mck::launch_forward(log2i(n), tp.PF, current_tuning(log2i(n)).waves, vec_ok(x, phi, d, n), true,
+                                         x, batch, (int)d, E, B, tp.goffF, tp.GsF, tp.Sh, feature_scale(n, E), phi, s);
     (void)hipFreeAsync(tp.block, s);
     return err == hipSuccess ? MCK_OK : hip_fail(err, "forward launch");
 }
@@ -797,8 +1038,8 @@ mck_status mck_fastfood_train_step(const float* x, const int32_t* labels, int64_
         return st;
     }
     const int M = log2i(n);
-    err = mck::launch_forward(M, vec_ok(x, phi, d, n), true, x, batch, (int)d, E, B, tp.goffF, tp.GsF, tp.Sh,
-                              feature_scale(n, E), phi, s);
+    err = mck::launch_forward(M, tp.PF, current_tuning(M).waves, vec_ok(x, phi, d, n), true, x, batch, (int)d, E, B,
+                              tp.goffF, tp.GsF, tp.Sh, feature_scale(n, E), phi, s);
     if (err == hipSuccess)
         err = mck::launch_head_logits(phi, W, b, batch, F, (int)C, part, lg, s);
     if (err == hipSuccess)
