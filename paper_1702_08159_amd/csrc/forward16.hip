@@ -1,6 +1,7 @@
 // forward16.hip -- the feature map with 16-bit storage of x and/or phi
 // (bfloat16 or IEEE half), FP32 arithmetic; the kernel is the one of
-// forward.hpp, instantiated here for the 16-bit storage combinations.
+// forward.hpp, instantiated here for the 16-bit storage combinations (for
+// generated maps only: packed parameters at P = 5).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -14,7 +15,7 @@ hipError_t launch_forward_t(int M, int P, int waves, bool vec, int xt, int yt, c
                             int64_t E, const float* B, const uint32_t* goff, const float* Gs, const float* Sx,
                             float cs, void* out, hipStream_t s)
 {
-#define MCK_FWDT_ARGS M, P, waves, vec, true, x, batch, d, E, B, goff, Gs, Sx, cs, out, s
+#define MCK_FWDT_ARGS M, P, waves, true, vec, true, x, batch, d, E, B, goff, Gs, Sx, cs, out, s
     if (xt == kF32 && yt == kBF16)
         return dispatch_m<RunForwardT<kF32, kBF16>::Run>(MCK_FWDT_ARGS);
     if (xt == kF32 && yt == kF16)

@@ -623,10 +623,14 @@ __device__ __forceinline__ uint32_t lane_major_slot(uint32_t i)
     return t * g::EPL + r;
 }
 
-template <int M, int P>
+// PACK (P = 5, generated B): goff in the packed form of forward.hpp, the
+// gather source as a 16-bit LDS float index and the sign words of B after
+// the E expansions' indices.
+template <int M, int P, bool PACK>
 __global__ void k_derive(int64_t E, const int32_t* __restrict__ perm, const float* __restrict__ G,
-                         const double* __restrict__ S64, const float* __restrict__ S32, uint32_t* __restrict__ goff,
-                         float* __restrict__ Gk, float* __restrict__ Gs, float* __restrict__ Sh)
+                         const float* __restrict__ Bsign, const double* __restrict__ S64,
+                         const float* __restrict__ S32, uint32_t* __restrict__ goff, float* __restrict__ Gk,
+                         float* __restrict__ Gs, float* __restrict__ Sh)
 {
     using g = Geo<M, P>;
     constexpr int K = g::K, EPL = g::EPL, n = g::n;
@@ -642,7 +646,21 @@ __global__ void k_derive(int64_t E, const int32_t* __restrict__ perm, const floa
     const uint32_t t = g::kMulti ? lane : lane % g::LPR;
     const uint32_t i = tpart<M, P, g::GL>(t) | rpart(M, P, g::GL, r);
     const uint32_t src = (uint32_t)perm[e * n + i] & (uint32_t)(n - 1);
-    goff[idx] = 4u * (grp * (uint32_t)g::STRIDE + phys<P>(src));
+    if constexpr (PACK) {
+        static_assert((int64_t)g::RPB * g::STRIDE <= 65536, "16-bit LDS float index");
+        reinterpret_cast<uint16_t*>(goff)[idx] = (uint16_t)(grp * (uint32_t)g::STRIDE + phys<P>(src));
+        if (q < (uint32_t)g::LPR) {
+            // sign word of lane-in-row t = q: bit r set where B is -1 at the
+            // element register r holds in the coalesced layout
+            uint32_t w = 0;
+            const uint32_t tb = tpart<M, P, 0>(q);
+            for (int rr = 0; rr < EPL; ++rr)
+                w |= (Bsign[e * n + (tb | rpart(M, P, 0, rr))] < 0.f ? 1u : 0u) << rr;
+            goff[packed_sign_word0<M, P>(E) + e * g::LPR + q] = w;
+        }
+    } else {
+        goff[idx] = 4u * (grp * (uint32_t)g::STRIDE + phys<P>(src));
+    }
     if (q < (uint32_t)n) {
         const uint32_t tq = q / EPL;
         const uint32_t iq = tpart<M, P, g::GL>(tq) | rpart(M, P, g::GL, (int)(q % EPL));
@@ -786,47 +804,59 @@ struct RunPlanElems {
     }
 };
 
-template <int M, int P>
-hipError_t derive_one(int64_t E, const int32_t* perm, const float* G, const double* S64, const float* S32,
-                      uint32_t* goff, float* Gk, float* Gs, float* Sh, hipStream_t s)
+template <int M, int P, bool PACK = false>
+hipError_t derive_one(int64_t E, const int32_t* perm, const float* G, const float* Bsign, const double* S64,
+                      const float* S32, uint32_t* goff, float* Gk, float* Gs, float* Sh, hipStream_t s)
 {
     const int64_t t = E * Geo<M, P>::RPB * Geo<M, P>::n;
-    k_derive<M, P><<<dim3((unsigned)((t + 255) / 256)), dim3(256), 0, s>>>(E, perm, G, S64, S32, goff, Gk, Gs, Sh);
+    k_derive<M, P, PACK><<<dim3((unsigned)((t + 255) / 256)), dim3(256), 0, s>>>(E, perm, G, Bsign, S64, S32, goff,
+                                                                                 Gk, Gs, Sh);
     return hipGetLastError();
 }
 
-// forward arrays (and Sh when given) for register split PF
+// forward arrays (and Sh when given) for register split PF; packed at P = 5
+// when Bsign (the generated B) is given
+template <int M, int PF>
+hipError_t derive_fwd_p(int64_t E, const int32_t* perm, const float* G, const float* Bsign, const double* S64,
+                        const float* S32, uint32_t* goff_f, float* Gs_f, float* Sh, hipStream_t s)
+{
+    if constexpr (PF == 5)
+        if (Bsign)
+            return derive_one<M, PF, true>(E, perm, G, Bsign, S64, S32, goff_f, nullptr, Gs_f, Sh, s);
+    return derive_one<M, PF>(E, perm, G, nullptr, S64, S32, goff_f, nullptr, Gs_f, Sh, s);
+}
+
 template <int M>
-hipError_t derive_fwd(int PF, int64_t E, const int32_t* perm, const float* G, const double* S64, const float* S32,
-                      uint32_t* goff_f, float* Gs_f, float* Sh, hipStream_t s)
+hipError_t derive_fwd(int PF, int64_t E, const int32_t* perm, const float* G, const float* Bsign, const double* S64,
+                      const float* S32, uint32_t* goff_f, float* Gs_f, float* Sh, hipStream_t s)
 {
     if (PF == fwd_p(M))
-        return derive_one<M, fwd_p(M)>(E, perm, G, S64, S32, goff_f, nullptr, Gs_f, Sh, s);
+        return derive_fwd_p<M, fwd_p(M)>(E, perm, G, Bsign, S64, S32, goff_f, Gs_f, Sh, s);
     if constexpr (fwd_p_tunable(M))
         if (PF == fwd_p_alt(M))
-            return derive_one<M, fwd_p_alt(M)>(E, perm, G, S64, S32, goff_f, nullptr, Gs_f, Sh, s);
+            return derive_fwd_p<M, fwd_p_alt(M)>(E, perm, G, Bsign, S64, S32, goff_f, Gs_f, Sh, s);
     return hipErrorInvalidValue;
 }
 
 template <int M>
 struct RunDerive {
-    static hipError_t run(int PF, int64_t E, const int32_t* perm, const float* G, const double* S64,
-                          const float* S32, uint32_t* goff_f, float* Gs_f, uint32_t* goff_b, float* Gk_b, float* Sh,
-                          hipStream_t s)
+    static hipError_t run(int PF, int64_t E, const int32_t* perm, const float* G, const float* Bsign,
+                          const double* S64, const float* S32, uint32_t* goff_f, float* Gs_f, uint32_t* goff_b,
+                          float* Gk_b, float* Sh, hipStream_t s)
     {
-        const hipError_t err = derive_fwd<M>(PF, E, perm, G, S64, S32, goff_f, Gs_f, Sh, s);
+        const hipError_t err = derive_fwd<M>(PF, E, perm, G, Bsign, S64, S32, goff_f, Gs_f, Sh, s);
         if (err != hipSuccess)
             return err;
-        return derive_one<M, bwd_p(M)>(E, perm, G, S64, S32, goff_b, Gk_b, nullptr, nullptr, s);
+        return derive_one<M, bwd_p(M)>(E, perm, G, nullptr, S64, S32, goff_b, Gk_b, nullptr, nullptr, s);
     }
 };
 
 template <int M>
 struct RunDeriveFwd {
-    static hipError_t run(int PF, int64_t E, const int32_t* perm, const float* G, uint32_t* goff_f, float* Gs_f,
-                          hipStream_t s)
+    static hipError_t run(int PF, int64_t E, const int32_t* perm, const float* G, const float* Bsign,
+                          uint32_t* goff_f, float* Gs_f, hipStream_t s)
     {
-        return derive_fwd<M>(PF, E, perm, G, nullptr, nullptr, goff_f, Gs_f, nullptr, s);
+        return derive_fwd<M>(PF, E, perm, G, Bsign, nullptr, nullptr, goff_f, Gs_f, nullptr, s);
     }
 };
 
@@ -847,12 +877,12 @@ hipError_t launch_fwht(int M, float* data, int64_t batch, bool vec, hipStream_t 
     return dispatch_m<RunFwht>(M, data, batch, vec, s);
 }
 
-hipError_t launch_forward(int M, int P, int waves, bool vec, bool trig, const float* x, int64_t batch, int d,
-                          int64_t E, const float* B, const uint32_t* goff, const float* Gs, const float* Sx,
+hipError_t launch_forward(int M, int P, int waves, bool packed, bool vec, bool trig, const float* x, int64_t batch,
+                          int d, int64_t E, const float* B, const uint32_t* goff, const float* Gs, const float* Sx,
                           float cs, float* out, hipStream_t s)
 {
-    return dispatch_m<RunForwardT<kF32, kF32>::Run>(M, P, waves, vec, trig, x, batch, d, E, B, goff, Gs, Sx, cs,
-                                                    out, s);
+    return dispatch_m<RunForwardT<kF32, kF32>::Run>(M, P, waves, packed, vec, trig, x, batch, d, E, B, goff, Gs, Sx,
+                                                    cs, out, s);
 }
 
 bool fwd_split_ok(int M, int P)
@@ -973,17 +1003,17 @@ void plan_elems(int M, int64_t* fwd_goff, int64_t* bwd_goff)
     (void)dispatch_m<RunPlanElems>(M, fwd_goff, bwd_goff);
 }
 
-hipError_t launch_derive(int M, int PF, int64_t E, const int32_t* perm, const float* G, const double* S64,
-                         const float* S32, uint32_t* goff_f, float* Gs_f, uint32_t* goff_b, float* Gk_b, float* Sh,
-                         hipStream_t s)
+hipError_t launch_derive(int M, int PF, int64_t E, const int32_t* perm, const float* G, const float* Bsign,
+                         const double* S64, const float* S32, uint32_t* goff_f, float* Gs_f, uint32_t* goff_b,
+                         float* Gk_b, float* Sh, hipStream_t s)
 {
-    return dispatch_m<RunDerive>(M, PF, E, perm, G, S64, S32, goff_f, Gs_f, goff_b, Gk_b, Sh, s);
+    return dispatch_m<RunDerive>(M, PF, E, perm, G, Bsign, S64, S32, goff_f, Gs_f, goff_b, Gk_b, Sh, s);
 }
 
-hipError_t launch_derive_fwd(int M, int PF, int64_t E, const int32_t* perm, const float* G, uint32_t* goff_f,
-                             float* Gs_f, hipStream_t s)
+hipError_t launch_derive_fwd(int M, int PF, int64_t E, const int32_t* perm, const float* G, const float* Bsign,
+                             uint32_t* goff_f, float* Gs_f, hipStream_t s)
 {
-    return dispatch_m<RunDeriveFwd>(M, PF, E, perm, G, goff_f, Gs_f, s);
+    return dispatch_m<RunDeriveFwd>(M, PF, E, perm, G, Bsign, goff_f, Gs_f, s);
 }
 
 }  // namespace mck

@@ -26,12 +26,16 @@ hipError_t launch_boxmuller(const uint32_t* a, const uint32_t* b, int64_t count,
 // fwd_goff is the largest count over the forward's compiled register
 // splits, so that one allocation serves whichever split a plan uses.
 void plan_elems(int M, int64_t* fwd_goff, int64_t* bwd_goff);
-hipError_t launch_derive(int M, int PF, int64_t E, const int32_t* perm, const float* G, const double* S64,
-                         const float* S32, uint32_t* goff_f, float* Gs_f, uint32_t* goff_b, float* Gk_b, float* Sh,
-                         hipStream_t s);
+// Bsign: the generated +-1 diagonal B of a seed plan, or null for
+// caller-given diagonals; with it the forward arrays of split PF = 5 are
+// derived in the packed form of forward.hpp (16-bit gather indices and the
+// sign words of B).
+hipError_t launch_derive(int M, int PF, int64_t E, const int32_t* perm, const float* G, const float* Bsign,
+                         const double* S64, const float* S32, uint32_t* goff_f, float* Gs_f, uint32_t* goff_b,
+                         float* Gk_b, float* Sh, hipStream_t s);
 // The forward arrays alone (goff_f, Gs_f) for register split PF.
-hipError_t launch_derive_fwd(int M, int PF, int64_t E, const int32_t* perm, const float* G, uint32_t* goff_f,
-                             float* Gs_f, hipStream_t s);
+hipError_t launch_derive_fwd(int M, int PF, int64_t E, const int32_t* perm, const float* G, const float* Bsign,
+                             uint32_t* goff_f, float* Gs_f, hipStream_t s);
 
 // Forward register splits (register bits per layout, 4 or 5) compiled for
 // n = 2^M, and the default one.
@@ -44,13 +48,16 @@ hipError_t launch_fwht(int M, float* data, int64_t batch, bool vec, hipStream_t 
 
 // Forward: phi (trig = true) or z = S H G Pi H B xhat (trig = false).  P is
 // the register split the arrays goff, Gs were derived for; the expansions
-// are split into chunks until the grid holds about `waves` waves.
-hipError_t launch_forward(int M, int P, int waves, bool vec, bool trig, const float* x, int64_t batch, int d,
-                          int64_t E, const float* B, const uint32_t* goff, const float* Gs, const float* Sx,
+// are split into chunks until the grid holds about `waves` waves.  packed:
+// the arrays belong to a seed plan (derived with Bsign); caller-given
+// diagonals (packed = false) support only the feature map at P = 5.
+hipError_t launch_forward(int M, int P, int waves, bool packed, bool vec, bool trig, const float* x, int64_t batch,
+                          int d, int64_t E, const float* B, const uint32_t* goff, const float* Gs, const float* Sx,
                           float cs, float* out, hipStream_t s);
 
 // Forward with 16-bit storage (forward16.hip): xt, yt = 0 (FP32), 1 (bf16),
-// 2 (half); supported pairs (0,1), (0,2), (1,1), (2,2); the feature map only.
+// 2 (half); supported pairs (0,1), (0,2), (1,1), (2,2); the feature map of
+// a seed plan only.
 hipError_t launch_forward_t(int M, int P, int waves, bool vec, int xt, int yt, const void* x, int64_t batch, int d,
                             int64_t E, const float* B, const uint32_t* goff, const float* Gs, const float* Sx,
                             float cs, void* out, hipStream_t s);

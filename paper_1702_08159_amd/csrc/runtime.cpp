@@ -283,10 +283,10 @@ mck_status get_plan(uint32_t seed, int64_t n, int64_t E, double sigma, int calib
     err = mck::launch_generate(seed, n, E, sigma, matern_t, p.B, p.perm, p.G, p.S64, p.S32, p.norm2, stream);
     if (err == hipSuccess)
         err = n > MCK_MAX_N ? mck::launch_sh(p.S64, p.Sh, n * E, stream)
-                            : mck::launch_derive(M, mck::fwd_split_default(M), E, p.perm, p.G, p.S64, p.S32,
+                            : mck::launch_derive(M, mck::fwd_split_default(M), E, p.perm, p.G, p.B, p.S64, p.S32,
                                                  p.goffF, p.GsF, p.goffB, p.GkB, p.Sh, stream);
     if (err == hipSuccess && two)
-        err = mck::launch_derive_fwd(M, alt_split(M), E, p.perm, p.G, p.goffF2, p.GsF2, stream);
+        err = mck::launch_derive_fwd(M, alt_split(M), E, p.perm, p.G, p.B, p.goffF2, p.GsF2, stream);
     if (err == hipSuccess && n > MCK_MAX_N)
         err = mck::launch_buckets(log2i(n), E, p.perm, p.G, p.packA, p.dstB, p.pdelta, p.Gx, p.bscratch, stream);
     if (err == hipSuccess)
@@ -345,8 +345,8 @@ mck_status make_temp_plan(int64_t n, int64_t E, const int32_t* perm, const float
     tp->GkB = reinterpret_cast<float*>(b + af + ab + a);
     tp->Sh = reinterpret_cast<float*>(b + af + ab + 2 * a);
     tp->PF = current_tuning(log2i(n)).P;
-    err = mck::launch_derive(log2i(n), tp->PF, E, perm, G, nullptr, S, tp->goffF, tp->GsF, tp->goffB, tp->GkB,
-                             tp->Sh, s);
+    err = mck::launch_derive(log2i(n), tp->PF, E, perm, G, nullptr, nullptr, S, tp->goffF, tp->GsF, tp->goffB,
+                             tp->GkB, tp->Sh, s);
     if (err != hipSuccess) {
         (void)hipFreeAsync(tp->block, s);
         return hip_fail(err, "derive kernel");
@@ -561,9 +561,9 @@ static mck_status forward_common(const float* x, int64_t batch, int64_t d, int64
         return forward_long(p, x, 0, batch, d, n, E, out, 0, s);
     const FwdTune t = current_tuning(log2i(n));
     const FwdArrays a = fwd_arrays(p, t.P);
-    const hipError_t err = mck::launch_forward(log2i(n), t.P, t.waves, vec_ok(x, out, d, n), trig, x, batch, (int)d,
-                                               E, p->B, a.goff, a.Gs, trig ? p->Sh : p->S32, feature_scale(n, E),
-                                               out, s);
+    const hipError_t err = mck::launch_forward(log2i(n), t.P, t.waves, true, vec_ok(x, out, d, n), trig, x, batch,
+                                               (int)d, E, p->B, a.goff, a.Gs, trig ? p->Sh : p->S32,
+                                               feature_scale(n, E), out, s);
     return err == hipSuccess ? MCK_OK : hip_fail(err, "forward launch");
 }
 
@@ -693,8 +693,8 @@ hipError_t launch_maps(int M, const FwdTune& t, const std::vector<MapRef>& maps,
             grp[vec ? 1 : 0].push_back(
                 {q.x, q.batch, (int)q.d, q.E, m.p->B, a.goff, a.Gs, m.p->Sh, feature_scale(n, q.E), q.phi});
         } else if (err == hipSuccess) {
-            err = mck::launch_forward(M, t.P, t.waves, vec, true, q.x, q.batch, (int)q.d, q.E, m.p->B, a.goff, a.Gs,
-                                      m.p->Sh, feature_scale(n, q.E), q.phi, s);
+            err = mck::launch_forward(M, t.P, t.waves, true, vec, true, q.x, q.batch, (int)q.d, q.E, m.p->B, a.goff,
+                                      a.Gs, m.p->Sh, feature_scale(n, q.E), q.phi, s);
         }
     }
     for (int v = 0; v < 2 && err == hipSuccess; ++v)
@@ -955,8 +955,9 @@ mck_status mck_fastfood_forward_p(const float* x, int64_t batch, int64_t d, int6
     st = make_temp_plan(n, E, perm, G, S, s, &tp);
     if (st != MCK_OK)
         return st;
-    hipError_t err = mck::launch_forward(log2i(n), tp.PF, current_tuning(log2i(n)).waves, vec_ok(x, phi, d, n), true,
-                                         x, batch, (int)d, E, B, tp.goffF, tp.GsF, tp.Sh, feature_scale(n, E), phi, s);
+    hipError_t err = mck::launch_forward(log2i(n), tp.PF, current_tuning(log2i(n)).waves, false, vec_ok(x, phi, d, n),
+                                         true, x, batch, (int)d, E, B, tp.goffF, tp.GsF, tp.Sh, feature_scale(n, E),
+                                         phi, s);
     (void)hipFreeAsync(tp.block, s);
     return err == hipSuccess ? MCK_OK : hip_fail(err, "forward launch");
 }
@@ -1038,8 +1039,8 @@ mck_status mck_fastfood_train_step(const float* x, const int32_t* labels, int64_
         return st;
     }
     const int M = log2i(n);
-    err = mck::launch_forward(M, tp.PF, current_tuning(M).waves, vec_ok(x, phi, d, n), true, x, batch, (int)d, E, B,
-                              tp.goffF, tp.GsF, tp.Sh, feature_scale(n, E), phi, s);
+    err = mck::launch_forward(M, tp.PF, current_tuning(M).waves, false, vec_ok(x, phi, d, n), true, x, batch, (int)d,
+                              E, B, tp.goffF, tp.GsF, tp.Sh, feature_scale(n, E), phi, s);
     if (err == hipSuccess)
         err = mck::launch_head_logits(phi, W, b, batch, F, (int)C, part, lg, s);
     if (err == hipSuccess)

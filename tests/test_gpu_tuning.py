@@ -51,7 +51,7 @@ def bf16_rne(f32):
 
 def test_defaults(mk):
     for m in range(1, 16):
-        assert mk.forward_tuning(1 << m) == ((5 if m >= 14 else 4), 16384)
+        assert mk.forward_tuning(1 << m) == ((5 if m >= 13 else 4), 16384)
 
 
 def test_set_is_validated(mk):
