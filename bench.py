@@ -50,7 +50,7 @@ KERNEL_SOURCES = ("paper_1702_08159_amd/csrc/forward.hpp", "paper_1702_08159_amd
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 TRAFFIC_KIB = {
     # sha1 of the kernel sources: (FETCH_SIZE KiB, WRITE_SIZE KiB) per launch
-    "f275bed66f257f976b7272b7321214ac56330ad8": (13863.0, 1048589.9),
+    "f87e527b18d0c0258c40d255630fc08b9c31fea5": (13861.5, 1048608.9),
 }
 
 
@@ -216,6 +216,60 @@ def main():
             longv[name]["speedup_vs_f32"] = longv["f32"]["ms_per_step"] / longv[name]["ms_per_step"]
         xl_head = xl[:3].cpu().numpy()
         del xl
+    small = None
+    if args.only in ("fwd", "all") and args.batched_steps > 0:
+        # 256 small maps: n = 2^U{6..11}, batch U{16..256}, E U{1..4}, N(0,1)
+        # rows, sigma = sqrt(n): one map alone cannot fill the GPU, so one
+        # grouped launch per n against one launch per map, each replayed from
+        # a HIP graph (GPU time only) and called eagerly (with host overhead)
+        rng = np.random.default_rng(1)
+        ms_, bs_, es_ = rng.integers(6, 12, 256), rng.integers(16, 257, 256), rng.integers(1, 5, 256)
+        smaps, souts, salg = [], [], 0
+        for k in range(256):
+            n_k, b_k, e_k = 1 << int(ms_[k]), int(bs_[k]), int(es_[k])
+            xk = torch.randn((b_k, n_k), generator=torch.Generator(device=dev).manual_seed(10000 + k), device=dev)
+            smaps.append((xk, e_k, 3000 + k, float(n_k) ** 0.5))
+            souts.append(torch.empty((b_k, 2 * n_k * e_k), dtype=torch.float32, device=dev))
+            salg += b_k * (4 * n_k + 8 * n_k * e_k)
+
+        def s_batched():
+            mk.forward_batched(smaps, outs=souts)
+
+        def s_single():
+            for (xk, e_k, s_k, sg_k), o in zip(smaps, souts):
+                mk.forward(xk, e_k, s_k, sg_k, out=o)
+
+        sres = {}
+        for name, fn in (("batched", s_batched), ("one_call_per_map", s_single)):
+            fn()  # plans built and cached
+            torch.cuda.synchronize()
+            t0.record(stream)
+            for _ in range(10):
+                fn()
+            t1.record(stream)
+            torch.cuda.synchronize()
+            sres[name + "_eager"] = t0.elapsed_time(t1) / 10
+            gs = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(gs):
+                fn()
+            gs.replay()
+            torch.cuda.synchronize()
+            t0.record(stream)
+            for _ in range(10):
+                gs.replay()
+            t1.record(stream)
+            torch.cuda.synchronize()
+            sres[name + "_graph"] = t0.elapsed_time(t1) / 10
+            del gs
+            log("256 small maps, %s: %.3f ms eager, %.3f ms graph replay"
+                % (name, sres[name + "_eager"], sres[name + "_graph"]))
+        small = {"maps": 256, "phi_GB": sum(o.numel() for o in souts) * 4 / 1e9,
+                 **{k + "_ms": v for k, v in sres.items()},
+                 "speedup_graph": sres["one_call_per_map_graph"] / sres["batched_graph"],
+                 "speedup_eager": sres["one_call_per_map_eager"] / sres["batched_eager"],
+                 "achieved_GBs_graph": salg / (sres["batched_graph"] * 1e-3) / 1e9}
+        del smaps, souts
+        torch.cuda.empty_cache()
     batched = None
     if args.only in ("fwd", "all") and args.batched_steps > 0:
         # 32 independent maps: n = 2^U{8..16}, batch U{16..4096}, E U{1..16},
@@ -402,6 +456,7 @@ def main():
         "bwd_steps": args.bwd_steps,
         "fwd_16bit_phi": lowp,
         "batched_uneven_maps": batched,
+        "batched_small_maps": small,
         "long_vectors": {"config": {"batch": LONG_BATCH, "n": LONG_N, "E": LONG_E, "sigma": LONG_SIGMA,
                                     "x": "N(0,1) float32"}, **longv} if longv else None,
         "train_step_ms": train_ms,
