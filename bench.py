@@ -275,11 +275,8 @@ def main():
         # 32 independent maps: n = 2^U{8..16}, batch U{16..4096}, E U{1..16},
         # N(0,1) rows of length n, sigma = sqrt(n); one batched call vs one
         # call per map
-        rng = np.random.default_rng(0)
-        ms_, bs_, es_ = rng.integers(8, 17, 32), rng.integers(16, 4097, 32), rng.integers(1, 17, 32)
         maps, outs, alg = [], [], 0
-        for k in range(32):
-            n_k, b_k, e_k = 1 << int(ms_[k]), int(bs_[k]), int(es_[k])
+        for k, (n_k, b_k, e_k) in enumerate(workloads.ragged_instances(32, 0)):
             xk = torch.randn((b_k, n_k), generator=torch.Generator(device=dev).manual_seed(k), device=dev)
             maps.append((xk, e_k, 2000 + k, float(n_k) ** 0.5))
             outs.append(torch.empty((b_k, 2 * n_k * e_k), dtype=torch.float32, device=dev))

@@ -78,3 +78,41 @@ def test_batched_validates_before_enqueue(mk):
     bad = (torch.zeros((2, 8), device="cuda"), 1, 1, -1.0)
     with pytest.raises(mk.MckError, match="instance 1"):
         mk.forward_batched([good, bad])
+
+
+def test_full_uneven_set_sampled(mk, orc):
+    # the 32-map set the benchmark times (n = 2^8..2^16, batch up to 4096,
+    # E up to 16: 64 GB of phi), in its launch configuration: sampled rows
+    # of sampled maps against the oracle, and each sampled map equal to its
+    # own single call bit for bit, before and after the autotuner
+    import torch
+
+    specs = workloads.ragged_instances(32, 0)
+    maps, outs = [], []
+    for k, (n, b, E) in enumerate(specs):
+        x = torch.randn((b, n), generator=torch.Generator(device="cuda").manual_seed(k), device="cuda")
+        maps.append((x, E, 2000 + k, float(n) ** 0.5))
+        outs.append(torch.empty((b, 2 * n * E), dtype=torch.float32, device="cuda"))
+    order = sorted(range(32), key=lambda k: specs[k][0])
+    picks = sorted({order[0], order[10], order[20], order[-4], order[-2], order[-1]})
+    rng = np.random.default_rng(5)
+    try:
+        for tuned in (False, True):
+            if tuned:
+                mk.autotune_batched(maps, outs=outs, reps=1)
+            mk.forward_batched(maps, outs=outs)
+            torch.cuda.synchronize()
+            for k in picks:
+                x, E, s, sg = maps[k]
+                assert torch.equal(outs[k], mk.forward(x, E, s, sg)), (k, tuned)
+                rows = rng.choice(x.shape[0], size=2, replace=False)
+                xr = x[rows].cpu().numpy().astype(np.float64)
+                ref, _, _ = orc.forward(xr, E, s, sg)
+                got = outs[k][rows].cpu().numpy().astype(np.float64)
+                rel = np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)
+                assert rel.max() <= 1e-5, (k, specs[k], tuned, rel.max())
+    finally:
+        for m in range(1, 16):
+            mk.set_forward_tuning(1 << m)
+        del maps, outs
+        torch.cuda.empty_cache()

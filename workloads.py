@@ -47,10 +47,5 @@ def grad_features(batch: int, width: int, seed: int = 1) -> np.ndarray:
 
 def ragged_instances(count: int = 32, seed: int = 0):
     rng = np.random.default_rng(seed)
-    out = []
-    for _ in range(count):
-        n = 1 << int(rng.integers(8, 17))
-        batch = int(rng.integers(16, 4097))
-        E = int(rng.integers(1, 17))
-        out.append((n, batch, E))
-    return out
+    ms, bs, es = rng.integers(8, 17, count), rng.integers(16, 4097, count), rng.integers(1, 17, count)
+    return [(1 << int(m), int(b), int(e)) for m, b, e in zip(ms, bs, es)]
