@@ -263,6 +263,22 @@ def main():
             del gs
             log("256 small maps, %s: %.3f ms eager, %.3f ms graph replay"
                 % (name, sres[name + "_eager"], sres[name + "_graph"]))
+        # the same batched call recorded by the library (mck_batched_graph_*)
+        # and launched from Python: one graph launch per call, no per-map host work
+        lg = mk.BatchedGraph(smaps, outs=souts)
+        lg.launch()
+        torch.cuda.synchronize()
+        tt = time.perf_counter()
+        t0.record(stream)
+        for _ in range(10):
+            lg.launch()
+        t1.record(stream)
+        torch.cuda.synchronize()
+        sres["batched_library_graph"] = t0.elapsed_time(t1) / 10
+        host_ms = (time.perf_counter() - tt) * 1e3 / 10
+        lg.close()
+        log("256 small maps, library-recorded graph: %.3f ms per launch (%.3f ms wall per call)"
+            % (sres["batched_library_graph"], host_ms))
         small = {"maps": 256, "phi_GB": sum(o.numel() for o in souts) * 4 / 1e9,
                  **{k + "_ms": v for k, v in sres.items()},
                  "speedup_graph": sres["one_call_per_map_graph"] / sres["batched_graph"],

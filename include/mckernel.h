@@ -179,6 +179,26 @@ typedef struct mck_instance {
 mck_status mck_fastfood_forward_batched(const mck_instance* inst, int64_t count, mck_stream stream);
 
 /*
+ * Recorded batched call.  mck_batched_graph_create does what
+ * mck_fastfood_forward_batched does for `inst` (validation first, plans
+ * built on `stream`, which it synchronizes) but records the launches into a
+ * HIP graph instead of running them, with the forward tuning current at
+ * that moment; the instances (pointers and sizes) are copied.  Every
+ * mck_batched_graph_launch then enqueues the whole set on `stream` as one
+ * graph launch: same results bit for bit as the eager call, no allocation,
+ * no host work per map.  The object keeps the maps' plans from eviction and
+ * owns the long maps' scratch rows, so replays that overlap on several
+ * streams race on that scratch; mck_batched_graph_destroy waits for the
+ * device, then frees both.  Destroy every graph before mck_shutdown.
+ * Launching on a device other than the recording one is MCK_ERR_INVALID_ARG.
+ */
+typedef struct mck_batched_graph mck_batched_graph;
+mck_status mck_batched_graph_create(const mck_instance* inst, int64_t count, mck_stream stream,
+                                    mck_batched_graph** out);
+mck_status mck_batched_graph_launch(mck_batched_graph* graph, mck_stream stream);
+void mck_batched_graph_destroy(mck_batched_graph* graph);
+
+/*
  * Launch choice of the single-pass forward for one n (2 <= n <= MCK_MAX_N,
  * a power of two).  The operation is fixed by equation "mckernel" of section
  * "McKernel"; these two numbers only choose how the kernel covers it:

@@ -39,7 +39,7 @@ MAX_N = 32768
 __all__ = ["padded_dim", "fwht", "fwht_", "params", "forward", "project", "backward", "forward_p",
            "backward_p", "fastfood", "FastfoodFunction", "FastfoodExplicit", "gen_boxmuller", "shutdown",
            "MckError", "PAPER_SEED", "MAX_N", "forward_batched", "autotune_batched", "forward_tuning",
-           "set_forward_tuning"]
+           "set_forward_tuning", "BatchedGraph"]
 
 
 def _stream(t: torch.Tensor):
@@ -177,6 +177,40 @@ def forward_batched(maps, outs=None):
         _lib.call("mck_fastfood_forward_batched", ctypes.cast(arr, ctypes.c_void_p), len(maps),
                   _stream(maps[0][0]))
     return res
+
+
+class BatchedGraph:
+    """A batched call recorded once into a HIP graph by the library
+    (mck_batched_graph_create) and replayed with launch(): `maps` as for
+    forward_batched; `phis` are the output tensors every launch rewrites.
+    The tensors of `maps` and `phis` must stay alive while the object does."""
+
+    def __init__(self, maps, outs=None):
+        maps = list(maps)
+        if not maps:
+            raise ValueError("no maps")
+        arr, self.phis, self.device = _instances(maps, outs)
+        self._keep = ([m[0] for m in maps], self.phis)
+        self._h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _lib.call("mck_batched_graph_create", ctypes.cast(arr, ctypes.c_void_p), len(maps),
+                      _stream(maps[0][0]), ctypes.byref(self._h))
+
+    def launch(self):
+        with torch.cuda.device(self.device):
+            _lib.call("mck_batched_graph_launch", self._h, _stream(self.phis[0]))
+        return self.phis
+
+    def close(self):
+        if self._h:
+            _lib.lib().mck_batched_graph_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def autotune_batched(maps, outs=None, reps: int = 3):

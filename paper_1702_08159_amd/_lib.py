@@ -36,6 +36,9 @@ SIGNATURES = {
     "mck_forward_tuning_get": (_int, [_i64, _vp]),
     "mck_forward_tuning_set": (_int, [_i64, _vp]),
     "mck_autotune_forward_batched": (_int, [_vp, _i64, ctypes.c_int32, _vp]),
+    "mck_batched_graph_create": (_int, [_vp, _i64, _vp, _vp]),
+    "mck_batched_graph_launch": (_int, [_vp, _vp]),
+    "mck_batched_graph_destroy": (None, [_vp]),
     "mck_fastfood_backward": (_int, [_vp, _vp, _i64, _i64, _i64, _u32, _f64, _int, _vp, _vp, _vp, _vp, _vp]),
     "mck_fastfood_forward_p": (_int, [_vp, _i64, _i64, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
     "mck_fastfood_backward_p": (_int, [_vp, _vp, _i64, _i64, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp,

@@ -11,6 +11,7 @@
 #include <map>
 #include <vector>
 #include <mutex>
+#include <new>
 #include <string>
 
 #include "mckernel.h"
@@ -500,34 +501,57 @@ mck_status mck_fastfood_params(uint32_t seed, int64_t n, int64_t E, double sigma
 // scratch per row, so only a row of phi must stay below 2^31 bytes; rows go
 // in equal chunks of at most 2^27 floats per FP32 scratch buffer (u, w,
 // stream-ordered).
-static mck_status forward_long(const Plan* p, const void* x, int xt, int64_t batch, int64_t d, int64_t n, int64_t E,
-                               void* phi, int yt, hipStream_t s)
+// Rows per launch of the long-vector path (the FP32 scratch rows u, w hold
+// at most 2^27 floats each).
+static int64_t long_rows_per(int64_t batch, int64_t n)
+{
+    const int64_t max_rows = ((int64_t)1 << 27) / n;
+    const int64_t nchunks = (batch + max_rows - 1) / max_rows;
+    return (batch + nchunks - 1) / nchunks;
+}
+
+// Launches of the long-vector feature map with caller-provided scratch u
+// (2 x long_rows_per(batch, n) x n floats).
+static mck_status forward_long_launch(const Plan* p, const void* x, int xt, int64_t batch, int64_t d, int64_t n,
+                                      int64_t E, void* phi, int yt, float* u, hipStream_t s)
 {
     const int64_t xb = xt == 0 ? 4 : 2, yb = yt == 0 ? 4 : 2;
     const int64_t row_phi = 2 * n * E * yb;
-    if (row_phi > (int64_t(1) << 31) - 4096)
-        return fail(MCK_ERR_UNSUPPORTED, "one row of phi exceeds 2^31 bytes");
-    if (batch == 0)
-        return MCK_OK;
-    const int64_t max_rows = ((int64_t)1 << 27) / n;
-    const int64_t nchunks = (batch + max_rows - 1) / max_rows;
-    const int64_t rows_per = (batch + nchunks - 1) / nchunks;
-    float* u = nullptr;
-    hipError_t err = hipMallocAsync(reinterpret_cast<void**>(&u), (size_t)(2 * rows_per * n) * sizeof(float), s);
-    if (err != hipSuccess)
-        return fail(MCK_ERR_NO_MEMORY, std::string("long-vector scratch: ") + hipGetErrorString(err));
+    const int64_t rows_per = long_rows_per(batch, n);
     float* w = u + rows_per * n;
     const uintptr_t xa = (uintptr_t)(4 * xb);
     const bool vec = reinterpret_cast<uintptr_t>(x) % xa == 0 && d % 4 == 0;
     const float cs = feature_scale(n, E);
+    hipError_t err = hipSuccess;
     for (int64_t r0 = 0; r0 < batch && err == hipSuccess; r0 += rows_per) {
         const int64_t rows = batch - r0 < rows_per ? batch - r0 : rows_per;
         err = mck::launch_forward_long(log2i(n), vec, xt, yt, static_cast<const char*>(x) + r0 * d * xb, rows,
                                        (int)d, E, p->B, p->packA, p->dstB, p->pdelta, p->Gx, p->Sh, cs,
                                        static_cast<char*>(phi) + r0 * row_phi, u, w, s);
     }
-    (void)hipFreeAsync(u, s);
     return err == hipSuccess ? MCK_OK : hip_fail(err, "long-vector forward launch");
+}
+
+// Feature map for n > MCK_MAX_N.  The kernels address phi, x and the
+// scratch per row, so only a row of phi must stay below 2^31 bytes; rows go
+// in equal chunks of at most 2^27 floats per FP32 scratch buffer (u, w,
+// stream-ordered).
+static mck_status forward_long(const Plan* p, const void* x, int xt, int64_t batch, int64_t d, int64_t n, int64_t E,
+                               void* phi, int yt, hipStream_t s)
+{
+    const int64_t yb = yt == 0 ? 4 : 2;
+    if (2 * n * E * yb > (int64_t(1) << 31) - 4096)
+        return fail(MCK_ERR_UNSUPPORTED, "one row of phi exceeds 2^31 bytes");
+    if (batch == 0)
+        return MCK_OK;
+    const int64_t rows_per = long_rows_per(batch, n);
+    float* u = nullptr;
+    hipError_t err = hipMallocAsync(reinterpret_cast<void**>(&u), (size_t)(2 * rows_per * n) * sizeof(float), s);
+    if (err != hipSuccess)
+        return fail(MCK_ERR_NO_MEMORY, std::string("long-vector scratch: ") + hipGetErrorString(err));
+    const mck_status st = forward_long_launch(p, x, xt, batch, d, n, E, phi, yt, u, s);
+    (void)hipFreeAsync(u, s);
+    return st;
 }
 
 static mck_status forward_common(const float* x, int64_t batch, int64_t d, int64_t E, uint32_t seed, double sigma,
@@ -873,6 +897,172 @@ mck_status mck_forward_tuning_set(int64_t n, const mck_forward_tuning* t)
     else
         g_tune[{dev, M}] = FwdTune{t->split, t->waves};
     return MCK_OK;
+}
+
+}  // extern "C"
+
+// A recorded batched call: the maps' plans stay pinned, and the long maps'
+// scratch rows are owned here, so that replays allocate nothing.
+struct mck_batched_graph {
+    int device = 0;
+    std::vector<mck_instance> inst;
+    std::vector<MapRef> maps;
+    void* scratch = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void graph_release(mck_batched_graph* g)
+{
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(g->device);
+    (void)hipDeviceSynchronize();  // no replay may still use the scratch or the plans
+    if (g->exec)
+        (void)hipGraphExecDestroy(g->exec);
+    if (g->graph)
+        (void)hipGraphDestroy(g->graph);
+    if (g->scratch)
+        (void)hipFree(g->scratch);
+    batched_unpin(g->maps);
+    (void)hipSetDevice(cur);
+    delete g;
+}
+
+// Records every launch of the batched call into the stream being captured.
+mck_status record_maps(mck_batched_graph* g, hipStream_t cs)
+{
+    std::map<int, std::vector<MapRef>> by_m;
+    for (const MapRef& m : g->maps) {
+        if (m.n <= MCK_MAX_N) {
+            by_m[log2i(m.n)].push_back(m);
+        } else {
+            const mck_status st = forward_long_launch(m.p, m.q->x, 0, m.q->batch, m.q->d, m.n, m.q->E, m.q->phi, 0,
+                                                      static_cast<float*>(g->scratch), cs);
+            if (st != MCK_OK)
+                return st;
+        }
+    }
+    for (const auto& kv : by_m) {
+        const hipError_t err = launch_maps(kv.first, current_tuning(kv.first), kv.second, cs);
+        if (err != hipSuccess)
+            return hip_fail(err, "batched forward launch");
+    }
+    return MCK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mck_status mck_batched_graph_create(const mck_instance* inst, int64_t count, mck_stream stream,
+                                    mck_batched_graph** out)
+{
+    if (out == nullptr)
+        return fail(MCK_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    hipError_t err = hipStreamIsCapturing(s, &cap);
+    if (err != hipSuccess)
+        return hip_fail(err, "hipStreamIsCapturing");
+    if (cap != hipStreamCaptureStatusNone)
+        return fail(MCK_ERR_INVALID_ARG, "cannot record a batched graph while the stream is being captured");
+    mck_batched_graph* g = new (std::nothrow) mck_batched_graph();
+    if (g == nullptr)
+        return fail(MCK_ERR_NO_MEMORY, "batched graph object");
+    err = hipGetDevice(&g->device);
+    if (err != hipSuccess) {
+        delete g;
+        return hip_fail(err, "hipGetDevice");
+    }
+    // the instances are copied: the recorded launches keep their pointers
+    // and sizes, the caller's array may go away
+    if (count > 0 && inst != nullptr)
+        g->inst.assign(inst, inst + count);
+    mck_status st = batched_setup(count > 0 ? g->inst.data() : inst, count, s, &g->maps);
+    if (st != MCK_OK) {
+        delete g;
+        return st;
+    }
+    // one scratch for the long maps: their launches are serialized in the graph
+    size_t scratch = 0;
+    for (const MapRef& m : g->maps) {
+        if (m.n <= MCK_MAX_N)
+            continue;
+        if (2 * m.n * m.q->E * 4 > (int64_t(1) << 31) - 4096) {
+            graph_release(g);
+            return fail(MCK_ERR_UNSUPPORTED, "one row of phi exceeds 2^31 bytes");
+        }
+        const size_t need = (size_t)(2 * long_rows_per(m.q->batch, m.n) * m.n) * sizeof(float);
+        scratch = need > scratch ? need : scratch;
+    }
+    if (scratch > 0) {
+        err = hipMalloc(&g->scratch, scratch);
+        if (err != hipSuccess) {
+            g->scratch = nullptr;
+            graph_release(g);
+            return fail(MCK_ERR_NO_MEMORY, std::string("long-vector scratch: ") + hipGetErrorString(err));
+        }
+    }
+    if (g->maps.empty()) {  // nothing to record: launches do nothing
+        *out = g;
+        return MCK_OK;
+    }
+    // record on a private stream (default priority), then instantiate
+    hipStream_t cs = nullptr;
+    err = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (err != hipSuccess) {
+        graph_release(g);
+        return hip_fail(err, "capture stream");
+    }
+    err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (err == hipSuccess) {
+        st = record_maps(g, cs);
+        const hipError_t end = hipStreamEndCapture(cs, &g->graph);
+        if (st == MCK_OK && end != hipSuccess)
+            st = hip_fail(end, "hipStreamEndCapture");
+    } else {
+        st = hip_fail(err, "hipStreamBeginCapture");
+    }
+    (void)hipStreamDestroy(cs);
+    if (st == MCK_OK) {
+        err = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+        if (err != hipSuccess) {
+            g->exec = nullptr;
+            st = hip_fail(err, "hipGraphInstantiate");
+        }
+    }
+    if (st != MCK_OK) {
+        graph_release(g);
+        return st;
+    }
+    *out = g;
+    return MCK_OK;
+}
+
+mck_status mck_batched_graph_launch(mck_batched_graph* g, mck_stream stream)
+{
+    if (g == nullptr)
+        return fail(MCK_ERR_INVALID_ARG, "graph is NULL");
+    int dev = 0;
+    hipError_t err = hipGetDevice(&dev);
+    if (err != hipSuccess)
+        return hip_fail(err, "hipGetDevice");
+    if (dev != g->device)
+        return fail(MCK_ERR_INVALID_ARG, "the graph was recorded on another device");
+    if (g->exec == nullptr)
+        return MCK_OK;
+    err = hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream));
+    return err == hipSuccess ? MCK_OK : hip_fail(err, "hipGraphLaunch");
+}
+
+void mck_batched_graph_destroy(mck_batched_graph* g)
+{
+    if (g != nullptr)
+        graph_release(g);
 }
 
 mck_status mck_fastfood_project(const float* x, int64_t batch, int64_t d, int64_t E, uint32_t seed, double sigma,

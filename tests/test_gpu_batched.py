@@ -116,3 +116,32 @@ def test_full_uneven_set_sampled(mk, orc):
             mk.set_forward_tuning(1 << m)
         del maps, outs
         torch.cuda.empty_cache()
+
+
+def test_recorded_graph_replays_match_eager(mk):
+    # mck_batched_graph_create records the batched call (short maps grouped
+    # by n, a long map on the multi-pass path with the object's own scratch,
+    # an empty map); every launch reproduces the eager call bit for bit
+    import torch
+
+    maps = _maps(9, 6, max_batch=40, max_E=3, m_lo=3, m_hi=15)
+    maps.append((workloads.normal(5, 40000, seed=7), 2, 99, 256.0))  # n = 2^16
+    dev = [(torch.from_numpy(x).cuda(), E, s, sg) for x, E, s, sg in maps]
+    dev.append((torch.zeros((0, 300), device="cuda"), 2, 5, 1.0))
+    ref = [p.clone() for p in mk.forward_batched(dev)]
+    g = mk.BatchedGraph(dev)
+    try:
+        for k in range(3):
+            for o in g.phis:
+                o.fill_(float("nan"))
+            out = g.launch()
+            torch.cuda.synchronize()
+            for o, r in zip(out, ref):
+                assert torch.equal(o, r), k
+            junk = mk.forward(dev[0][0][:2], 3, 1, 1.0)  # eager work between launches
+            torch.cuda.synchronize()
+            del junk
+    finally:
+        g.close()
+    with pytest.raises(mk.MckError, match="instance 1"):
+        mk.BatchedGraph([dev[0], (dev[1][0], 1, 1, -1.0)])
