@@ -189,7 +189,8 @@ mck_status mck_fastfood_forward_batched(const mck_instance* inst, int64_t count,
  * no host work per map.  The object keeps the maps' plans from eviction and
  * owns the long maps' scratch rows, so replays that overlap on several
  * streams race on that scratch; mck_batched_graph_destroy waits for the
- * device, then frees both.  Destroy every graph before mck_shutdown.
+ * device, then frees the scratch and releases the plans (mck_shutdown
+ * leaves the plans of live graphs in place).
  * Launching on a device other than the recording one is MCK_ERR_INVALID_ARG.
  */
 typedef struct mck_batched_graph mck_batched_graph;
@@ -347,7 +348,8 @@ mck_status mck_fastfood_train_step(const float* x, const int32_t* labels, int64_
  */
 mck_status mck_axpy(float* y, const float* x, int64_t count, float alpha, mck_stream stream);
 
-/* Frees every cached plan (waits for the device first). */
+/* Frees every cached plan (waits for the device first) except those held by
+ * a live mck_batched_graph or a call in progress on another thread. */
 void mck_shutdown(void);
 
 #ifdef __cplusplus

@@ -1386,15 +1386,19 @@ mck_status mck_axpy(float* y, const float* x, int64_t count, float alpha, mck_st
 void mck_shutdown(void)
 {
     std::lock_guard<std::mutex> lock(g_mutex);
-    for (auto& p : g_plans) {
+    for (auto it = g_plans.begin(); it != g_plans.end();) {
+        if (it->pins > 0) {  // held by a recorded graph or a call in progress
+            ++it;
+            continue;
+        }
         int cur = 0;
         (void)hipGetDevice(&cur);
-        (void)hipSetDevice(p.device);
+        (void)hipSetDevice(it->device);
         (void)hipDeviceSynchronize();
         (void)hipSetDevice(cur);
-        free_plan(p);
+        free_plan(*it);
+        it = g_plans.erase(it);
     }
-    g_plans.clear();
 }
 
 }  // extern "C"
