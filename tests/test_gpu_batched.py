@@ -141,6 +141,8 @@ def test_recorded_graph_replays_match_eager(mk):
             junk = mk.forward(dev[0][0][:2], 3, 1, 1.0)  # eager work between launches
             torch.cuda.synchronize()
             del junk
+            if k == 1:
+                mk.shutdown()  # frees the unpinned plans; the graph's stay
     finally:
         g.close()
     with pytest.raises(mk.MckError, match="instance 1"):
