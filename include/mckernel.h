@@ -308,7 +308,7 @@ mck_status mck_softmax_xent(const float* logits, const int32_t* labels, int64_t 
  * computed); for a non-empty batch W and dlogits must be valid, and phi
  * when dW is requested.  Every sum runs in a fixed order, so results are
  * deterministic.  Partial sums live in scratch allocated on `stream`
- * (stream-ordered): batch C F / 4096 floats for the logits, at most 32 C F
+ * (stream-ordered): batch C F / 8192 floats for the logits, at most 32 C F
  * for dW.  An empty batch gives dW = 0.
  */
 mck_status mck_head_logits(const float* phi, const float* W, const float* b, int64_t batch, int64_t F, int64_t C,

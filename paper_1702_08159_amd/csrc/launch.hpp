@@ -139,6 +139,17 @@ hipError_t launch_softmax_xent(const float* logits, const int32_t* labels, int64
                                float* dlogits, float* loss, float* db, hipStream_t s);
 
 // y += alpha x over count floats.
+// y_k += alpha x_k for up to kAxpySegs arrays in one launch.
+constexpr int kAxpySegs = 8;
+struct AxpySegs {
+    int count;
+    float* y[kAxpySegs];
+    const float* x[kAxpySegs];
+    int64_t n[kAxpySegs];
+    int64_t block0[kAxpySegs];
+};
+hipError_t launch_axpy_multi(float* const* y, const float* const* x, const int64_t* count, int nseg, float alpha,
+                             hipStream_t s);
 hipError_t launch_axpy(float* y, const float* x, int64_t count, float alpha, hipStream_t s);
 // Classifier head products, C in [1, 16] classes, F a multiple of 4, phi,
 // W, dphi 16-byte aligned, C F 4 < 2^31.

@@ -1248,16 +1248,11 @@ mck_status mck_fastfood_train_step(const float* x, const int32_t* labels, int64_
         }
     }
     if (err == hipSuccess && lr != 0.f) {
-        const float a = -lr;
-        err = mck::launch_axpy(W, dW, C * F, a, s);
-        if (err == hipSuccess)
-            err = mck::launch_axpy(b, db, C, a, s);
-        if (err == hipSuccess)
-            err = mck::launch_axpy(B, dB, n * E, a, s);
-        if (err == hipSuccess)
-            err = mck::launch_axpy(G, dG, n * E, a, s);
-        if (err == hipSuccess)
-            err = mck::launch_axpy(S, dS, n * E, a, s);
+        // the SGD update of W, b, B, G, S in one launch
+        float* const ys[5] = {W, b, B, G, S};
+        const float* const xs[5] = {dW, db, dB, dG, dS};
+        const int64_t cnt[5] = {C * F, C, n * E, n * E, n * E};
+        err = mck::launch_axpy_multi(ys, xs, cnt, 5, -lr, s);
     }
     (void)hipFreeAsync(tp.block, s);
     (void)hipFreeAsync(block, s);
