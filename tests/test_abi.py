@@ -136,3 +136,22 @@ def test_python_binding_refuses_cpu_tensors():
         mk.forward(torch.zeros(2, 8), 1)
     with pytest.raises(TypeError):
         mk.fwht_(torch.zeros(2, 8))
+
+
+def test_tuning_and_graph_validation_without_gpu(lib):
+    from paper_1702_08159_amd import _lib
+
+    null = None
+    t = _lib.ForwardTuning(5, 4096)
+    # the tuning table: n must be a power of two in [2, 2^15]; NULL out
+    for n in (0, 1, 3, 1000, 65536):
+        assert _st(lib, "mck_forward_tuning_get", n, ctypes.byref(t)) == 1
+        assert _st(lib, "mck_forward_tuning_set", n, ctypes.byref(t)) == 1
+    assert _st(lib, "mck_forward_tuning_get", 1024, null) == 1
+    # the autotuner: reps outside [1, 1000]
+    assert _st(lib, "mck_autotune_forward_batched", null, 0, 0, null) == 1
+    assert _st(lib, "mck_autotune_forward_batched", null, 0, 1001, null) == 1
+    # the recorded batched call: NULL out, NULL graph; destroying NULL is a no-op
+    assert _st(lib, "mck_batched_graph_create", null, 0, null, null) == 1
+    assert _st(lib, "mck_batched_graph_launch", null, null) == 1
+    lib.mck_batched_graph_destroy(None)
