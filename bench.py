@@ -344,7 +344,7 @@ def main():
                    "autotune_s": tune_s, "tuning": {str(k): list(v) for k, v in sorted(chosen.items())}}
         del maps, outs
         torch.cuda.empty_cache()
-    if args.only in ("bwd", "all"):
+    if args.only in ("bwd", "all") and args.bwd_steps > 0:
         dphi = torch.from_numpy(workloads.grad_features(BATCH, 2 * N * E)).to(dev)
         grads = (torch.empty_like(x),) + tuple(torch.empty((E, N), dtype=torch.float32, device=dev)
                                                 for _ in range(3))

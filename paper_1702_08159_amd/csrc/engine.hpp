@@ -26,6 +26,29 @@ __device__ __forceinline__ void wave_fence()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// The lane index as a value the compiler cannot see through.  LDS
+// instructions reach 64 KiB past their address VGPR; in a row buffer larger
+// than that, every access further out needs an address VGPR of its own, and
+// when those addresses derive from a loop-invariant lane index the compiler
+// hoists them out of the kernel's loop, where they stay live and push the
+// transform into spills.  Passing the transforms this laundered copy makes
+// it compute them where they are used.
+__device__ __forceinline__ uint32_t lane_opaque(uint32_t t)
+{
+    asm volatile("" : "+v"(t));
+    return t;
+}
+
+// t, laundered when the geometry's row buffer exceeds the 64 KiB offset reach
+template <int M, int P>
+__device__ __forceinline__ uint32_t lds_lane(uint32_t t)
+{
+    if constexpr ((int64_t)Geo<M, P>::LDS_FLOATS * 4 > 65536)
+        return lane_opaque(t);
+    else
+        return t;
+}
+
 template <int M, int P>
 __device__ __forceinline__ void lds_sync()
 {

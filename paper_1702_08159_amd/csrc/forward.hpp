@@ -135,17 +135,6 @@ __device__ __forceinline__ void store_features(rsrc_t rY, uint32_t yoff, int e, 
     }
 }
 
-// The lane index as a value the compiler cannot see through: LDS addresses
-// derived from it are then computed where a transform uses them instead of
-// being hoisted out of the expansion loop, where each address past the
-// 64 KiB reach of the instruction offset (rows of 2^14 and more) would hold
-// a VGPR for the whole loop.
-__device__ __forceinline__ uint32_t lane_opaque(uint32_t t)
-{
-    asm volatile("" : "+v"(t));
-    return t;
-}
-
 // The forward with packed parameters (P = 5, generated B).  x stays in
 // VGPRs for the whole chunk; the sign word and the 16-bit gather indices of
 // expansion e+1 are loaded before the stores of e, so that e+1 starts its
@@ -164,8 +153,6 @@ __device__ __forceinline__ void forward_packed(rsrc_t rx, rsrc_t rG, rsrc_t rS, 
     constexpr int EPL = g::EPL, n = g::n, NW = EPL / 2;
     constexpr uint32_t kGoffE = (uint32_t)g::RPB * n;
     const uint32_t sign0 = 4u * (uint32_t)packed_sign_word0<M, P>(E);  // byte offset of the sign words
-    // rows of 2^14 and more span more than the 64 KiB instruction offset
-    constexpr bool kOpaque = (int64_t)g::LDS_FLOATS * 4 > 65536;
     float xh[EPL], gs[EPL], sx[EPL];
     uint32_t bw = 0, op[NW];
     auto load_params = [&](int e) {
@@ -185,18 +172,18 @@ __device__ __forceinline__ void forward_packed(rsrc_t rx, rsrc_t rG, rsrc_t rS, 
         // G' is first needed after the transform, which overlaps the drain
         // of the previous expansion's stores
         bload_lane<M, P, float>(gs, rG, 4u * (uint32_t)e * n, t);
-        fwht_up<M, P>(v, buf, kOpaque ? lane_opaque(t) : t);
+        fwht_up<M, P>(v, buf, lds_lane<M, P>(t));
 #pragma unroll
         for (int r = 0; r < EPL; ++r)
             v[r] *= gs[r];
-        lds_put<M, P, g::GL>(buf, kOpaque ? lane_opaque(t) : t, v);
+        lds_put<M, P, g::GL>(buf, lds_lane<M, P>(t), v);
         lds_sync<M, P>();
 #pragma unroll
         for (int r = 0; r < EPL; ++r)
             v[r] = lds[(op[r >> 1] >> (16 * (r & 1))) & 0xFFFFu];
         lds_sync<M, P>();
         bload_coal<M, P>(sx, rS, 4u * (uint32_t)e * n, t);
-        fwht_down<M, P>(v, buf, kOpaque ? lane_opaque(t) : t);
+        fwht_down<M, P>(v, buf, lds_lane<M, P>(t));
 #pragma unroll
         for (int r = 0; r < EPL; ++r)
             v[r] *= sx[r];
@@ -289,7 +276,7 @@ __device__ __forceinline__ void forward_body(const void* __restrict__ x, uint32_
                 v[r] *= xn[r];
         }
 
-        fwht_up<M, P>(v, buf, t);
+        fwht_up<M, P>(v, buf, lds_lane<M, P>(t));
         // without the pipeline (P = 5: 32 values per lane) the gather offsets
         // are loaded only now, which keeps the transform within 128 VGPRs
         // (loaded with the rest they spilled and cost a quarter of the speed)
@@ -301,7 +288,7 @@ __device__ __forceinline__ void forward_body(const void* __restrict__ x, uint32_
 #pragma unroll
         for (int r = 0; r < EPL; ++r)
             v[r] *= gs[r];
-        lds_put<M, P, g::GL>(buf, t, v);
+        lds_put<M, P, g::GL>(buf, lds_lane<M, P>(t), v);
         lds_sync<M, P>();
 #pragma unroll
         for (int r = 0; r < EPL; ++r)
@@ -310,7 +297,7 @@ __device__ __forceinline__ void forward_body(const void* __restrict__ x, uint32_
         if constexpr (!PIPE)
             bload_coal<M, P>(sx, rS, eo4, t);
 
-        fwht_down<M, P>(v, buf, t);
+        fwht_down<M, P>(v, buf, lds_lane<M, P>(t));
 #pragma unroll
         for (int r = 0; r < EPL; ++r)
             v[r] *= sx[r];

@@ -182,8 +182,8 @@ __global__ void __launch_bounds__(BwdGeo<M>::THREADS)
             }
             uint32_t off[EPL];
             bload_lane<M, P, uint32_t>(off, rO, go4, lane);
-            fwht_up<M, P>(v, buf, t);
-            lds_put<M, P, g::GL>(buf, t, v);
+            fwht_up<M, P>(v, buf, lds_lane<M, P>(t));
+            lds_put<M, P, g::GL>(buf, lds_lane<M, P>(t), v);
             lds_sync<M, P>();
             float w[EPL];
 #pragma unroll
@@ -197,7 +197,7 @@ __global__ void __launch_bounds__(BwdGeo<M>::THREADS)
                 for (int r = 0; r < EPL; ++r)
                     v[r] = w[r] * gk[r];
             }
-            fwht_down<M, P>(v, buf, t);
+            fwht_down<M, P>(v, buf, lds_lane<M, P>(t));
 
             // dz = c (-sin z dphi_cos + cos z dphi_sin); dS += dz v3; g3 = S dz
             {
@@ -222,7 +222,7 @@ __global__ void __launch_bounds__(BwdGeo<M>::THREADS)
                     v[r] *= s32[r];
             }
             // g2 = H g3 (ends in the gather layout); dG += g2 w; Pi^T scatter of G g2
-            fwht_up<M, P>(v, buf, t);
+            fwht_up<M, P>(v, buf, lds_lane<M, P>(t));
             {
                 float gk[EPL];
                 bload_lane<M, P, float>(gk, rG, eo4, t);
@@ -237,10 +237,10 @@ __global__ void __launch_bounds__(BwdGeo<M>::THREADS)
             for (int r = 0; r < EPL; ++r)
                 *reinterpret_cast<float*>(lbytes + off[r]) = v[r];
             lds_sync<M, P>();
-            lds_get<M, P, g::GL>(buf, t, v);
+            lds_get<M, P, g::GL>(buf, lds_lane<M, P>(t), v);
             lds_sync<M, P>();
             // g0 = H g1 (ends in the coalesced layout); dB += g0 xhat; dx += B g0
-            fwht_down<M, P>(v, buf, t);
+            fwht_down<M, P>(v, buf, lds_lane<M, P>(t));
             {
                 float xh[EPL], bb[EPL];
                 bload_row<M, P, VEC>(xh, rx, xoff, d, t, valid);

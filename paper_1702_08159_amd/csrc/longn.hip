@@ -152,7 +152,7 @@ __global__ void __launch_bounds__(RG::BLOCK) k_rows(RowArgs a)
             if (k + 1 < nr)
                 load_input(r + 1);
             __syncthreads();
-            lds_get<M, P, 0>(lds, t, v);
+            lds_get<M, P, 0>(lds, lds_lane<M, P>(t), v);
             __syncthreads();
         } else {
 #pragma unroll
@@ -168,9 +168,9 @@ __global__ void __launch_bounds__(RG::BLOCK) k_rows(RowArgs a)
             for (int j = 0; j < NQ; ++j)
                 bload4u(pk[j], ra, 16u * (j * BLOCK + t), 0u);
         }
-        fwht_up<M, P>(v, lds, t);
+        fwht_up<M, P>(v, lds, lds_lane<M, P>(t));
         if constexpr (OUT == kOutBucket) {
-            lds_put<M, P, RG::GL>(lds, t, v);
+            lds_put<M, P, RG::GL>(lds, lds_lane<M, P>(t), v);
             __syncthreads();
             const rsrc_t ro = make_rsrc(a.dst + r * n, (uint32_t)(n * 4));
 #pragma unroll
@@ -184,7 +184,7 @@ __global__ void __launch_bounds__(RG::BLOCK) k_rows(RowArgs a)
                 }
         } else {
             const rsrc_t ro = make_rsrc(a.dst + r * n + c * CH, (uint32_t)(CH * 4));
-            relayout<M, P, RG::GL, 0>(v, lds, t);
+            relayout<M, P, RG::GL, 0>(v, lds, lds_lane<M, P>(t));
             if constexpr (VEC || IN != kInRow) {
 #pragma unroll
                 for (int j = 0; j < EPL / 4; ++j)
