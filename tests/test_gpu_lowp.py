@@ -50,7 +50,8 @@ def to_f64(torch, t):
 
 
 @pytest.mark.parametrize("name", ["bfloat16", "float16"])
-@pytest.mark.parametrize("d,E,batch", [(784, 4, 37), (13, 2, 9), (1024, 1, 5), (4096, 2, 3)])
+@pytest.mark.parametrize("d,E,batch", [(784, 4, 37), (13, 2, 9), (1024, 1, 5), (4096, 2, 3), (12000, 2, 3),
+                                         (16384, 1, 2), (20000, 2, 3), (32768, 1, 2)])
 def test_phi16_is_rounded_fp32_phi(mk, name, d, E, batch):
     import torch
 
@@ -93,3 +94,20 @@ def test_unsupported_pairs_refused(mk):
         mk.forward(x, 1, 1, 1.0, out_dtype=torch.float32)
     with pytest.raises(mk.MckError):
         mk.forward(x, 1, 1, 1.0, out_dtype=torch.float16)
+
+
+@pytest.mark.parametrize("name", ["bfloat16", "float16"])
+@pytest.mark.parametrize("d", [9000, 16384, 30000])
+def test_phi16_large_rows_match_oracle(mk, orc, name, d):
+    # rows of 2^14 and 2^15 (packed parameters, 32 values per lane) with
+    # 16-bit x and 16-bit phi
+    import torch
+
+    dt = getattr(torch, name)
+    n = mk.padded_dim(d)
+    xt = torch.from_numpy(workloads.normal(3, d, seed=d)).cuda().to(dt)
+    x = xt.float().cpu().numpy()
+    sigma = float(np.sqrt(n))
+    phi = mk.forward(xt, 2, 13, sigma, out_dtype=dt)
+    ref, _, _ = orc.forward(x.astype(np.float64), 2, 13, sigma)
+    assert rowwise_rel(to_f64(torch, phi), ref).max() <= TOL[name]
