@@ -151,6 +151,25 @@ mck_status mck_fastfood_forward_t(const void* x, mck_dtype x_type, int64_t batch
                                   mck_stream stream);
 
 /*
+ * The feature map with per-row power-of-2 scaling of its storage (the 16-bit
+ * forms of the long-vector and reduced-precision configurations), n <=
+ * MCK_MAX_N, storage pairs as in mck_fastfood_forward_t:
+ *   x_exp   (device, batch int8, nullable): row r of the input is the stored
+ *           row times 2^x_exp[r]; the product must be finite in FP32.  The
+ *           scaling is exact, so a 16-bit x can carry rows of any magnitude.
+ *   phi_exp (device, batch int8, nullable, written): row r of phi is the
+ *           stored row times 2^-phi_exp[r].  Every feature is bounded by
+ *           c = 1/sqrt(nE) (equation "mcfeatures" with the normalisation of
+ *           the features), so the exponent is the same for every row: the
+ *           largest j with c 2^j <= 1, which keeps half-precision features
+ *           out of the subnormal range.  Scaling by 2^j is exact: the stored
+ *           value is the round-to-nearest-even of 2^j times the FP32 feature.
+ */
+mck_status mck_fastfood_forward_scaled(const void* x, mck_dtype x_type, const int8_t* x_exp, int64_t batch, int64_t d,
+                                       int64_t E, uint32_t seed, double sigma, mck_calibration calib, void* phi,
+                                       mck_dtype phi_type, int8_t* phi_exp, mck_stream stream);
+
+/*
  * One of several independent feature maps for mck_fastfood_forward_batched:
  * the arguments of mck_fastfood_forward (FP32 x and phi, caller-owned device
  * arrays).

@@ -39,7 +39,7 @@ MAX_N = 32768
 __all__ = ["padded_dim", "fwht", "fwht_", "params", "forward", "project", "backward", "forward_p",
            "backward_p", "fastfood", "FastfoodFunction", "FastfoodExplicit", "gen_boxmuller", "shutdown",
            "MckError", "PAPER_SEED", "MAX_N", "forward_batched", "autotune_batched", "forward_tuning",
-           "set_forward_tuning", "BatchedGraph"]
+           "set_forward_tuning", "BatchedGraph", "forward_scaled"]
 
 
 def _stream(t: torch.Tensor):
@@ -137,6 +137,30 @@ def _forward_t(x, E, seed, sigma, out, out_dtype, matern_t=0):
         _lib.call("mck_fastfood_forward_t", _ptr(x), _DTYPES[x.dtype], batch, d, E, seed & 0xFFFFFFFF,
                   float(sigma), calibration(matern_t), _ptr(out), _DTYPES[out.dtype], _stream(x))
     return out
+
+
+def forward_scaled(x: torch.Tensor, E: int, seed: int = PAPER_SEED, sigma: float = 1.0, x_exp=None,
+                   out_dtype=None, matern_t: int = 0):
+    """phi with per-row power-of-2 scaling of its storage: x (float32,
+    bfloat16 or float16) holds rows x_true[r] / 2^x_exp[r] (x_exp: int8 per
+    row, or None); returns (phi_stored, phi_exp) with phi = phi_stored *
+    2^-phi_exp[r] per row (n <= 2^15)."""
+    if x.dtype not in _DTYPES:
+        raise TypeError("x must be float32, bfloat16 or float16")
+    _check(x, "x", x.dtype)
+    batch, d = _rows(x)
+    n = padded_dim(d)
+    if x_exp is not None:
+        _check(x_exp, "x_exp", torch.int8)
+        if x_exp.shape != (batch,):
+            raise ValueError("x_exp must hold one exponent per row")
+    out = torch.empty((batch, 2 * n * E), dtype=out_dtype or x.dtype, device=x.device)
+    phi_exp = torch.empty((batch,), dtype=torch.int8, device=x.device)
+    with torch.cuda.device(x.device):
+        _lib.call("mck_fastfood_forward_scaled", _ptr(x), _DTYPES[x.dtype], _ptr(x_exp), batch, d, E,
+                  seed & 0xFFFFFFFF, float(sigma), calibration(matern_t), _ptr(out), _DTYPES[out.dtype],
+                  _ptr(phi_exp), _stream(x))
+    return out, phi_exp
 
 
 def _instances(maps, outs):

@@ -33,6 +33,7 @@ SIGNATURES = {
     "mck_fastfood_project": (_int, [_vp, _i64, _i64, _i64, _u32, _f64, _int, _vp, _vp]),
     "mck_fastfood_forward_t": (_int, [_vp, _int, _i64, _i64, _i64, _u32, _f64, _int, _vp, _int, _vp]),
     "mck_fastfood_forward_batched": (_int, [_vp, _i64, _vp]),
+    "mck_fastfood_forward_scaled": (_int, [_vp, _int, _vp, _i64, _i64, _i64, _u32, _f64, _int, _vp, _int, _vp, _vp]),
     "mck_forward_tuning_get": (_int, [_i64, _vp]),
     "mck_forward_tuning_set": (_int, [_i64, _vp]),
     "mck_autotune_forward_batched": (_int, [_vp, _i64, ctypes.c_int32, _vp]),

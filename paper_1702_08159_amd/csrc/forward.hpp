@@ -146,8 +146,8 @@ __device__ __forceinline__ void store_features(rsrc_t rY, uint32_t yoff, int e, 
 template <int M, int P, bool VEC, bool TRIG, int XT, int YT>
 __device__ __forceinline__ void forward_packed(rsrc_t rx, rsrc_t rG, rsrc_t rS, rsrc_t rO, rsrc_t rY, uint32_t xoff,
                                                uint32_t yoff, int d, int E, int e0, int e1, uint32_t t,
-                                               uint32_t lane, bool valid, uint32_t nE, float cs, float* buf,
-                                               const float* lds)
+                                               uint32_t lane, bool valid, uint32_t nE, float cs, float xs,
+                                               float* buf, const float* lds)
 {
     using g = Geo<M, P>;
     constexpr int EPL = g::EPL, n = g::n, NW = EPL / 2;
@@ -163,6 +163,9 @@ __device__ __forceinline__ void forward_packed(rsrc_t rx, rsrc_t rG, rsrc_t rS, 
             bload4u(&op[4 * j], rO, 4u * NW * lane, 2u * (uint32_t)e * kGoffE + 16u * j);
     };
     bload_row_t<M, P, VEC, XT>(xh, rx, xoff, d, t, valid);
+#pragma unroll
+    for (int r = 0; r < EPL; ++r)
+        xh[r] *= xs;
     load_params(e0);
     for (int e = e0; e < e1; ++e) {
         float v[EPL];
@@ -212,7 +215,7 @@ __device__ __forceinline__ void forward_body(const void* __restrict__ x, uint32_
                                              const uint32_t* __restrict__ goff, const float* __restrict__ Gs,
                                              const float* __restrict__ Sx, uint32_t par_bytes, uint32_t goff_bytes,
                                              float cs, void* __restrict__ out, uint32_t out_bytes, int64_t blk,
-                                             float* lds)
+                                             float* lds, const int8_t* __restrict__ xexp = nullptr)
 {
     constexpr uint32_t XB = elem_bytes<XT>(), YB = elem_bytes<YT>();
     using g = Geo<M, P>;
@@ -237,12 +240,14 @@ __device__ __forceinline__ void forward_body(const void* __restrict__ x, uint32_
     const rsrc_t rS = make_rsrc(Sx, par_bytes), rO = make_rsrc(goff, goff_bytes), rY = make_rsrc(out, out_bytes);
     const uint32_t nE = (uint32_t)n * (uint32_t)E;
     const uint32_t xoff = valid ? (uint32_t)(row * d) * XB : 0u;
+    // per-row power-of-2 scale of a scaled x (x = stored x * 2^xexp[row]): exact
+    const float xs = (xexp != nullptr && valid) ? __builtin_ldexpf(1.f, (int)xexp[row]) : 1.f;
     const uint32_t ooff = valid ? (uint32_t)(row * (TRIG ? 2 * (int64_t)nE : (int64_t)nE)) * YB : kOutOfRange;
     const uint32_t yoff = ooff + YB * tpart<M, P, 0>(t);  // this lane's output base
 
     if constexpr (PACK) {
         forward_packed<M, P, VEC, TRIG, XT, YT>(rx, rG, rS, rO, rY, xoff, yoff, d, E, e0, e1, t, lane, valid, nE,
-                                                 cs, buf, lds);
+                                                 cs, xs, buf, lds);
         return;
     }
 
@@ -253,6 +258,9 @@ __device__ __forceinline__ void forward_body(const void* __restrict__ x, uint32_
     uint32_t off[EPL];
     if constexpr (PIPE) {
         bload_row_t<M, P, VEC, XT>(xh, rx, xoff, d, t, valid);
+#pragma unroll
+        for (int r = 0; r < EPL; ++r)
+            xh[r] *= xs;
         bload_coal<M, P>(bn, rB, 4u * (uint32_t)e0 * n, t);
         bload_lane<M, P, float>(gs, rG, 4u * (uint32_t)e0 * n, t);
         bload_lane<M, P, uint32_t>(off, rO, 4u * (uint32_t)e0 * kGoffE, lane);
@@ -273,7 +281,7 @@ __device__ __forceinline__ void forward_body(const void* __restrict__ x, uint32_
             bload_lane<M, P, float>(gs, rG, eo4, t);
 #pragma unroll
             for (int r = 0; r < EPL; ++r)
-                v[r] *= xn[r];
+                v[r] *= xn[r] * xs;
         }
 
         fwht_up<M, P>(v, buf, lds_lane<M, P>(t));
@@ -329,11 +337,11 @@ __global__ void __launch_bounds__((Geo<M, P>::BLOCK), (fwd_min_blocks<M, P>()))
     k_forward(const void* __restrict__ x, uint32_t x_bytes, int64_t batch, int d, int E, int echunk, int nchunks,
               const float* __restrict__ B, const uint32_t* __restrict__ goff, const float* __restrict__ Gs,
               const float* __restrict__ Sx, uint32_t par_bytes, uint32_t goff_bytes, float cs,
-              void* __restrict__ out, uint32_t out_bytes)
+              void* __restrict__ out, uint32_t out_bytes, const int8_t* __restrict__ xexp)
 {
     __shared__ float lds[Geo<M, P>::LDS_FLOATS];
     forward_body<M, P, VEC, TRIG, XT, YT, PACK>(x, x_bytes, batch, d, E, echunk, nchunks, B, goff, Gs, Sx,
-                                                par_bytes, goff_bytes, cs, out, out_bytes, blockIdx.x, lds);
+                                                par_bytes, goff_bytes, cs, out, out_bytes, blockIdx.x, lds, xexp);
 }
 
 // Grouped launch: up to kGroupMax feature maps of the same n (FP32 x and
@@ -383,22 +391,24 @@ struct RunForwardT {
     // P: register bits (a compiled split for this n), waves: grid target,
     // packed: goff is a generated map's (packed form at P = 5; no meaning
     // at P = 4)
+    // xexp: per-row power-of-2 exponents of a scaled x, or null
     static hipError_t run(int P, int waves, bool packed, bool vec, bool trig, const void* x, int64_t batch, int d,
                           int64_t E, const float* B, const uint32_t* goff, const float* Gs, const float* Sx,
-                          float cs, void* out, hipStream_t s)
+                          float cs, void* out, hipStream_t s, const int8_t* xexp)
     {
         if (P == fwd_p(M))
-            return run_p<fwd_p(M)>(waves, packed, vec, trig, x, batch, d, E, B, goff, Gs, Sx, cs, out, s);
+            return run_p<fwd_p(M)>(waves, packed, vec, trig, x, batch, d, E, B, goff, Gs, Sx, cs, out, s, xexp);
         if constexpr (fwd_p_tunable(M))
             if (P == fwd_p_alt(M))
-                return run_p<fwd_p_alt(M)>(waves, packed, vec, trig, x, batch, d, E, B, goff, Gs, Sx, cs, out, s);
+                return run_p<fwd_p_alt(M)>(waves, packed, vec, trig, x, batch, d, E, B, goff, Gs, Sx, cs, out, s,
+                                           xexp);
         return hipErrorInvalidValue;
     }
 
     template <int P>
     static hipError_t run_p(int waves, bool packed, bool vec, bool trig, const void* x, int64_t batch, int d,
                             int64_t E, const float* B, const uint32_t* goff, const float* Gs, const float* Sx,
-                            float cs, void* out, hipStream_t s)
+                            float cs, void* out, hipStream_t s, const int8_t* xexp)
     {
         constexpr bool kPk = (P == 5);
         if (kPk && !packed && !(XT == kF32 && YT == kF32 && trig))
@@ -427,7 +437,8 @@ struct RunForwardT {
             void* os = static_cast<char*>(out) + r0 * out_row * YB;
             const uint32_t xb = (uint32_t)(XB * rows * d), ob = (uint32_t)(YB * rows * out_row);
             const int Ei = (int)E, ec = (int)echunk, nc = (int)nchunks;
-#define MCK_FWD_ARGS xs, xb, rows, d, Ei, ec, nc, B, goff, Gs, Sx, par_bytes, goff_bytes, cs, os, ob
+            const int8_t* xe = xexp ? xexp + r0 : nullptr;
+#define MCK_FWD_ARGS xs, xb, rows, d, Ei, ec, nc, B, goff, Gs, Sx, par_bytes, goff_bytes, cs, os, ob, xe
             if constexpr (XT == kF32 && YT == kF32) {
                 // z (no feature map) only in FP32
                 if (kPk && !packed) {

@@ -13,9 +13,9 @@ namespace mck {
 
 hipError_t launch_forward_t(int M, int P, int waves, bool vec, int xt, int yt, const void* x, int64_t batch, int d,
                             int64_t E, const float* B, const uint32_t* goff, const float* Gs, const float* Sx,
-                            float cs, void* out, hipStream_t s)
+                            float cs, void* out, hipStream_t s, const int8_t* xexp)
 {
-#define MCK_FWDT_ARGS M, P, waves, true, vec, true, x, batch, d, E, B, goff, Gs, Sx, cs, out, s
+#define MCK_FWDT_ARGS M, P, waves, true, vec, true, x, batch, d, E, B, goff, Gs, Sx, cs, out, s, xexp
     if (xt == kF32 && yt == kBF16)
         return dispatch_m<RunForwardT<kF32, kBF16>::Run>(MCK_FWDT_ARGS);
     if (xt == kF32 && yt == kF16)

@@ -7,6 +7,7 @@
 //   k_head_sums     fixed-order sums over rows: the mean loss and db
 //   k_axpy          y += alpha x (the SGD update with alpha = -learning rate)
 //   k_axpy_multi    the same over up to 8 arrays in one launch (W, b, B, G, S)
+//   k_fill_i8       fills an int8 array (the per-row exponents of a scaled phi)
 //   k_head_logits   logits = phi W^T + b for C <= 16 classes: the W rows of a
 //                   column live in VGPRs, phi streams once from HBM
 //   k_head_bwd      dphi = dlogits W and per-row-group partials of
@@ -96,6 +97,15 @@ __global__ void __launch_bounds__(kHeadThreads)
     const int64_t stride = (int64_t)gridDim.x * kHeadThreads;
     for (int64_t i = (int64_t)blockIdx.x * kHeadThreads + threadIdx.x; i < count; i += stride)
         y[i] += alpha * x[i];
+}
+
+// p[i] = value (an exponent array; written by a kernel so that a captured
+// graph holds no memset node)
+__global__ void __launch_bounds__(kHeadThreads) k_fill_i8(int8_t* __restrict__ p, int64_t count, int8_t value)
+{
+    const int64_t stride = (int64_t)gridDim.x * kHeadThreads;
+    for (int64_t i = (int64_t)blockIdx.x * kHeadThreads + threadIdx.x; i < count; i += stride)
+        p[i] = value;
 }
 
 // The same update over several arrays in one launch: segment k owns blocks
@@ -429,6 +439,14 @@ hipError_t launch_axpy_multi(float* const* y, const float* const* x, const int64
         blocks += bk > 1024 ? 1024 : (bk < 1 ? 1 : bk);
     }
     k_axpy_multi<<<dim3((unsigned)blocks), dim3(kHeadThreads), 0, s>>>(segs, alpha);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i8(int8_t* p, int64_t count, int8_t value, hipStream_t s)
+{
+    int64_t blocks = (count + kHeadThreads - 1) / kHeadThreads;
+    blocks = blocks > 4096 ? 4096 : (blocks < 1 ? 1 : blocks);
+    k_fill_i8<<<dim3((unsigned)blocks), dim3(kHeadThreads), 0, s>>>(p, count, value);
     return hipGetLastError();
 }
 

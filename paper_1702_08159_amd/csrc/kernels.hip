@@ -879,10 +879,10 @@ hipError_t launch_fwht(int M, float* data, int64_t batch, bool vec, hipStream_t 
 
 hipError_t launch_forward(int M, int P, int waves, bool packed, bool vec, bool trig, const float* x, int64_t batch,
                           int d, int64_t E, const float* B, const uint32_t* goff, const float* Gs, const float* Sx,
-                          float cs, float* out, hipStream_t s)
+                          float cs, float* out, hipStream_t s, const int8_t* xexp)
 {
     return dispatch_m<RunForwardT<kF32, kF32>::Run>(M, P, waves, packed, vec, trig, x, batch, d, E, B, goff, Gs, Sx,
-                                                    cs, out, s);
+                                                    cs, out, s, xexp);
 }
 
 bool fwd_split_ok(int M, int P)

@@ -51,16 +51,17 @@ hipError_t launch_fwht(int M, float* data, int64_t batch, bool vec, hipStream_t 
 // are split into chunks until the grid holds about `waves` waves.  packed:
 // the arrays belong to a seed plan (derived with Bsign); caller-given
 // diagonals (packed = false) support only the feature map at P = 5.
+// xexp (nullable): per-row power-of-2 exponents of a scaled x, x = stored x * 2^xexp[row].
 hipError_t launch_forward(int M, int P, int waves, bool packed, bool vec, bool trig, const float* x, int64_t batch,
                           int d, int64_t E, const float* B, const uint32_t* goff, const float* Gs, const float* Sx,
-                          float cs, float* out, hipStream_t s);
+                          float cs, float* out, hipStream_t s, const int8_t* xexp = nullptr);
 
 // Forward with 16-bit storage (forward16.hip): xt, yt = 0 (FP32), 1 (bf16),
 // 2 (half); supported pairs (0,1), (0,2), (1,1), (2,2); the feature map of
 // a seed plan only.
 hipError_t launch_forward_t(int M, int P, int waves, bool vec, int xt, int yt, const void* x, int64_t batch, int d,
                             int64_t E, const float* B, const uint32_t* goff, const float* Gs, const float* Sx,
-                            float cs, void* out, hipStream_t s);
+                            float cs, void* out, hipStream_t s, const int8_t* xexp = nullptr);
 
 // n = 2^M > 2^15 (longn.hip): in-place H on 16-byte aligned rows, and the
 // feature map through FP32 scratch rows u, w (batch x n each).  Sh for such
@@ -151,6 +152,7 @@ struct AxpySegs {
 hipError_t launch_axpy_multi(float* const* y, const float* const* x, const int64_t* count, int nseg, float alpha,
                              hipStream_t s);
 hipError_t launch_axpy(float* y, const float* x, int64_t count, float alpha, hipStream_t s);
+hipError_t launch_fill_i8(int8_t* p, int64_t count, int8_t value, hipStream_t s);
 // Classifier head products, C in [1, 16] classes, F a multiple of 4, phi,
 // W, dphi 16-byte aligned, C F 4 < 2^31.
 // part: head_logit_slabs(F) x batch x C floats of scratch.

@@ -746,6 +746,63 @@ mck_status split_maps(const std::vector<MapRef>& maps, hipStream_t s, bool run_l
 
 }  // namespace
 
+mck_status mck_fastfood_forward_scaled(const void* x, mck_dtype x_type, const int8_t* x_exp, int64_t batch, int64_t d,
+                                       int64_t E, uint32_t seed, double sigma, mck_calibration calib, void* phi,
+                                       mck_dtype phi_type, int8_t* phi_exp, mck_stream stream)
+{
+    const int xt = (int)x_type, yt = (int)phi_type;
+    if (xt < 0 || xt > 2 || yt < 0 || yt > 2)
+        return fail(MCK_ERR_INVALID_ARG, "unknown storage type");
+    const bool supported = (xt == 0) || (xt == yt);
+    if (!supported)
+        return fail(MCK_ERR_UNSUPPORTED, "storage pair not supported (use F32 x, or the same 16-bit type)");
+    int64_t n = 0;
+    mck_status st = check_common(batch, d, E, &n);
+    if (st != MCK_OK)
+        return st;
+    if (n > MCK_MAX_N)
+        return fail(MCK_ERR_UNSUPPORTED, "the scaled feature map covers n <= MCK_MAX_N");
+    st = check_sigma(sigma);
+    if (st != MCK_OK)
+        return st;
+    {
+        int mt = 0;
+        st = check_calib((int)calib, n, &mt);
+        if (st != MCK_OK)
+            return st;
+    }
+    if (batch > 0 && (x == nullptr || phi == nullptr))
+        return fail(MCK_ERR_INVALID_ARG, "x or phi is NULL");
+    if (batch == 0)
+        return MCK_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Plan* p = nullptr;
+    st = get_plan(seed, n, E, sigma, calib, s, &p);
+    if (st != MCK_OK)
+        return st;
+    // |phi| <= c = 1/sqrt(nE): scale by 2^j, the largest power of two with
+    // c 2^j <= 1 (4^j <= nE), folded exactly into the feature scale
+    int j = 0;
+    while ((int64_t(1) << (2 * (j + 1))) <= n * E)
+        ++j;
+    const float cs = std::ldexp(feature_scale(n, E), j);
+    const FwdTune t = current_tuning(log2i(n));
+    const FwdArrays a = fwd_arrays(p, t.P);
+    const uintptr_t xa = 4u * (xt == 0 ? 4u : 2u), ya = 4u * (yt == 0 ? 4u : 2u);
+    const bool vec = (reinterpret_cast<uintptr_t>(x) % xa == 0) && (reinterpret_cast<uintptr_t>(phi) % ya == 0) &&
+                     d % 4 == 0 && n >= 4;
+    hipError_t err;
+    if (xt == 0 && yt == 0)
+        err = mck::launch_forward(log2i(n), t.P, t.waves, true, vec, true, static_cast<const float*>(x), batch,
+                                  (int)d, E, p->B, a.goff, a.Gs, p->Sh, cs, static_cast<float*>(phi), s, x_exp);
+    else
+        err = mck::launch_forward_t(log2i(n), t.P, t.waves, vec, xt, yt, x, batch, (int)d, E, p->B, a.goff, a.Gs,
+                                    p->Sh, cs, phi, s, x_exp);
+    if (err == hipSuccess && phi_exp != nullptr)
+        err = mck::launch_fill_i8(phi_exp, batch, (int8_t)j, s);
+    return err == hipSuccess ? MCK_OK : hip_fail(err, "scaled forward launch");
+}
+
 mck_status mck_fastfood_forward_batched(const mck_instance* inst, int64_t count, mck_stream stream)
 {
     hipStream_t s = static_cast<hipStream_t>(stream);

@@ -155,3 +155,15 @@ def test_tuning_and_graph_validation_without_gpu(lib):
     assert _st(lib, "mck_batched_graph_create", null, 0, null, null) == 1
     assert _st(lib, "mck_batched_graph_launch", null, null) == 1
     lib.mck_batched_graph_destroy(None)
+
+
+def test_scaled_forward_validation_without_gpu(lib):
+    null = None
+    sc = "mck_fastfood_forward_scaled"
+    p16 = ctypes.c_void_p(16)
+    # unknown storage type, unsupported pair, n too large, NULL x; empty batch is a no-op
+    assert _st(lib, sc, p16, 3, null, 2, 8, 1, 1, 1.0, 0, p16, 0, null, null) == 1
+    assert _st(lib, sc, p16, 1, null, 2, 8, 1, 1, 1.0, 0, p16, 2, null, null) == 2
+    assert _st(lib, sc, p16, 0, null, 2, 40000, 1, 1, 1.0, 0, p16, 0, null, null) == 2
+    assert _st(lib, sc, null, 0, null, 2, 8, 1, 1, 1.0, 0, p16, 0, null, null) == 1
+    assert _st(lib, sc, null, 0, null, 0, 8, 1, 1, 1.0, 0, null, 0, null, null) == 0

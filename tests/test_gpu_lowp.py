@@ -111,3 +111,73 @@ def test_phi16_large_rows_match_oracle(mk, orc, name, d):
     phi = mk.forward(xt, 2, 13, sigma, out_dtype=dt)
     ref, _, _ = orc.forward(x.astype(np.float64), 2, 13, sigma)
     assert rowwise_rel(to_f64(torch, phi), ref).max() <= TOL[name]
+
+
+@pytest.mark.parametrize("name", ["bfloat16", "float16"])
+@pytest.mark.parametrize("d,E", [(784, 16), (13, 2), (5000, 4), (30000, 2)])
+def test_scaled_storage_matches_oracle(mk, orc, name, d, E):
+    # per-row power-of-2 scaling: x rows of very different magnitude carried
+    # in 16 bits with their exponents, phi stored times 2^phi_exp
+    import torch
+
+    dt = getattr(torch, name)
+    batch = 6
+    n = mk.padded_dim(d)
+    sigma = float(np.sqrt(n))
+    base = workloads.normal(batch, d, seed=d + 1)
+    k = np.array([-3, 0, 2, -1, 1, 0][:batch], np.int8)
+    x16 = torch.from_numpy(base).cuda().to(dt)
+    phi, pexp = mk.forward_scaled(x16, E, 9, sigma, x_exp=torch.from_numpy(k).cuda(), out_dtype=dt)
+    j = int(pexp[0].item())
+    assert torch.equal(pexp, torch.full((batch,), j, dtype=torch.int8, device="cuda"))
+    assert 1.0 / np.sqrt(n * E) * 2.0 ** j <= 1.0 < 1.0 / np.sqrt(n * E) * 2.0 ** (j + 1)
+    x_true = x16.float().cpu().numpy().astype(np.float64) * (2.0 ** k.astype(np.float64))[:, None]
+    ref, _, _ = orc.forward(x_true, E, 9, sigma)
+    got = to_f64(torch, phi) * 2.0 ** (-j)
+    assert rowwise_rel(got, ref).max() <= TOL[name]
+
+
+@pytest.mark.parametrize("name", ["bfloat16", "float16"])
+def test_scaled_phi_is_rounded_scaled_fp32_phi(mk, name):
+    import torch
+
+    dt = getattr(torch, name)
+    x = torch.from_numpy(workloads.normal(7, 1000, seed=4)).cuda()
+    E, sigma = 8, 32.0
+    phi32 = mk.forward(x, E, 3, sigma).cpu().numpy()
+    phi16, pexp = mk.forward_scaled(x, E, 3, sigma, out_dtype=dt)
+    j = int(pexp[0].item())
+    scaled = (phi32.astype(np.float64) * 2.0 ** j).astype(np.float32)  # exact: a power of two
+    if name == "float16":
+        assert np.array_equal(phi16.cpu().numpy().view(np.uint16), scaled.astype(np.float16).view(np.uint16))
+    else:
+        assert np.array_equal(phi16.cpu().view(torch.int16).numpy().view(np.uint16), bf16_rne(scaled))
+    # FP32 storage: exactly 2^j times the plain map
+    phif, _ = mk.forward_scaled(x, E, 3, sigma)
+    assert np.array_equal(phif.cpu().numpy(), scaled)
+
+
+def test_scaled_half_beats_plain_half_when_features_are_small(mk, orc):
+    # n = 8192, E = 16: c = 2^-8.5, so plain half phi has many subnormal
+    # features; the scaled form keeps them normal
+    import torch
+
+    x = torch.from_numpy(workloads.normal(4, 8192, seed=8)).cuda()
+    sigma = float(np.sqrt(8192))
+    ref, _, _ = orc.forward(x.cpu().numpy().astype(np.float64), 16, 21, sigma)
+    plain = to_f64(torch, mk.forward(x, 16, 21, sigma, out_dtype=torch.float16))
+    sc, pexp = mk.forward_scaled(x, 16, 21, sigma, out_dtype=torch.float16)
+    scaled = to_f64(torch, sc) * 2.0 ** (-int(pexp[0].item()))
+    e_plain, e_scaled = rowwise_rel(plain, ref).max(), rowwise_rel(scaled, ref).max()
+    assert e_scaled <= e_plain and e_scaled <= TOL["float16"]
+
+
+def test_scaled_refusals(mk):
+    import torch
+
+    x = torch.zeros((2, 40000), device="cuda")
+    with pytest.raises(mk.MckError, match="UNSUPPORTED"):
+        mk.forward_scaled(x, 1, 1, 1.0)
+    xb = torch.zeros((2, 8), device="cuda", dtype=torch.bfloat16)
+    with pytest.raises(mk.MckError, match="UNSUPPORTED"):
+        mk.forward_scaled(xb, 1, 1, 1.0, out_dtype=torch.float16)
