@@ -212,7 +212,27 @@ def main():
                 longv[name]["sample"] = out[:3].float().cpu().numpy()
             log("long vectors (n=2^20, E=4), phi %s: %.3f ms/step" % (name, ms))
             del out
-        for name in ("bf16", "f16"):
+        # the same with per-row power-of-2 scaling of the stored phi
+        for name, dt in (("bf16_scaled", torch.bfloat16), ("f16_scaled", torch.float16)):
+            res_ = {}
+
+            def lfs():
+                res_["phi"], res_["exp"] = mk.forward_scaled(xl, LONG_E, seed, LONG_SIGMA, out_dtype=dt)
+
+            lfs()
+            torch.cuda.synchronize()
+            t0.record(stream)
+            for _ in range(args.long_steps):
+                lfs()
+            t1.record(stream)
+            torch.cuda.synchronize()
+            ms = t0.elapsed_time(t1) / args.long_steps
+            j = int(res_["exp"][0].item())
+            longv[name] = {"ms_per_step": ms, "vectors_per_s": LONG_BATCH / (ms * 1e-3), "phi_exp": j,
+                           "sample": res_["phi"][:3].float().cpu().numpy() * 2.0 ** (-j)}
+            log("long vectors (n=2^20, E=4), phi %s: %.3f ms/step" % (name, ms))
+            del res_
+        for name in ("bf16", "f16", "bf16_scaled", "f16_scaled"):
             longv[name]["speedup_vs_f32"] = longv["f32"]["ms_per_step"] / longv[name]["ms_per_step"]
         xl_head = xl[:3].cpu().numpy()
         del xl
@@ -437,7 +457,7 @@ def main():
                 (np.linalg.norm(ph - ref, axis=1) / np.linalg.norm(ref, axis=1)).max())
         if longv:
             refl, _, _ = oracle.forward(xl_head.astype(np.float64), LONG_E, seed, LONG_SIGMA)
-            for name in ("bf16", "f16"):
+            for name in ("bf16", "f16", "bf16_scaled", "f16_scaled"):
                 ph = longv[name]["sample"].astype(np.float64)
                 longv[name]["max_row_rel_err_vs_oracle"] = float(
                     (np.linalg.norm(ph - refl, axis=1) / np.linalg.norm(refl, axis=1)).max())

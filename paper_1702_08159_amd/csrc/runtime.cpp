@@ -513,7 +513,7 @@ static int64_t long_rows_per(int64_t batch, int64_t n)
 // Launches of the long-vector feature map with caller-provided scratch u
 // (2 x long_rows_per(batch, n) x n floats).
 static mck_status forward_long_launch(const Plan* p, const void* x, int xt, int64_t batch, int64_t d, int64_t n,
-                                      int64_t E, void* phi, int yt, float* u, hipStream_t s)
+                                      int64_t E, void* phi, int yt, float* u, hipStream_t s, float cs)
 {
     const int64_t xb = xt == 0 ? 4 : 2, yb = yt == 0 ? 4 : 2;
     const int64_t row_phi = 2 * n * E * yb;
@@ -521,7 +521,6 @@ static mck_status forward_long_launch(const Plan* p, const void* x, int xt, int6
     float* w = u + rows_per * n;
     const uintptr_t xa = (uintptr_t)(4 * xb);
     const bool vec = reinterpret_cast<uintptr_t>(x) % xa == 0 && d % 4 == 0;
-    const float cs = feature_scale(n, E);
     hipError_t err = hipSuccess;
     for (int64_t r0 = 0; r0 < batch && err == hipSuccess; r0 += rows_per) {
         const int64_t rows = batch - r0 < rows_per ? batch - r0 : rows_per;
@@ -537,7 +536,7 @@ static mck_status forward_long_launch(const Plan* p, const void* x, int xt, int6
 // in equal chunks of at most 2^27 floats per FP32 scratch buffer (u, w,
 // stream-ordered).
 static mck_status forward_long(const Plan* p, const void* x, int xt, int64_t batch, int64_t d, int64_t n, int64_t E,
-                               void* phi, int yt, hipStream_t s)
+                               void* phi, int yt, hipStream_t s, float cs)
 {
     const int64_t yb = yt == 0 ? 4 : 2;
     if (2 * n * E * yb > (int64_t(1) << 31) - 4096)
@@ -549,7 +548,7 @@ static mck_status forward_long(const Plan* p, const void* x, int xt, int64_t bat
     hipError_t err = hipMallocAsync(reinterpret_cast<void**>(&u), (size_t)(2 * rows_per * n) * sizeof(float), s);
     if (err != hipSuccess)
         return fail(MCK_ERR_NO_MEMORY, std::string("long-vector scratch: ") + hipGetErrorString(err));
-    const mck_status st = forward_long_launch(p, x, xt, batch, d, n, E, phi, yt, u, s);
+    const mck_status st = forward_long_launch(p, x, xt, batch, d, n, E, phi, yt, u, s, cs);
     (void)hipFreeAsync(u, s);
     return st;
 }
@@ -582,7 +581,7 @@ static mck_status forward_common(const float* x, int64_t batch, int64_t d, int64
     if (st != MCK_OK)
         return st;
     if (n > MCK_MAX_N)
-        return forward_long(p, x, 0, batch, d, n, E, out, 0, s);
+        return forward_long(p, x, 0, batch, d, n, E, out, 0, s, feature_scale(n, E));
     const FwdTune t = current_tuning(log2i(n));
     const FwdArrays a = fwd_arrays(p, t.P);
     const hipError_t err = mck::launch_forward(log2i(n), t.P, t.waves, true, vec_ok(x, out, d, n), trig, x, batch,
@@ -633,7 +632,7 @@ mck_status mck_fastfood_forward_t(const void* x, mck_dtype x_type, int64_t batch
     if (st != MCK_OK)
         return st;
     if (n > MCK_MAX_N)
-        return forward_long(p, x, xt, batch, d, n, E, phi, yt, s);
+        return forward_long(p, x, xt, batch, d, n, E, phi, yt, s, feature_scale(n, E));
     // vector path: 4 elements per access, so 4-element alignment of both arrays
     const uintptr_t xa = 4u * (xt == 0 ? 4u : 2u), ya = 4u * (yt == 0 ? 4u : 2u);
     const bool vec = (reinterpret_cast<uintptr_t>(x) % xa == 0) && (reinterpret_cast<uintptr_t>(phi) % ya == 0) &&
@@ -736,7 +735,8 @@ mck_status split_maps(const std::vector<MapRef>& maps, hipStream_t s, bool run_l
         if (m.n <= MCK_MAX_N) {
             (*by_m)[log2i(m.n)].push_back(m);
         } else if (run_long) {
-            const mck_status st = forward_long(m.p, m.q->x, 0, m.q->batch, m.q->d, m.n, m.q->E, m.q->phi, 0, s);
+            const mck_status st = forward_long(m.p, m.q->x, 0, m.q->batch, m.q->d, m.n, m.q->E, m.q->phi, 0, s,
+                                               feature_scale(m.n, m.q->E));
             if (st != MCK_OK)
                 return st;
         }
@@ -760,8 +760,8 @@ mck_status mck_fastfood_forward_scaled(const void* x, mck_dtype x_type, const in
     mck_status st = check_common(batch, d, E, &n);
     if (st != MCK_OK)
         return st;
-    if (n > MCK_MAX_N)
-        return fail(MCK_ERR_UNSUPPORTED, "the scaled feature map covers n <= MCK_MAX_N");
+    if (n > MCK_MAX_N && x_exp != nullptr)
+        return fail(MCK_ERR_UNSUPPORTED, "per-row x exponents are supported for n <= MCK_MAX_N");
     st = check_sigma(sigma);
     if (st != MCK_OK)
         return st;
@@ -786,6 +786,15 @@ mck_status mck_fastfood_forward_scaled(const void* x, mck_dtype x_type, const in
     while ((int64_t(1) << (2 * (j + 1))) <= n * E)
         ++j;
     const float cs = std::ldexp(feature_scale(n, E), j);
+    if (n > MCK_MAX_N) {
+        st = forward_long(p, x, xt, batch, d, n, E, phi, yt, s, cs);
+        if (st == MCK_OK && phi_exp != nullptr) {
+            const hipError_t ferr = mck::launch_fill_i8(phi_exp, batch, (int8_t)j, s);
+            if (ferr != hipSuccess)
+                return hip_fail(ferr, "exponent fill");
+        }
+        return st;
+    }
     const FwdTune t = current_tuning(log2i(n));
     const FwdArrays a = fwd_arrays(p, t.P);
     const uintptr_t xa = 4u * (xt == 0 ? 4u : 2u), ya = 4u * (yt == 0 ? 4u : 2u);
@@ -997,7 +1006,7 @@ mck_status record_maps(mck_batched_graph* g, hipStream_t cs)
             by_m[log2i(m.n)].push_back(m);
         } else {
             const mck_status st = forward_long_launch(m.p, m.q->x, 0, m.q->batch, m.q->d, m.n, m.q->E, m.q->phi, 0,
-                                                      static_cast<float*>(g->scratch), cs);
+                                                      static_cast<float*>(g->scratch), cs, feature_scale(m.n, m.q->E));
             if (st != MCK_OK)
                 return st;
         }

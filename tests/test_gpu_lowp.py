@@ -172,12 +172,28 @@ def test_scaled_half_beats_plain_half_when_features_are_small(mk, orc):
     assert e_scaled <= e_plain and e_scaled <= TOL["float16"]
 
 
+def test_scaled_long_rows(mk, orc):
+    # n = 2^16 (the multi-pass path): phi scaled by 2^j, bit for bit the
+    # rounding of 2^j times the FP32 map, and within the half bound
+    import torch
+
+    x = torch.from_numpy(workloads.normal(3, 40000, seed=5)).cuda()
+    sigma = 256.0
+    phi32 = mk.forward(x, 2, 17, sigma).cpu().numpy()
+    sc, pexp = mk.forward_scaled(x, 2, 17, sigma, out_dtype=torch.float16)
+    j = int(pexp[0].item())
+    scaled = (phi32.astype(np.float64) * 2.0 ** j).astype(np.float32)
+    assert np.array_equal(sc.cpu().numpy().view(np.uint16), scaled.astype(np.float16).view(np.uint16))
+    ref, _, _ = orc.forward(x.cpu().numpy().astype(np.float64), 2, 17, sigma)
+    assert rowwise_rel(to_f64(torch, sc) * 2.0 ** (-j), ref).max() <= TOL["float16"]
+
+
 def test_scaled_refusals(mk):
     import torch
 
     x = torch.zeros((2, 40000), device="cuda")
     with pytest.raises(mk.MckError, match="UNSUPPORTED"):
-        mk.forward_scaled(x, 1, 1, 1.0)
+        mk.forward_scaled(x, 1, 1, 1.0, x_exp=torch.zeros((2,), dtype=torch.int8, device="cuda"))
     xb = torch.zeros((2, 8), device="cuda", dtype=torch.bfloat16)
     with pytest.raises(mk.MckError, match="UNSUPPORTED"):
         mk.forward_scaled(xb, 1, 1, 1.0, out_dtype=torch.float16)
