@@ -194,7 +194,10 @@ typedef struct mck_instance {
  * GPU together); longer maps run through the row and column passes.  `inst`
  * is a host array.  Every instance is validated before anything is enqueued;
  * the error message names the first bad instance.  Plans are built (and
- * kept from eviction) for the duration of the call.
+ * kept from eviction) for the duration of the call.  Each n launches with
+ * the current entry of the forward tuning table (below); once the plans are
+ * cached, a call with no map longer than MCK_MAX_N neither allocates nor
+ * synchronizes, so it can be captured into a graph.
  */
 mck_status mck_fastfood_forward_batched(const mck_instance* inst, int64_t count, mck_stream stream);
 
