@@ -8,10 +8,12 @@ A step is one forward pass x -> phi over the whole batch (one kernel launch).
 Forward steps are replayed from a HIP graph that holds GRAPH_STEPS launches,
 so host launch gaps do not count; the fwd+bwd figure adds the adjoint (dx
 and the batch-summed dB, dG, dS), launched eagerly.  Inputs are resident in
-HBM before timing.  The defaults warm up for about 100 steps first: the
-card's power management lowers clocks a few milliseconds into a sustained
-run and settles after about 20 ms, and the steady state is what is reported.
-Prints one JSON line.
+HBM before timing.  Every timed leg is preceded by an untimed, time-based
+pre-heat (at least PREHEAT_MS of back-to-back launches of the same work,
+reported as `preheat_ms`) and then the counted warm-up steps: the card's
+power management lowers clocks a few milliseconds into a sustained run and
+settles after about 20 ms, and the steady state is what is reported.  No
+work is skipped inside a timed region.  Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--cpu-seconds S]
 """
@@ -38,6 +40,9 @@ TRAIN_BATCH, TRAIN_CLASSES = 1024, 10
 LONG_BATCH, LONG_N, LONG_E = 64, 1 << 20, 4
 LONG_SIGMA = float(LONG_N) ** 0.5
 METRIC = "Fastfood vectors/s + %HBM peak at n=1024 E=16, fwd and fwd+bwd vs oracle error"
+PREHEAT_MS = 500.0          # before the forward leg
+PREHEAT_LEG_MS = 200.0      # before each other leg
+FWHT_ROWS = 1 << 18         # mck_fwht sanity leg: 2^18 rows of n = 1024 (1 GiB, in place)
 
 # HBM bytes per forward launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of
 # this workload, scaled by what the same counters read for a 1 GiB device
@@ -58,6 +63,42 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+def preheat(fn, ms, sync):
+    """Untimed back-to-back calls of fn for at least `ms` of wall time; returns
+    the wall time spent (ms).  Calls are enqueued in rounds of 8 so that the
+    GPU never idles for long between them."""
+    t = time.perf_counter()
+    while (time.perf_counter() - t) * 1e3 < ms:
+        for _ in range(8):
+            fn()
+        sync()
+    return (time.perf_counter() - t) * 1e3
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads() -> int:
+    """Worker threads for the all-core oracle leg: the CPUs this process may
+    run on, capped by OMP_NUM_THREADS when it is set."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        avail = min(avail, int(env))
+    return max(1, avail)
+
+
 def kernel_hash() -> str:
     h = hashlib.sha1()
     for rel in KERNEL_SOURCES:
@@ -76,6 +117,11 @@ def main():
     ap.add_argument("--lowp-steps", type=int, default=100)
     ap.add_argument("--long-steps", type=int, default=5)
     ap.add_argument("--batched-steps", type=int, default=3)
+    ap.add_argument("--fwht-steps", type=int, default=50)
+    ap.add_argument("--preheat-ms", type=float, default=PREHEAT_MS,
+                    help="untimed launches before the forward's counted warm-up (wall ms)")
+    ap.add_argument("--preheat-leg-ms", type=float, default=PREHEAT_LEG_MS,
+                    help="untimed launches before every other leg's warm-up (wall ms)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["fwd", "bwd", "train", "all"], default="all",
@@ -145,9 +191,13 @@ def main():
         del a, b
 
     fwd_ms = bwd_ms = float("nan")
+    bwd_check = bwd_shape = None
+    preheat_ms = {}
+    sync = torch.cuda.synchronize
     if args.only in ("fwd", "all"):
         gblock = capture(GRAPH_STEPS)
         one = capture(1)
+        preheat_ms["fwd"] = preheat(gblock.replay, args.preheat_ms, sync)
         run_steps(gblock.replay, one.replay, args.warmup)
         torch.cuda.synchronize()
         t0.record(stream)
@@ -156,6 +206,36 @@ def main():
         torch.cuda.synchronize()
         fwd_ms = t0.elapsed_time(t1) / args.steps
         log("forward %.4f ms/step over %d steps" % (fwd_ms, args.steps))
+    fwht_leg = None
+    if args.only in ("fwd", "all") and args.fwht_steps > 0:
+        # mck_fwht alone, in place on 2^18 rows of n = 1024 (1 GiB): reads and
+        # writes each row once, 8n bytes per row, a pure bandwidth sanity figure
+        buf = torch.randn((FWHT_ROWS, N), device=dev)
+        mk.fwht_(buf)
+        gf = torch.cuda.CUDAGraph()
+        sf = torch.cuda.Stream(dev)
+        sf.wait_stream(stream)
+        with torch.cuda.stream(sf):
+            mk.fwht_(buf)
+        stream.wait_stream(sf)
+        with torch.cuda.graph(gf):
+            for _ in range(GRAPH_STEPS):
+                mk.fwht_(buf)
+        torch.cuda.synchronize()
+        preheat_ms["fwht"] = preheat(gf.replay, args.preheat_leg_ms, sync)
+        reps = max(1, args.fwht_steps // GRAPH_STEPS)
+        t0.record(stream)
+        for _ in range(reps):
+            gf.replay()
+        t1.record(stream)
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / (reps * GRAPH_STEPS)
+        fb = 8 * N * FWHT_ROWS
+        fwht_leg = {"rows": FWHT_ROWS, "n": N, "ms_per_launch": ms, "bytes_per_row": 8 * N,
+                    "achieved_GBs": fb / (ms * 1e-3) / 1e9, "hbm_frac": fb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        log("fwht 2^18 x 1024 in place: %.4f ms per launch, %.0f GB/s" % (ms, fwht_leg["achieved_GBs"]))
+        del buf, gf
+        torch.cuda.empty_cache()
     lowp = {}
     if args.only in ("fwd", "all") and args.lowp_steps > 0:
         # the same forward with phi stored in 16 bits (FP32 arithmetic)
@@ -172,6 +252,7 @@ def main():
                 for _ in range(GRAPH_STEPS):
                     mk.forward(x, E, seed, SIGMA, out=phi16)
             torch.cuda.synchronize()
+            preheat_ms["fwd_" + name] = preheat(g16.replay, args.preheat_leg_ms, sync)
             for _ in range(max(1, args.warmup // GRAPH_STEPS)):
                 g16.replay()
             torch.cuda.synchronize()
@@ -372,6 +453,7 @@ def main():
         def bwd():
             mk.backward(x, dphi, E, seed, SIGMA, out=grads)
 
+        preheat_ms["bwd"] = preheat(bwd, args.preheat_leg_ms, sync)
         for _ in range(max(1, args.warmup // 10)):
             bwd()
         torch.cuda.synchronize()
@@ -382,6 +464,15 @@ def main():
         torch.cuda.synchronize()
         bwd_ms = t0.elapsed_time(t1) / args.bwd_steps
         log("backward %.4f ms/step over %d steps" % (bwd_ms, args.bwd_steps))
+        bwd_shape = mk.backward_launch_shape(BATCH, D, E)
+        # rows checked against the oracle: first and last row of every pass
+        # of the first and the last row block, and a few others
+        R, P, NB = bwd_shape["rows_per_pass"], bwd_shape["passes"], bwd_shape["rowblocks"]
+        bwd_rows = sorted({r for b in (0, NB - 1) for p_ in range(P) for r in ((b * P + p_) * R,
+                                                                              (b * P + p_) * R + R - 1)}
+                          | {1234, 4321, BATCH - 1})
+        bwd_rows = [r for r in bwd_rows if r < BATCH]
+        bwd_check = (x_np[bwd_rows], dphi[bwd_rows].cpu().numpy(), grads[0][bwd_rows].cpu().numpy())
         del dphi
 
     train_ms = float("nan")
@@ -400,6 +491,7 @@ def main():
         def step():
             mk.train_step(xt, labels, W, bias, B, perm, G, S, lr=0.001)
 
+        preheat_ms["train"] = preheat(step, args.preheat_leg_ms, sync)
         for _ in range(3):
             step()
         torch.cuda.synchronize()
@@ -425,42 +517,72 @@ def main():
         traffic = int(round((fk * FETCH_SCALE + wk * WRITE_SCALE) * 1024))
 
     cpu = None
-    err = None
-    if not args.no_cpu_baseline and args.only != "bwd":
+    err = err_elem = bwd_err = None
+    if not args.no_cpu_baseline:
+        import concurrent.futures as cf
+
         import oracle
 
         oracle.build(force=False)
-        phi_host = phi.cpu().numpy()
         p = oracle.params(seed, N, E, SIGMA)
         xs = x_np.astype(np.float64)
+    if not args.no_cpu_baseline and args.only != "bwd":
+        phi_host = phi.cpu().numpy()
+        # one thread: a bounded prefix of the batch (about --cpu-seconds of work)
         t = time.perf_counter()
         oracle.forward(xs[:64], E, seed, SIGMA, p=p)
         per_row = (time.perf_counter() - t) / 64
-        rows = int(min(BATCH, max(64, args.cpu_seconds / per_row)))
-        worst = 0.0
+        rows1 = int(min(BATCH, max(64, args.cpu_seconds / per_row)))
         t = time.perf_counter()
-        for r0 in range(0, rows, 512):
-            r1 = min(rows, r0 + 512)
-            ref, _, _ = oracle.forward(xs[r0:r1], E, seed, SIGMA, p=p)
-            dif = np.linalg.norm(phi_host[r0:r1].astype(np.float64) - ref, axis=1) / np.linalg.norm(ref, axis=1)
-            worst = max(worst, float(dif.max()))
-        cpu_s = time.perf_counter() - t
-        log("oracle: %d rows in %.1f s" % (rows, cpu_s))
-        cpu = {"value": rows / cpu_s, "unit": "vectors/s", "cores": 1, "kind": "oracle",
-               "sample": "first %d of the %d rows, forward, FP64 C oracle, one thread" % (rows, BATCH)}
-        err = worst
+        for r0 in range(0, rows1, 512):
+            oracle.forward(xs[r0:min(rows1, r0 + 512)], E, seed, SIGMA, p=p)
+        one_s = time.perf_counter() - t
+        # all host cores: the whole batch in chunks of 64 rows on a thread pool
+        # (the oracle's C calls release the interpreter lock; the per-row
+        # arithmetic is the same)
+        threads = host_threads()
+        ref_all = np.empty((BATCH, 2 * N * E), np.float64)
+
+        def chunk(r0):
+            r1 = min(BATCH, r0 + 64)
+            ref_all[r0:r1] = oracle.forward(xs[r0:r1], E, seed, SIGMA, p=p)[0]
+
+        t = time.perf_counter()
+        with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+            list(ex.map(chunk, range(0, BATCH, 64)))
+        all_s = time.perf_counter() - t
+        log("oracle: %d rows in %.1f s on one thread; %d rows in %.2f s on %d threads"
+            % (rows1, one_s, BATCH, all_s, threads))
+        dif = phi_host.astype(np.float64) - ref_all
+        err = float((np.linalg.norm(dif, axis=1) / np.linalg.norm(ref_all, axis=1)).max())
+        err_elem = float(np.abs(dif).max() * math.sqrt(N * E))
+        del dif
+        cpu = {"value": BATCH / all_s, "unit": "vectors/s", "cores": threads, "kind": "oracle",
+               "sample": "all %d rows of the metric batch, forward, FP64 C oracle on %d threads "
+                         "(chunks of 64 rows)" % (BATCH, threads),
+               "single_thread_value": rows1 / one_s,
+               "single_thread_sample": "first %d rows, one thread" % rows1,
+               "host_cpus": os.cpu_count(), "cpu_model": cpu_model()}
         # 16-bit storage: error of the stored phi against the oracle, first 256 rows
-        ref, _, _ = oracle.forward(xs[:256], E, seed, SIGMA, p=p)
+        ref = ref_all[:256]
         for name, rec in lowp.items():
             ph = rec["phi"][:256].float().cpu().numpy().astype(np.float64)
             rec["max_row_rel_err_vs_oracle"] = float(
                 (np.linalg.norm(ph - ref, axis=1) / np.linalg.norm(ref, axis=1)).max())
+        del ref_all, ref
         if longv:
             refl, _, _ = oracle.forward(xl_head.astype(np.float64), LONG_E, seed, LONG_SIGMA)
             for name in ("bf16", "f16", "bf16_scaled", "f16_scaled"):
                 ph = longv[name]["sample"].astype(np.float64)
                 longv[name]["max_row_rel_err_vs_oracle"] = float(
                     (np.linalg.norm(ph - refl, axis=1) / np.linalg.norm(refl, axis=1)).max())
+    if not args.no_cpu_baseline and bwd_check is not None:
+        bx, bd, bdx = bwd_check
+        rdx = oracle.backward(bx.astype(np.float64), bd.astype(np.float64), N, E, p["B"], p["perm"], p["G"],
+                              p["S64"])[0]
+        bwd_err = float((np.linalg.norm(bdx - rdx, axis=1) / np.linalg.norm(rdx, axis=1)).max())
+        log("backward dx on %d rows (pass boundaries of the first and last block): max row error %.2e"
+            % (len(bx), bwd_err))
     for rec in longv.values():
         rec.pop("sample", None)
     for rec in lowp.values():
@@ -498,6 +620,11 @@ def main():
         "train_config": {"batch": TRAIN_BATCH, "classes": TRAIN_CLASSES, "d": D, "n": N, "E": E, "sigma": 1.0,
                          "lr": 0.001, "learnable": "W, b, B, G, S"},
         "max_row_rel_err_vs_oracle": err,
+        "max_abs_err_times_sqrt_nE": err_elem,
+        "bwd_max_row_rel_err_vs_oracle": bwd_err,
+        "bwd_launch_shape": bwd_shape,
+        "fwht_sanity": fwht_leg,
+        "preheat_ms": preheat_ms,
         "roofline": {"bound": "hbm", "achieved": fwd_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": fwd_gbs / HBM_PEAK_GBS, "traffic": traffic},
         "kernel_sources_sha1": khash,

@@ -31,7 +31,13 @@
  *    a cached parameter plan in device memory; building it allocates memory,
  *    launches the generator kernels on `stream` and waits for them.  Calls
  *    that reuse a cached plan allocate nothing except where noted.
- *    mck_shutdown() frees the cache.  The cache is thread-safe.
+ *    The cache is thread-safe and holds at most 32 plans / 2 GiB per
+ *    process, evicting the least recently used.  Each call pins its plan
+ *    from lookup until its last launch is enqueued, so an eviction or
+ *    mck_shutdown() on another thread never frees a plan in use.  A call
+ *    enqueued on a stream that is being captured into a graph marks its
+ *    plan "captured": eviction never frees it (the graph reads it at every
+ *    replay); mck_shutdown() does, so destroy such graphs first.
  *  - Gradient outputs are overwritten, not accumulated; a NULL gradient
  *    pointer skips that gradient.
  *  - batch == 0 is a no-op that returns MCK_OK.
@@ -115,8 +121,11 @@ const char* mck_last_error(void);
 mck_status mck_fwht(float* data, int64_t batch, int64_t n, mck_stream stream);
 
 /*
- * Generated parameters of a seed-mode plan, copied to caller buffers
- * (E x n each, n = a power of two in [2, MCK_MAX_N]): B (+-1 as float),
+ * Generated parameters of a seed-mode plan (section "McKernel", items
+ * Binary B, Permutation Pi, Gaussian G and the calibration C: the diagonals
+ * and the permutation of equation "mckernel", drawn from the seed by the
+ * hash-driven generator), copied to caller buffers
+ * (E x n each, n = a power of two in [2, MCK_MAX_N_LONG]): B (+-1 as float),
  * perm (int32 gather indices), G, S (FP32, S = RNE of the FP64 value with the
  * 1/(sigma sqrt n ||G||) factor included) and S64 (FP64, may be NULL).
  * Any of the outputs may be NULL.  sigma must be finite and > 0.
@@ -263,12 +272,22 @@ mck_status mck_forward_tuning_set(int64_t n, const mck_forward_tuning* t);
  */
 mck_status mck_autotune_forward_batched(const mck_instance* inst, int64_t count, int32_t reps, mck_stream stream);
 
-/* z = Z xhat without the trigonometric map: batch x (n E), expansion-major. */
+/*
+ * z = Z xhat without the trigonometric map (equation "mckernel" alone, before
+ * the [cos, sin] of equation "mcfeatures"): batch x (n E), expansion-major,
+ * block e = S_e H G_e Pi_e H B_e xhat.  Arguments as for mck_fastfood_forward
+ * (n <= MCK_MAX_N).  A test hook that exposes the projection the features
+ * are computed from.
+ */
 mck_status mck_fastfood_project(const float* x, int64_t batch, int64_t d, int64_t E, uint32_t seed,
                                 double sigma, mck_calibration calib, float* z, mck_stream stream);
 
 /*
- * Adjoint of the feature map: given dphi (batch x 2nE, the cotangent of phi)
+ * Adjoint of the feature map (the chain rule through equations "mckernel"
+ * and "mcfeatures"; H is symmetric and Pi^T is the scatter of Pi's gather),
+ * the gradient the paper's training of C, G and B by back-propagation needs
+ * (section "Empirical Analysis and Experiments").  n <= MCK_MAX_N.
+ * Given dphi (batch x 2nE, the cotangent of phi)
  * computes dx (batch x d), and dB, dG, dS (E x n each): the gradients of
  * <dphi, phi> with respect to x and to the diagonals B, G, S taken as free
  * variables, summed over the batch.  The forward chain is recomputed, not
@@ -280,7 +299,37 @@ mck_status mck_fastfood_backward(const float* x, const float* dphi, int64_t batc
                                  float* dG, float* dS, mck_stream stream);
 
 /*
- * Explicit-parameter forms: B, G, S (float) and perm (int32, a permutation of
+ * Launch shape that mck_fastfood_backward (and the explicit-parameter and
+ * training-step adjoints) use for a batch of `batch` rows of length d with E
+ * expansions: a host-side query that launches nothing and needs no GPU.  The
+ * adjoint's arithmetic (the chain rule through equation "mckernel") does not
+ * depend on it; the shape says which kernel path covers the rows, so that
+ * tests can show that every path they claim is exercised.
+ *   rows_per_pass  rows one block transforms together (one per wave, or
+ *                  several per wave for short rows);
+ *   passes         row groups one block takes in turn within each expansion;
+ *   rowblocks      blocks along the batch; block b owns rows
+ *                  [b passes rows_per_pass, (b + 1) passes rows_per_pass);
+ *   esplit         groups of expansions run by separate blocks (their dx
+ *                  shares summed afterwards in group order).
+ * Only the first 2^31-byte chunk of a batch larger than that is described.
+ * MCK_ERR_INVALID_ARG / MCK_ERR_UNSUPPORTED as for mck_fastfood_backward.
+ */
+typedef struct mck_backward_shape {
+    int32_t rows_per_pass;
+    int32_t passes;
+    int32_t esplit;
+    int32_t reserved;
+    int64_t rowblocks;
+} mck_backward_shape;
+mck_status mck_backward_launch_shape(int64_t batch, int64_t d, int64_t E, mck_backward_shape* out);
+
+/*
+ * Explicit-parameter forms of the feature map and its adjoint (equations
+ * "mckernel" and "mcfeatures" with the diagonals and the permutation given
+ * instead of generated: section "Empirical Analysis and Experiments" learns
+ * C, G and B, so they become free real diagonals).
+ * B, G, S (float) and perm (int32, a permutation of
  * 0..n-1; entries are reduced mod n) are caller-provided E x n device arrays,
  * with n = mck_padded_dim(d) given explicitly (must match) and S including
  * every scale.  These calls allocate a small temporary plan (E x n x 12
@@ -372,7 +421,9 @@ mck_status mck_fastfood_train_step(const float* x, const int32_t* labels, int64_
 mck_status mck_axpy(float* y, const float* x, int64_t count, float alpha, mck_stream stream);
 
 /* Frees every cached plan (waits for the device first) except those held by
- * a live mck_batched_graph or a call in progress on another thread. */
+ * a live mck_batched_graph or a call in progress on another thread.  Plans
+ * that calls under stream capture used are freed too: graphs captured from
+ * library calls must be destroyed before this is called. */
 void mck_shutdown(void);
 
 #ifdef __cplusplus

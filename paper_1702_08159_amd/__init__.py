@@ -39,7 +39,7 @@ MAX_N = 32768
 __all__ = ["padded_dim", "fwht", "fwht_", "params", "forward", "project", "backward", "forward_p",
            "backward_p", "fastfood", "FastfoodFunction", "FastfoodExplicit", "gen_boxmuller", "shutdown",
            "MckError", "PAPER_SEED", "MAX_N", "forward_batched", "autotune_batched", "forward_tuning",
-           "set_forward_tuning", "BatchedGraph", "forward_scaled"]
+           "set_forward_tuning", "BatchedGraph", "forward_scaled", "backward_launch_shape"]
 
 
 def _stream(t: torch.Tensor):
@@ -326,6 +326,15 @@ def forward_p(x, B, perm, G, S) -> torch.Tensor:
         _lib.call("mck_fastfood_forward_p", _ptr(x), batch, d, n, E, _ptr(B), _ptr(perm), _ptr(G), _ptr(S),
                   _ptr(out), _stream(x))
     return out
+
+
+def backward_launch_shape(batch: int, d: int, E: int) -> dict:
+    """Launch shape of the adjoint for (batch, d, E): rows_per_pass, passes,
+    esplit, rowblocks (a host query; nothing runs on the GPU)."""
+    sh = _lib.BackwardShape()
+    _lib.call("mck_backward_launch_shape", batch, d, E, ctypes.byref(sh))
+    return {"rows_per_pass": sh.rows_per_pass, "passes": sh.passes, "esplit": sh.esplit,
+            "rowblocks": sh.rowblocks}
 
 
 def backward_p(x, dphi, B, perm, G, S, need_dx=True, need_params=True):

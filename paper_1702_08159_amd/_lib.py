@@ -51,6 +51,7 @@ SIGNATURES = {
     "mck_head_backward": (_int, [_vp, _vp, _vp, _i64, _i64, _i64, _vp, _vp, _vp]),
     "mck_fastfood_train_step": (_int, [_vp, _vp, _i64, _i64, _i64, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp,
                                         ctypes.c_float, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "mck_backward_launch_shape": (_int, [_i64, _i64, _i64, _vp]),
     "mck_shutdown": (None, []),
 }
 
@@ -64,6 +65,12 @@ class Instance(ctypes.Structure):
 class ForwardTuning(ctypes.Structure):
     """mck_forward_tuning of the C interface."""
     _fields_ = [("split", ctypes.c_int32), ("waves", ctypes.c_int32)]
+
+
+class BackwardShape(ctypes.Structure):
+    """mck_backward_shape of the C interface."""
+    _fields_ = [("rows_per_pass", ctypes.c_int32), ("passes", ctypes.c_int32), ("esplit", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("rowblocks", _i64)]
 
 
 class MckError(RuntimeError):

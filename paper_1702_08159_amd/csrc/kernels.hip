@@ -785,6 +785,7 @@ struct RunGeometry {
             out->blocks = out->rowblocks * es;
         }
         out->block_threads = bg::THREADS;
+        out->rows_per_pass = bg::ROWS;
         return hipSuccess;
     }
 };
@@ -975,7 +976,7 @@ hipError_t launch_forward_group(int M, int P, int waves, bool vec, const GroupIn
 
 BwdGeometry backward_geometry(int M, int64_t batch, int d, int64_t E)
 {
-    BwdGeometry g{1, 1, 64, 1, 1};
+    BwdGeometry g{1, 1, 64, 1, 1, 1};
     (void)dispatch_m<RunGeometry>(M, batch, d, E, &g);
     return g;
 }

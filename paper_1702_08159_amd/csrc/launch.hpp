@@ -116,6 +116,7 @@ struct BwdGeometry {
     int block_threads;
     int esplit;
     int64_t rowblocks;
+    int rows_per_pass;
 };
 BwdGeometry backward_geometry(int M, int64_t batch, int d, int64_t E);
 

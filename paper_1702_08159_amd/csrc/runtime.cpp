@@ -16,6 +16,7 @@
 
 #include "mckernel.h"
 #include "launch.hpp"
+#include "plan_cache.hpp"
 
 namespace {
 
@@ -141,7 +142,8 @@ FwdTune current_tuning(int M)
 
 // ------------------------------------------------------------------ plan cache
 struct Plan {
-    int pins = 0;  // > 0 while a batched call holds it: not evicted
+    int pins = 0;           // > 0 while a call or a recorded graph holds it: not evicted
+    bool captured = false;  // used by a call under stream capture: not evicted (mck_shutdown frees it)
     int device = 0;
     uint32_t seed = 0;
     int64_t n = 0, E = 0;
@@ -172,7 +174,13 @@ struct Plan {
 };
 
 std::mutex g_mutex;
-std::list<Plan> g_plans;  // most recently used first
+mck::PlanList<Plan> g_plans;  // guarded by g_mutex
+
+struct GlobalCache {
+    std::mutex& mutex() { return g_mutex; }
+    mck::PlanList<Plan>& list() { return g_plans; }
+};
+GlobalCache g_cache;
 constexpr size_t kMaxPlans = 32;
 constexpr size_t kMaxPlanBytes = size_t(2) << 30;
 
@@ -199,15 +207,14 @@ mck_status get_plan(uint32_t seed, int64_t n, int64_t E, double sigma, int calib
     if (err != hipSuccess)
         return hip_fail(err, "hipGetDevice");
     std::lock_guard<std::mutex> lock(g_mutex);
-    for (auto it = g_plans.begin(); it != g_plans.end(); ++it) {
-        if (it->device == dev && it->seed == seed && it->n == n && it->E == E && it->sigma == sigma &&
-            it->calib == calib) {
-            g_plans.splice(g_plans.begin(), g_plans, it);
-            *out = &g_plans.front();
-            if (pin)
-                ++g_plans.front().pins;
-            return MCK_OK;
-        }
+    Plan* hit = g_plans.find(
+        [&](const Plan& q) {
+            return q.device == dev && q.seed == seed && q.n == n && q.E == E && q.sigma == sigma && q.calib == calib;
+        },
+        pin);
+    if (hit != nullptr) {
+        *out = hit;
+        return MCK_OK;
     }
     Plan p;
     p.device = dev;
@@ -232,18 +239,8 @@ mck_status get_plan(uint32_t seed, int64_t n, int64_t E, double sigma, int calib
         off[i] = total;
         total += align_up(sz[i]);
     }
-    size_t used = 0;
-    for (auto& q : g_plans)
-        used += q.bytes;
-    // evict least recently used unpinned plans
-    for (auto it = g_plans.end(); it != g_plans.begin() && (g_plans.size() >= kMaxPlans || used + total > kMaxPlanBytes);) {
-        --it;
-        if (it->pins > 0)
-            continue;
-        used -= it->bytes;
-        free_plan(*it);
-        it = g_plans.erase(it);
-    }
+    // evict least recently used plans that no call or graph holds
+    g_plans.make_room(total, kMaxPlans, kMaxPlanBytes, free_plan);
     err = hipMalloc(&p.block, total);
     if (err != hipSuccess) {
         p.block = nullptr;
@@ -296,12 +293,39 @@ mck_status get_plan(uint32_t seed, int64_t n, int64_t E, double sigma, int calib
         free_plan(p);
         return hip_fail(err, "plan generation");
     }
-    g_plans.push_front(p);
-    *out = &g_plans.front();
-    if (pin)
-        ++g_plans.front().pins;
+    *out = g_plans.insert(std::move(p), pin);
     return MCK_OK;
 }
+
+// The plan of one call, pinned from lookup until the call has enqueued its
+// last launch, so that an eviction or mck_shutdown on another thread cannot
+// free it in between.  A call made while its stream is being captured into
+// a graph marks the plan `captured`: the graph reads it at every replay, so
+// eviction never frees it (mck_shutdown does).
+class PlanHold : public mck::PinnedPlan<GlobalCache, Plan> {
+public:
+    PlanHold() : mck::PinnedPlan<GlobalCache, Plan>(g_cache) {}
+
+    mck_status acquire(uint32_t seed, int64_t n, int64_t E, double sigma, int calib, hipStream_t s)
+    {
+        release();
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        const hipError_t err = hipStreamIsCapturing(s, &cap);
+        if (err != hipSuccess)
+            return hip_fail(err, "hipStreamIsCapturing");
+        Plan* p = nullptr;
+        const mck_status st = get_plan(seed, n, E, sigma, calib, s, &p, true);
+        if (st != MCK_OK)
+            return st;
+        if (cap != hipStreamCaptureStatusNone) {
+            std::lock_guard<std::mutex> lock(g_mutex);
+            p->captured = true;
+        }
+        adopt(p);
+        return MCK_OK;
+    }
+};
+
 
 struct FwdArrays {
     const uint32_t* goff;
@@ -360,16 +384,22 @@ bool vec_ok(const void* a, const void* b, int64_t d, int64_t n)
     return aligned16(a) && aligned16(b) && (d % 4 == 0) && n >= 4;
 }
 
+// Rows per backward launch: the x, dx and dphi ranges of a launch stay below
+// 2^31 bytes.
+int64_t backward_rows_per_launch(int64_t d, int64_t n, int64_t E)
+{
+    const int64_t lim = (int64_t(1) << 31) - 4096;
+    const int64_t row_bytes = 4 * (2 * n * E > d ? 2 * n * E : d);
+    return lim / row_bytes < 1 ? 1 : lim / row_bytes;
+}
+
 mck_status run_backward(const float* x, const float* dphi, int64_t batch, int64_t d, int64_t n, int64_t E,
                         const float* B, const uint32_t* goff, const float* Gk, const float* S32, const float* Sh,
                         float* dx, float* dB, float* dG, float* dS, hipStream_t s)
 {
     const int M = log2i(n);
     const bool want_params = dB || dG || dS;
-    // rows per launch: keep the x, dx and dphi ranges of a launch below 2^31 bytes
-    const int64_t lim = (int64_t(1) << 31) - 4096;
-    const int64_t row_bytes = 4 * (2 * n * E > d ? 2 * n * E : d);
-    const int64_t rows_per = lim / row_bytes < 1 ? 1 : lim / row_bytes;
+    const int64_t rows_per = backward_rows_per_launch(d, n, E);
     int64_t total_blocks = 0;
     for (int64_t r0 = 0; r0 < batch; r0 += rows_per)
         total_blocks += mck::backward_geometry(M, batch - r0 < rows_per ? batch - r0 : rows_per, (int)d, E).rowblocks;
@@ -478,8 +508,8 @@ mck_status mck_fastfood_params(uint32_t seed, int64_t n, int64_t E, double sigma
             return st;
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
-    Plan* p = nullptr;
-    st = get_plan(seed, n, E, sigma, calib, s, &p);
+    PlanHold p;
+    st = p.acquire(seed, n, E, sigma, calib, s);
     if (st != MCK_OK)
         return st;
     const size_t en = (size_t)(n * E);
@@ -574,16 +604,16 @@ static mck_status forward_common(const float* x, int64_t batch, int64_t d, int64
     if (batch == 0)
         return MCK_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    Plan* p = nullptr;
+    PlanHold p;
     if (n > MCK_MAX_N && !trig)
         return check_single_pass(n);
-    st = get_plan(seed, n, E, sigma, calib, s, &p);
+    st = p.acquire(seed, n, E, sigma, calib, s);
     if (st != MCK_OK)
         return st;
     if (n > MCK_MAX_N)
-        return forward_long(p, x, 0, batch, d, n, E, out, 0, s, feature_scale(n, E));
+        return forward_long(p.get(), x, 0, batch, d, n, E, out, 0, s, feature_scale(n, E));
     const FwdTune t = current_tuning(log2i(n));
-    const FwdArrays a = fwd_arrays(p, t.P);
+    const FwdArrays a = fwd_arrays(p.get(), t.P);
     const hipError_t err = mck::launch_forward(log2i(n), t.P, t.waves, true, vec_ok(x, out, d, n), trig, x, batch,
                                                (int)d, E, p->B, a.goff, a.Gs, trig ? p->Sh : p->S32,
                                                feature_scale(n, E), out, s);
@@ -627,18 +657,18 @@ mck_status mck_fastfood_forward_t(const void* x, mck_dtype x_type, int64_t batch
     if (batch == 0)
         return MCK_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    Plan* p = nullptr;
-    st = get_plan(seed, n, E, sigma, calib, s, &p);
+    PlanHold p;
+    st = p.acquire(seed, n, E, sigma, calib, s);
     if (st != MCK_OK)
         return st;
     if (n > MCK_MAX_N)
-        return forward_long(p, x, xt, batch, d, n, E, phi, yt, s, feature_scale(n, E));
+        return forward_long(p.get(), x, xt, batch, d, n, E, phi, yt, s, feature_scale(n, E));
     // vector path: 4 elements per access, so 4-element alignment of both arrays
     const uintptr_t xa = 4u * (xt == 0 ? 4u : 2u), ya = 4u * (yt == 0 ? 4u : 2u);
     const bool vec = (reinterpret_cast<uintptr_t>(x) % xa == 0) && (reinterpret_cast<uintptr_t>(phi) % ya == 0) &&
                      d % 4 == 0 && n >= 4;
     const FwdTune t = current_tuning(log2i(n));
-    const FwdArrays a = fwd_arrays(p, t.P);
+    const FwdArrays a = fwd_arrays(p.get(), t.P);
     const hipError_t err = mck::launch_forward_t(log2i(n), t.P, t.waves, vec, xt, yt, x, batch, (int)d, E, p->B,
                                                  a.goff, a.Gs, p->Sh, feature_scale(n, E), phi, s);
     return err == hipSuccess ? MCK_OK : hip_fail(err, "forward launch");
@@ -657,7 +687,7 @@ void batched_unpin(const std::vector<MapRef>& maps)
 {
     std::lock_guard<std::mutex> lock(g_mutex);
     for (const MapRef& m : maps)
-        --const_cast<Plan*>(m.p)->pins;
+        g_plans.unpin(const_cast<Plan*>(m.p));
 }
 
 // Validates every instance and pins the plans of the non-empty ones; on
@@ -685,14 +715,23 @@ mck_status batched_setup(const mck_instance* inst, int64_t count, hipStream_t s,
         }
     }
     maps->clear();
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    const hipError_t cerr = hipStreamIsCapturing(s, &cap);
+    if (cerr != hipSuccess)
+        return hip_fail(cerr, "hipStreamIsCapturing");
     mck_status st = MCK_OK;
     for (int64_t i = 0; i < count && st == MCK_OK; ++i) {
         if (inst[i].batch == 0)
             continue;
         Plan* p = nullptr;
         st = get_plan(inst[i].seed, ns[i], inst[i].E, inst[i].sigma, inst[i].calib, s, &p, true);
-        if (st == MCK_OK)
+        if (st == MCK_OK) {
             maps->push_back(MapRef{&inst[i], ns[i], p});
+            if (cap != hipStreamCaptureStatusNone) {  // a caller's graph replays these launches
+                std::lock_guard<std::mutex> lock(g_mutex);
+                p->captured = true;
+            }
+        }
     }
     if (st != MCK_OK)
         batched_unpin(*maps);
@@ -776,8 +815,8 @@ mck_status mck_fastfood_forward_scaled(const void* x, mck_dtype x_type, const in
     if (batch == 0)
         return MCK_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    Plan* p = nullptr;
-    st = get_plan(seed, n, E, sigma, calib, s, &p);
+    PlanHold p;
+    st = p.acquire(seed, n, E, sigma, calib, s);
     if (st != MCK_OK)
         return st;
     // |phi| <= c = 1/sqrt(nE): scale by 2^j, the largest power of two with
@@ -787,7 +826,7 @@ mck_status mck_fastfood_forward_scaled(const void* x, mck_dtype x_type, const in
         ++j;
     const float cs = std::ldexp(feature_scale(n, E), j);
     if (n > MCK_MAX_N) {
-        st = forward_long(p, x, xt, batch, d, n, E, phi, yt, s, cs);
+        st = forward_long(p.get(), x, xt, batch, d, n, E, phi, yt, s, cs);
         if (st == MCK_OK && phi_exp != nullptr) {
             const hipError_t ferr = mck::launch_fill_i8(phi_exp, batch, (int8_t)j, s);
             if (ferr != hipSuccess)
@@ -796,7 +835,7 @@ mck_status mck_fastfood_forward_scaled(const void* x, mck_dtype x_type, const in
         return st;
     }
     const FwdTune t = current_tuning(log2i(n));
-    const FwdArrays a = fwd_arrays(p, t.P);
+    const FwdArrays a = fwd_arrays(p.get(), t.P);
     const uintptr_t xa = 4u * (xt == 0 ? 4u : 2u), ya = 4u * (yt == 0 ? 4u : 2u);
     const bool vec = (reinterpret_cast<uintptr_t>(x) % xa == 0) && (reinterpret_cast<uintptr_t>(phi) % ya == 0) &&
                      d % 4 == 0 && n >= 4;
@@ -1162,7 +1201,7 @@ mck_status mck_fastfood_backward(const float* x, const float* dphi, int64_t batc
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (!dx && !dB && !dG && !dS)
         return MCK_OK;
-    Plan* p = nullptr;
+    PlanHold p;
     if (batch == 0) {
         if (!dB && !dG && !dS)
             return MCK_OK;
@@ -1173,10 +1212,31 @@ mck_status mck_fastfood_backward(const float* x, const float* dphi, int64_t batc
                 err = hipMemsetAsync(o, 0, (size_t)(n * E) * sizeof(float), s);
         return err == hipSuccess ? MCK_OK : hip_fail(err, "zero gradients");
     }
-    st = get_plan(seed, n, E, sigma, calib, s, &p);
+    st = p.acquire(seed, n, E, sigma, calib, s);
     if (st != MCK_OK)
         return st;
     return run_backward(x, dphi, batch, d, n, E, p->B, p->goffB, p->GkB, p->S32, p->Sh, dx, dB, dG, dS, s);
+}
+
+mck_status mck_backward_launch_shape(int64_t batch, int64_t d, int64_t E, mck_backward_shape* out)
+{
+    if (out == nullptr)
+        return fail(MCK_ERR_INVALID_ARG, "out is NULL");
+    int64_t n = 0;
+    mck_status st = check_common(batch, d, E, &n);
+    if (st != MCK_OK)
+        return st;
+    st = check_single_pass(n);
+    if (st != MCK_OK)
+        return st;
+    const int64_t rows = backward_rows_per_launch(d, n, E);
+    const mck::BwdGeometry geo = mck::backward_geometry(log2i(n), batch < rows ? batch : rows, (int)d, E);
+    out->rows_per_pass = geo.rows_per_pass;
+    out->passes = geo.passes;
+    out->esplit = geo.esplit;
+    out->reserved = 0;
+    out->rowblocks = geo.rowblocks;
+    return MCK_OK;
 }
 
 static mck_status check_explicit(int64_t batch, int64_t d, int64_t n, int64_t E, const float* B,
@@ -1447,19 +1507,15 @@ mck_status mck_axpy(float* y, const float* x, int64_t count, float alpha, mck_st
 void mck_shutdown(void)
 {
     std::lock_guard<std::mutex> lock(g_mutex);
-    for (auto it = g_plans.begin(); it != g_plans.end();) {
-        if (it->pins > 0) {  // held by a recorded graph or a call in progress
-            ++it;
-            continue;
-        }
+    // plans held by a recorded graph or a call in progress stay
+    g_plans.clear_unpinned([](Plan& p) {
         int cur = 0;
         (void)hipGetDevice(&cur);
-        (void)hipSetDevice(it->device);
+        (void)hipSetDevice(p.device);
         (void)hipDeviceSynchronize();
         (void)hipSetDevice(cur);
-        free_plan(*it);
-        it = g_plans.erase(it);
-    }
+        free_plan(p);
+    });
 }
 
 }  // extern "C"

@@ -167,3 +167,22 @@ def test_scaled_forward_validation_without_gpu(lib):
     assert _st(lib, sc, p16, 0, p16, 2, 40000, 1, 1, 1.0, 0, p16, 0, null, null) == 2  # x exponents, n > 2^15
     assert _st(lib, sc, null, 0, null, 2, 8, 1, 1, 1.0, 0, p16, 0, null, null) == 1
     assert _st(lib, sc, null, 0, null, 0, 8, 1, 1, 1.0, 0, null, 0, null, null) == 0
+
+
+def test_backward_launch_shape_without_gpu(lib):
+    # the host query of the adjoint's launch shape: the metric workload runs
+    # four row passes per block over 256 blocks, small batches split the
+    # expansions, the LDS caps the passes (4 at d = 784, 3 at d = 1024)
+    import paper_1702_08159_amd as mk
+
+    assert mk.backward_launch_shape(8192, 784, 16) == {"rows_per_pass": 8, "passes": 4, "esplit": 1,
+                                                       "rowblocks": 256}
+    assert mk.backward_launch_shape(1024, 784, 16) == {"rows_per_pass": 8, "passes": 1, "esplit": 2,
+                                                       "rowblocks": 128}
+    assert mk.backward_launch_shape(8200, 784, 1)["passes"] == 4
+    assert mk.backward_launch_shape(8193, 1024, 1)["passes"] == 3
+    assert mk.backward_launch_shape(32769, 64, 2) == {"rows_per_pass": 128, "passes": 2, "esplit": 2,
+                                                      "rowblocks": 129}
+    with pytest.raises(mk.MckError):
+        mk.backward_launch_shape(4, 40000, 1)   # beyond the single-pass kernels
+    assert _st(lib, "mck_backward_launch_shape", 4, 8, 1, None) == 1

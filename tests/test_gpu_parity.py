@@ -52,6 +52,24 @@ def tensor_rel(a, ref):
     return float(np.linalg.norm(a - ref) / max(np.linalg.norm(ref), 1e-300))
 
 
+def elem_err(phi, ref_phi, n, E):
+    """max |phi - ref| * sqrt(nE): the worst single feature's error in units of
+    the feature scale c = 1/sqrt(nE)."""
+    return float(np.abs(np.asarray(phi, np.float64) - ref_phi).max() * math.sqrt(n * E))
+
+
+def elem_tol(ref_z, n):
+    """Bound on elem_err from the FP32 arithmetic: a feature's error over c is
+    the absolute error of its z_i plus that of the hardware sin/cos (about
+    2^-20 after the exact reduction to revolutions).  z_i passes through
+    2 log2(n) butterfly levels and three diagonal products, each rounding
+    with unit roundoff u = 2^-24 relative to the partial sums, whose
+    magnitude is at most of the order of max_j |z_j|: the first-order
+    estimate (2 log2 n + 3) u max|z| + 2^-20."""
+    m = int(round(math.log2(n)))
+    return (2 * m + 3) * 2.0 ** -24 * float(np.abs(ref_z).max()) + 2.0 ** -20
+
+
 def to_dev(torch, a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
@@ -139,6 +157,9 @@ def test_forward_mnist_parity_case(mk, torch_mod, orc, seed):
     assert phi.shape == (64, 2048)
     assert rowwise_rel(z, ref_z).max() <= FEAT_TOL
     assert rowwise_rel(phi, ref_phi).max() <= FEAT_TOL
+    e, tol = elem_err(phi, ref_phi, 1024, 1), elem_tol(ref_z, 1024)
+    print("max |dphi| sqrt(nE) = %.3e (bound %.3e)" % (e, tol))
+    assert e <= tol
 
 
 @pytest.mark.parametrize("d,E,batch", [(1, 1, 5), (2, 2, 70), (3, 3, 9), (4, 1, 65), (8, 2, 33), (13, 3, 17),
@@ -155,6 +176,7 @@ def test_forward_all_sizes(mk, torch_mod, orc, d, E, batch):
     ref_phi, ref_z = _oracle_phi(orc, x, E, 4242, sigma)
     assert phi.shape == ref_phi.shape
     assert rowwise_rel(phi, ref_phi).max() <= FEAT_TOL
+    assert elem_err(phi, ref_phi, n, E) <= elem_tol(ref_z, n)
     z = mk.project(to_dev(torch, x), E, 4242, sigma).cpu().numpy()
     assert rowwise_rel(z, ref_z).max() <= FEAT_TOL
 
@@ -170,8 +192,11 @@ def test_forward_metric_workload_sampled(mk, torch_mod, orc):
     rows = np.random.default_rng(3).choice(8192, size=24, replace=False)
     rows = np.concatenate([rows, [0, 8191]])
     sub = phi[torch.from_numpy(rows).cuda()].cpu().numpy()
-    ref_phi, _ = _oracle_phi(orc, x[rows], 16, workloads.FASTFOOD_SEED, 2.0)
+    ref_phi, ref_z = _oracle_phi(orc, x[rows], 16, workloads.FASTFOOD_SEED, 2.0)
     assert rowwise_rel(sub, ref_phi).max() <= FEAT_TOL
+    e, tol = elem_err(sub, ref_phi, 1024, 16), elem_tol(ref_z, 1024)
+    print("max |dphi| sqrt(nE) = %.3e (bound %.3e)" % (e, tol))
+    assert e <= tol
 
 
 def test_forward_unaligned_and_empty(mk, torch_mod, orc):
