@@ -344,6 +344,31 @@ mck_status mck_fastfood_backward_p(const float* x, const float* dphi, int64_t ba
                                    float* dx, float* dB, float* dG, float* dS, mck_stream stream);
 
 /*
+ * mck_fastfood_backward_p for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, results (bit-identical) and errors as
+ * mck_fastfood_backward_p, and it calls no allocator.  Its temporaries (the
+ * backward's parameter copies, the per-block partial sums of dB, dG, dS and
+ * the dx slices of split expansions) live in one static device array of
+ * MCK_NOALLOC_SCRATCH_BYTES, which each GPU the library runs this call on
+ * holds from the call's first use there until the process ends.  A problem
+ * whose temporaries exceed it fails with MCK_ERR_UNSUPPORTED before anything
+ * is enqueued; the message gives the bytes needed.  With rowblocks and
+ * esplit as mck_backward_launch_shape reports them, and 256-byte alignment
+ * of each part, they are 4 E (max(n, min(64 n, 1024)) + 2 n) (parameter
+ * copies) + 12 n E rowblocks (partial sums, when dB, dG or dS is requested)
+ * + 4 esplit batch d (dx slices, when dx is requested and esplit > 1):
+ * 50.5 MB at batch 8192, d = 784, E = 16.
+ * All calls on one GPU share that array: calls that overlap on one GPU (on
+ * different streams or threads) race, and the caller must order them.
+ */
+#define MCK_NOALLOC_SCRATCH_BYTES (64u << 20)
+mck_status mck_fastfood_backward_p_noalloc(const float* x, const float* dphi, int64_t batch, int64_t d, int64_t n,
+                                           int64_t E, const float* B, const int32_t* perm, const float* G,
+                                           const float* S, float* dx, float* dB, float* dG, float* dS,
+                                           mck_stream stream);
+
+/*
  * Generator self-check: the FP32 Box-Muller pair of the generator for `count`
  * pairs of hash words (a[k], b[k]) -> (g0[k], g1[k]); lets a test compare the
  * device generator with an independent implementation over all 2^24 inputs.

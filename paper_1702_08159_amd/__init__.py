@@ -337,17 +337,25 @@ def backward_launch_shape(batch: int, d: int, E: int) -> dict:
             "rowblocks": sh.rowblocks}
 
 
-def backward_p(x, dphi, B, perm, G, S, need_dx=True, need_params=True):
+def backward_p(x, dphi, B, perm, G, S, need_dx=True, need_params=True, out=None, noalloc=False):
+    """dx, dB, dG, dS of <dphi, phi> for explicit diagonals.  out: optional
+    (dx, dB, dG, dS) tensors to write (None entries are skipped).  noalloc:
+    call mck_fastfood_backward_p_noalloc, whose temporaries live in the
+    library's static device scratch (the library allocates nothing)."""
     _check(x, "x")
     _check(dphi, "dphi")
     batch, d = _rows(x)
     E, n = B.shape
-    dx = torch.empty_like(x) if need_dx else None
-    dB = dG = dS = None
-    if need_params:
-        dB, dG, dS = (torch.empty((E, n), dtype=torch.float32, device=x.device) for _ in range(3))
+    if out is not None:
+        dx, dB, dG, dS = out
+    else:
+        dx = torch.empty_like(x) if need_dx else None
+        dB = dG = dS = None
+        if need_params:
+            dB, dG, dS = (torch.empty((E, n), dtype=torch.float32, device=x.device) for _ in range(3))
+    name = "mck_fastfood_backward_p_noalloc" if noalloc else "mck_fastfood_backward_p"
     with torch.cuda.device(x.device):
-        _lib.call("mck_fastfood_backward_p", _ptr(x), _ptr(dphi), batch, d, n, E, _ptr(B), _ptr(perm), _ptr(G),
+        _lib.call(name, _ptr(x), _ptr(dphi), batch, d, n, E, _ptr(B), _ptr(perm), _ptr(G),
                   _ptr(S), _ptr(dx), _ptr(dB), _ptr(dG), _ptr(dS), _stream(x))
     return dx, dB, dG, dS
 

@@ -44,6 +44,8 @@ SIGNATURES = {
     "mck_fastfood_forward_p": (_int, [_vp, _i64, _i64, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
     "mck_fastfood_backward_p": (_int, [_vp, _vp, _i64, _i64, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                        _vp, _vp]),
+    "mck_fastfood_backward_p_noalloc": (_int, [_vp, _vp, _i64, _i64, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp,
+                                               _vp, _vp, _vp]),
     "mck_gen_boxmuller": (_int, [_vp, _vp, _i64, _vp, _vp, _vp]),
     "mck_softmax_xent": (_int, [_vp, _vp, _i64, _i64, _vp, _vp, _vp, _vp]),
     "mck_axpy": (_int, [_vp, _vp, _i64, ctypes.c_float, _vp]),

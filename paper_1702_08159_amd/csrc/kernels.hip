@@ -853,6 +853,15 @@ struct RunDerive {
 };
 
 template <int M>
+struct RunDeriveBwd {
+    static hipError_t run(int64_t E, const int32_t* perm, const float* G, const float* S32, uint32_t* goff_b,
+                          float* Gk_b, float* Sh, hipStream_t s)
+    {
+        return derive_one<M, bwd_p(M)>(E, perm, G, nullptr, nullptr, S32, goff_b, Gk_b, nullptr, Sh, s);
+    }
+};
+
+template <int M>
 struct RunDeriveFwd {
     static hipError_t run(int PF, int64_t E, const int32_t* perm, const float* G, const float* Bsign,
                           uint32_t* goff_f, float* Gs_f, hipStream_t s)
@@ -1009,6 +1018,12 @@ hipError_t launch_derive(int M, int PF, int64_t E, const int32_t* perm, const fl
                          float* Gk_b, float* Sh, hipStream_t s)
 {
     return dispatch_m<RunDerive>(M, PF, E, perm, G, Bsign, S64, S32, goff_f, Gs_f, goff_b, Gk_b, Sh, s);
+}
+
+hipError_t launch_derive_bwd(int M, int64_t E, const int32_t* perm, const float* G, const float* S32,
+                             uint32_t* goff_b, float* Gk_b, float* Sh, hipStream_t s)
+{
+    return dispatch_m<RunDeriveBwd>(M, E, perm, G, S32, goff_b, Gk_b, Sh, s);
 }
 
 hipError_t launch_derive_fwd(int M, int PF, int64_t E, const int32_t* perm, const float* G, const float* Bsign,

@@ -33,6 +33,9 @@ void plan_elems(int M, int64_t* fwd_goff, int64_t* bwd_goff);
 hipError_t launch_derive(int M, int PF, int64_t E, const int32_t* perm, const float* G, const float* Bsign,
                          const double* S64, const float* S32, uint32_t* goff_f, float* Gs_f, uint32_t* goff_b,
                          float* Gk_b, float* Sh, hipStream_t s);
+// The backward arrays alone (goff_b, Gk_b) and Sh, from FP32 S.
+hipError_t launch_derive_bwd(int M, int64_t E, const int32_t* perm, const float* G, const float* S32,
+                             uint32_t* goff_b, float* Gk_b, float* Sh, hipStream_t s);
 // The forward arrays alone (goff_f, Gs_f) for register split PF.
 hipError_t launch_derive_fwd(int M, int PF, int64_t E, const int32_t* perm, const float* G, const float* Bsign,
                              uint32_t* goff_f, float* Gs_f, hipStream_t s);

@@ -393,23 +393,62 @@ int64_t backward_rows_per_launch(int64_t d, int64_t n, int64_t E)
     return lim / row_bytes < 1 ? 1 : lim / row_bytes;
 }
 
+// Device temporaries of one adjoint call: the per-block partial sums of dS,
+// dG, dB (all launches of the call, reduced once at the end) and the dx
+// slices of one launch whose expansions are split over block groups (reused
+// by the next launch: the launches are ordered on the stream).
+struct BwdScratch {
+    int64_t total_blocks = 0;
+    size_t partial_bytes = 0;
+    size_t dxs_bytes = 0;
+    size_t bytes() const { return align_up(partial_bytes) + align_up(dxs_bytes); }
+};
+
+BwdScratch backward_scratch(int64_t batch, int64_t d, int64_t n, int64_t E, bool want_dx, bool want_params)
+{
+    BwdScratch b;
+    const int M = log2i(n);
+    const int64_t rows_per = backward_rows_per_launch(d, n, E);
+    for (int64_t r0 = 0; r0 < batch; r0 += rows_per) {
+        const int64_t rows = batch - r0 < rows_per ? batch - r0 : rows_per;
+        const mck::BwdGeometry geo = mck::backward_geometry(M, rows, (int)d, E);
+        b.total_blocks += geo.rowblocks;
+        if (want_dx && geo.esplit > 1) {
+            const size_t need = (size_t)(geo.esplit * rows * d) * sizeof(float);
+            b.dxs_bytes = need > b.dxs_bytes ? need : b.dxs_bytes;
+        }
+    }
+    if (want_params)
+        b.partial_bytes = (size_t)b.total_blocks * E * 3 * n * sizeof(float);
+    return b;
+}
+
+// The adjoint's launches.  ws: the call's temporaries (BwdScratch layout:
+// partials, then dx slices), or null to allocate them on the stream.
 mck_status run_backward(const float* x, const float* dphi, int64_t batch, int64_t d, int64_t n, int64_t E,
                         const float* B, const uint32_t* goff, const float* Gk, const float* S32, const float* Sh,
-                        float* dx, float* dB, float* dG, float* dS, hipStream_t s)
+                        float* dx, float* dB, float* dG, float* dS, hipStream_t s, char* ws = nullptr)
 {
     const int M = log2i(n);
     const bool want_params = dB || dG || dS;
     const int64_t rows_per = backward_rows_per_launch(d, n, E);
-    int64_t total_blocks = 0;
-    for (int64_t r0 = 0; r0 < batch; r0 += rows_per)
-        total_blocks += mck::backward_geometry(M, batch - r0 < rows_per ? batch - r0 : rows_per, (int)d, E).rowblocks;
+    const BwdScratch need = backward_scratch(batch, d, n, E, dx != nullptr, want_params);
     float* partial = nullptr;
+    float* dxs_ws = ws ? reinterpret_cast<float*>(ws + align_up(need.partial_bytes)) : nullptr;
     hipError_t err;
     if (want_params) {
-        err = hipMallocAsync(reinterpret_cast<void**>(&partial), (size_t)total_blocks * E * 3 * n * sizeof(float), s);
-        if (err != hipSuccess)
-            return fail(MCK_ERR_NO_MEMORY, std::string("backward partials: ") + hipGetErrorString(err));
+        if (ws) {
+            partial = reinterpret_cast<float*>(ws);
+        } else {
+            err = hipMallocAsync(reinterpret_cast<void**>(&partial), need.partial_bytes, s);
+            if (err != hipSuccess)
+                return fail(MCK_ERR_NO_MEMORY, std::string("backward partials: ") + hipGetErrorString(err));
+        }
     }
+    auto release = [&](void* p) {
+        if (p && !ws)
+            (void)hipFreeAsync(p, s);
+    };
     const bool vec = vec_ok(x, dphi, d, n) && (dx == nullptr || aligned16(dx));
     const float cs = feature_scale(n, E);
     err = hipSuccess;
@@ -421,11 +460,15 @@ mck_status run_backward(const float* x, const float* dphi, int64_t batch, int64_
         float* dxr = dx ? dx + r0 * d : nullptr;
         float* dxs = nullptr;  // per expansion group dx slices
         if (dx && geo.esplit > 1) {
-            err = hipMallocAsync(reinterpret_cast<void**>(&dxs), (size_t)(geo.esplit * rows * d) * sizeof(float), s);
-            if (err != hipSuccess) {
-                if (partial)
-                    (void)hipFreeAsync(partial, s);
-                return fail(MCK_ERR_NO_MEMORY, std::string("backward dx slices: ") + hipGetErrorString(err));
+            if (ws) {
+                dxs = dxs_ws;
+            } else {
+                err = hipMallocAsync(reinterpret_cast<void**>(&dxs), (size_t)(geo.esplit * rows * d) * sizeof(float),
+                                     s);
+                if (err != hipSuccess) {
+                    release(partial);
+                    return fail(MCK_ERR_NO_MEMORY, std::string("backward dx slices: ") + hipGetErrorString(err));
+                }
             }
         }
         err = mck::launch_backward(M, vec && (dxs == nullptr || aligned16(dxs)), x + r0 * d, dphi + r0 * 2 * n * E,
@@ -433,16 +476,51 @@ mck_status run_backward(const float* x, const float* dphi, int64_t batch, int64_
         if (dxs) {
             if (err == hipSuccess)
                 err = mck::launch_sum_groups(dxs, geo.esplit, rows * d, dxr, s);
-            (void)hipFreeAsync(dxs, s);
+            release(dxs);
         }
         done_blocks += geo.rowblocks;
     }
     if (err == hipSuccess && want_params)
-        err = mck::launch_reduce(partial, total_blocks, E, n, dS, dG, dB, s);
-    if (partial)
-        (void)hipFreeAsync(partial, s);
+        err = mck::launch_reduce(partial, need.total_blocks, E, n, dS, dG, dB, s);
+    release(partial);
     if (err != hipSuccess)
         return hip_fail(err, "backward launch");
+    return MCK_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ static scratch
+// The temporaries of mck_fastfood_backward_p_noalloc live in this array
+// instead of allocations.  In host code its name stands for a host-side
+// shadow, not for device memory: the device address of each GPU's copy is
+// looked up once per device (scratch_on_current_device) and only that
+// address is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[MCK_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mutex;
+std::map<int, char*> g_scratch_addr;  // device ordinal -> address of its copy of `scratch`
+
+mck_status scratch_on_current_device(char** out)
+{
+    int dev = 0;
+    hipError_t err = hipGetDevice(&dev);
+    if (err != hipSuccess)
+        return hip_fail(err, "hipGetDevice");
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    const auto it = g_scratch_addr.find(dev);
+    if (it != g_scratch_addr.end()) {
+        *out = it->second;
+        return MCK_OK;
+    }
+    void* p = nullptr;
+    err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (err != hipSuccess || p == nullptr)
+        return hip_fail(err != hipSuccess ? err : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+    g_scratch_addr[dev] = static_cast<char*>(p);
+    *out = static_cast<char*>(p);
     return MCK_OK;
 }
 
@@ -1093,7 +1171,7 @@ mck_status mck_batched_graph_create(const mck_instance* inst, int64_t count, mck
         return st;
     }
     // one scratch for the long maps: their launches are serialized in the graph
-    size_t scratch = 0;
+    size_t long_bytes = 0;
     for (const MapRef& m : g->maps) {
         if (m.n <= MCK_MAX_N)
             continue;
@@ -1102,10 +1180,10 @@ mck_status mck_batched_graph_create(const mck_instance* inst, int64_t count, mck
             return fail(MCK_ERR_UNSUPPORTED, "one row of phi exceeds 2^31 bytes");
         }
         const size_t need = (size_t)(2 * long_rows_per(m.q->batch, m.n) * m.n) * sizeof(float);
-        scratch = need > scratch ? need : scratch;
+        long_bytes = need > long_bytes ? need : long_bytes;
     }
-    if (scratch > 0) {
-        err = hipMalloc(&g->scratch, scratch);
+    if (long_bytes > 0) {
+        err = hipMalloc(&g->scratch, long_bytes);
         if (err != hipSuccess) {
             g->scratch = nullptr;
             graph_release(g);
@@ -1304,6 +1382,50 @@ mck_status mck_fastfood_backward_p(const float* x, const float* dphi, int64_t ba
     st = run_backward(x, dphi, batch, d, n, E, B, tp.goffB, tp.GkB, S, tp.Sh, dx, dB, dG, dS, s);
     (void)hipFreeAsync(tp.block, s);
     return st;
+}
+
+mck_status mck_fastfood_backward_p_noalloc(const float* x, const float* dphi, int64_t batch, int64_t d, int64_t n,
+                                           int64_t E, const float* B, const int32_t* perm, const float* G,
+                                           const float* S, float* dx, float* dB, float* dG, float* dS,
+                                           mck_stream stream)
+{
+    mck_status st = check_explicit(batch, d, n, E, B, perm, G, S);
+    if (st != MCK_OK)
+        return st;
+    if (batch > 0 && (x == nullptr || dphi == nullptr))
+        return fail(MCK_ERR_INVALID_ARG, "x or dphi is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!dx && !dB && !dG && !dS)
+        return MCK_OK;
+    if (batch == 0) {
+        hipError_t err = hipSuccess;
+        for (float* o : {dB, dG, dS})
+            if (o && err == hipSuccess)
+                err = mck::launch_sum_groups(nullptr, 0, n * E, o, s);  // a fill kernel: zeros
+        return err == hipSuccess ? MCK_OK : hip_fail(err, "zero gradients");
+    }
+    // scratch layout: the backward's parameter copies (gather offsets, G in
+    // the gather layout, S in revolutions), then the adjoint's temporaries
+    int64_t gf = 0, gb = 0;
+    mck::plan_elems(log2i(n), &gf, &gb);
+    const size_t a = align_up((size_t)(n * E) * 4), ab = align_up((size_t)gb * E * 4);
+    const BwdScratch bs = backward_scratch(batch, d, n, E, dx != nullptr, dB || dG || dS);
+    const size_t need = ab + 2 * a + bs.bytes();
+    if (need > (size_t)MCK_NOALLOC_SCRATCH_BYTES)
+        return fail(MCK_ERR_UNSUPPORTED, "temporaries of " + std::to_string(need) +
+                                             " bytes exceed the static scratch of " +
+                                             std::to_string((size_t)MCK_NOALLOC_SCRATCH_BYTES) + " bytes");
+    char* base = nullptr;
+    st = scratch_on_current_device(&base);
+    if (st != MCK_OK)
+        return st;
+    uint32_t* goffB = reinterpret_cast<uint32_t*>(base);
+    float* GkB = reinterpret_cast<float*>(base + ab);
+    float* Sh = reinterpret_cast<float*>(base + ab + a);
+    hipError_t err = mck::launch_derive_bwd(log2i(n), E, perm, G, S, goffB, GkB, Sh, s);
+    if (err != hipSuccess)
+        return hip_fail(err, "derive kernel");
+    return run_backward(x, dphi, batch, d, n, E, B, goffB, GkB, S, Sh, dx, dB, dG, dS, s, base + ab + 2 * a);
 }
 
 static mck_status check_head(int64_t batch, int64_t F, int64_t C);

@@ -186,3 +186,18 @@ def test_backward_launch_shape_without_gpu(lib):
     with pytest.raises(mk.MckError):
         mk.backward_launch_shape(4, 40000, 1)   # beyond the single-pass kernels
     assert _st(lib, "mck_backward_launch_shape", 4, 8, 1, None) == 1
+
+
+def test_noalloc_backward_refuses_oversized_problem_without_gpu(lib):
+    # the adjoint without allocation: its temporaries must fit the static
+    # scratch; 256 row blocks x E = 64 x 3n floats of partial sums (about
+    # 200 MB) are refused on the host, before any GPU call
+    p16 = ctypes.c_void_p(16)
+    fn = "mck_fastfood_backward_p_noalloc"
+    assert _st(lib, fn, p16, p16, 8192, 1024, 1024, 64, p16, p16, p16, p16, p16, p16, p16, p16, None) == 2
+    assert b"static scratch" in lib.mck_last_error()
+    # ... while dx alone needs only the parameter copies: validation passes
+    # up to the GPU, which is not touched here (NULL x is refused first)
+    assert _st(lib, fn, None, p16, 8192, 1024, 1024, 64, p16, p16, p16, p16, p16, None, None, None, None) == 1
+    assert _st(lib, fn, p16, p16, 8192, 1024, 512, 64, p16, p16, p16, p16, p16, p16, p16, p16, None) == 1
+    assert _st(lib, fn, p16, p16, 0, 1024, 1024, 64, p16, p16, p16, p16, None, None, None, None, None) == 0
