@@ -313,7 +313,40 @@ def main():
                            "sample": res_["phi"][:3].float().cpu().numpy() * 2.0 ** (-j)}
             log("long vectors (n=2^20, E=4), phi %s: %.3f ms/step" % (name, ms))
             del res_
-        for name in ("bf16", "f16", "bf16_scaled", "f16_scaled"):
+        # the stated reduced-precision form: x stored in 16 bits with a
+        # per-row power-of-2 exponent (stored row max in [0.5, 1)) and phi in
+        # 16 bits times 2^phi_exp
+        xk = torch.ceil(torch.log2(xl.abs().amax(dim=1))).to(torch.int8)
+        xl_scaled = xl * torch.pow(2.0, -xk.float())[:, None]  # exact: powers of two
+        x16_rows = {}
+        for name, dt in (("bf16_x_scaled", torch.bfloat16), ("f16_x_scaled", torch.float16)):
+            x16 = xl_scaled.to(dt)
+            res_ = {}
+
+            def lfx():
+                res_["phi"], res_["exp"] = mk.forward_scaled(x16, LONG_E, seed, LONG_SIGMA, x_exp=xk, out_dtype=dt)
+
+            lfx()
+            torch.cuda.synchronize()
+            t0.record(stream)
+            for _ in range(args.long_steps):
+                lfx()
+            t1.record(stream)
+            torch.cuda.synchronize()
+            ms = t0.elapsed_time(t1) / args.long_steps
+            j = int(res_["exp"][0].item())
+            alg = 2 * LONG_N + 2 * LONG_N * LONG_E * 2
+            longv[name] = {"ms_per_step": ms, "vectors_per_s": LONG_BATCH / (ms * 1e-3), "phi_exp": j,
+                           "algorithmic_bytes_per_vector": alg,
+                           "achieved_GBs": alg * LONG_BATCH / (ms * 1e-3) / 1e9,
+                           "sample": res_["phi"][:3].float().cpu().numpy() * 2.0 ** (-j)}
+            # the input the stored rows represent (exact in FP64)
+            x16_rows[name] = (x16[:3].float().cpu().numpy().astype(np.float64)
+                              * (2.0 ** xk[:3].cpu().numpy().astype(np.float64))[:, None])
+            log("long vectors (n=2^20, E=4), x and phi %s: %.3f ms/step" % (name, ms))
+            del res_, x16
+        del xl_scaled
+        for name in ("bf16", "f16", "bf16_scaled", "f16_scaled", "bf16_x_scaled", "f16_x_scaled"):
             longv[name]["speedup_vs_f32"] = longv["f32"]["ms_per_step"] / longv[name]["ms_per_step"]
         xl_head = xl[:3].cpu().numpy()
         del xl
@@ -575,6 +608,15 @@ def main():
             for name in ("bf16", "f16", "bf16_scaled", "f16_scaled"):
                 ph = longv[name]["sample"].astype(np.float64)
                 longv[name]["max_row_rel_err_vs_oracle"] = float(
+                    (np.linalg.norm(ph - refl, axis=1) / np.linalg.norm(refl, axis=1)).max())
+            for name, xr in x16_rows.items():
+                # against the oracle on the input the 16-bit rows represent,
+                # and against the oracle on the FP32 rows (input rounding included)
+                refx, _, _ = oracle.forward(xr, LONG_E, seed, LONG_SIGMA)
+                ph = longv[name]["sample"].astype(np.float64)
+                longv[name]["max_row_rel_err_vs_oracle"] = float(
+                    (np.linalg.norm(ph - refx, axis=1) / np.linalg.norm(refx, axis=1)).max())
+                longv[name]["max_row_rel_err_vs_oracle_fp32_x"] = float(
                     (np.linalg.norm(ph - refl, axis=1) / np.linalg.norm(refl, axis=1)).max())
     if not args.no_cpu_baseline and bwd_check is not None:
         bx, bd, bdx = bwd_check

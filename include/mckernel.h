@@ -163,10 +163,10 @@ mck_status mck_fastfood_forward_t(const void* x, mck_dtype x_type, int64_t batch
  * The feature map with per-row power-of-2 scaling of its storage (the 16-bit
  * forms of the long-vector and reduced-precision configurations), n <=
  * MCK_MAX_N_LONG, storage pairs as in mck_fastfood_forward_t:
- *   x_exp   (device, batch int8, nullable; n <= MCK_MAX_N): row r of the
- *           input is the stored row times 2^x_exp[r]; the product must be
- *           finite in FP32.  The scaling is exact, so a 16-bit x can carry
- *           rows of any magnitude.
+ *   x_exp   (device, batch int8, nullable): row r of the input is the
+ *           stored row times 2^x_exp[r]; the product must be finite in
+ *           FP32.  The scaling is exact, so a 16-bit x can carry rows of
+ *           any magnitude.
  *   phi_exp (device, batch int8, nullable, written): row r of phi is the
  *           stored row times 2^-phi_exp[r].  Every feature is bounded by
  *           c = 1/sqrt(nE) (equation "mcfeatures" with the normalisation of

@@ -144,7 +144,7 @@ def forward_scaled(x: torch.Tensor, E: int, seed: int = PAPER_SEED, sigma: float
     """phi with per-row power-of-2 scaling of its storage: x (float32,
     bfloat16 or float16) holds rows x_true[r] / 2^x_exp[r] (x_exp: int8 per
     row, or None); returns (phi_stored, phi_exp) with phi = phi_stored *
-    2^-phi_exp[r] per row (n <= 2^15)."""
+    2^-phi_exp[r] per row."""
     if x.dtype not in _DTYPES:
         raise TypeError("x must be float32, bfloat16 or float16")
     _check(x, "x", x.dtype)

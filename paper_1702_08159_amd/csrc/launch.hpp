@@ -68,12 +68,13 @@ hipError_t launch_forward_t(int M, int P, int waves, bool vec, int xt, int yt, c
 
 // n = 2^M > 2^15 (longn.hip): in-place H on 16-byte aligned rows, and the
 // feature map through FP32 scratch rows u, w (batch x n each).  Sh for such
-// plans comes from launch_sh (S / 2 pi from the FP64 S).
+// plans comes from launch_sh (S / 2 pi from the FP64 S).  xexp (nullable):
+// per-row power-of-2 exponents of a scaled x.
 hipError_t launch_fwht_long(int M, float* data, int64_t batch, bool vec, hipStream_t s);
 hipError_t launch_forward_long(int M, bool vec, int xt, int yt, const void* x, int64_t batch, int d, int64_t E,
                                const float* B, const uint32_t* packA, const uint16_t* dstB, const int32_t* pdelta,
                                const float* Gx, const float* Sh, float cs, void* phi, float* u, float* w,
-                               hipStream_t s);
+                               hipStream_t s, const int8_t* xexp = nullptr);
 // Pi (destination i takes source perm[i]) of each expansion as an exchange
 // between the C = n / 2^15 chunks of 2^15 elements.  The exchange buffer T
 // holds, for each destination chunk co, the elements it receives, grouped

@@ -268,11 +268,13 @@ __global__ void __launch_bounds__(kColThreads)
 
 // The first column pass of an expansion: the same butterflies on
 // B o xhat, read from x (rows of d elements of type XT; past d reads zero
-// through the range check) and written to out (rows of n floats).
+// through the range check) and written to out (rows of n floats).  xexp
+// (nullable): row r of x is the stored row times 2^xexp[r], applied exactly
+// to the widened values.
 template <int B, int XT, bool VEC>
 __global__ void __launch_bounds__(kColThreads)
     k_cols_x(float* __restrict__ out, const void* __restrict__ x, int d, const float* __restrict__ Bv, int64_t rows,
-             int64_t n, int s, int64_t blocks_per_row)
+             int64_t n, int s, int64_t blocks_per_row, const int8_t* __restrict__ xexp)
 {
     constexpr int L = 1 << B;
     constexpr uint32_t XB = elem_bytes<XT>();
@@ -286,12 +288,16 @@ __global__ void __launch_bounds__(kColThreads)
     const rsrc_t rx = make_rsrc(static_cast<const char*>(x) + r * d * XB, (uint32_t)d * XB);
     const rsrc_t rb = make_rsrc(Bv, (uint32_t)(n * 4));
     const rsrc_t ro = make_rsrc(out + r * n, (uint32_t)(n * 4));
+    const float xs = xexp != nullptr ? __builtin_ldexpf(1.f, (int)xexp[r]) : 1.f;
     float v[L][4];
 #pragma unroll
     for (int k = 0; k < L; ++k) {
         const uint32_t i = (uint32_t)(base + ((int64_t)k << s));
         float bq[4];
         bload4(bq, rb, 4u * i, 0u);
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            bq[m] *= xs;
         if constexpr (VEC && XT == kF32) {
             bload4<2>(v[k], rx, 4u * i, 0u);
         } else if constexpr (VEC) {
@@ -329,12 +335,12 @@ __global__ void __launch_bounds__(kColThreads)
 
 template <int XT, bool VEC>
 hipError_t col_pass_x(int B, float* out, const void* x, int d, const float* Bv, int64_t rows, int64_t n, int s,
-                      hipStream_t st)
+                      const int8_t* xexp, hipStream_t st)
 {
     const int64_t groups = (n >> B) / 4;
     const int64_t bpr = (groups + kColThreads - 1) / kColThreads;
     const dim3 grid((unsigned)(rows * bpr)), blk(kColThreads);
-#define MCK_COLX_ARGS out, x, d, Bv, rows, n, s, bpr
+#define MCK_COLX_ARGS out, x, d, Bv, rows, n, s, bpr, xexp
     switch (B) {
     case 1: k_cols_x<1, XT, VEC><<<grid, blk, 0, st>>>(MCK_COLX_ARGS); break;
     case 2: k_cols_x<2, XT, VEC><<<grid, blk, 0, st>>>(MCK_COLX_ARGS); break;
@@ -372,7 +378,8 @@ hipError_t col_pass(int B, float* data, int64_t rows, int64_t n, int s, const fl
 // xhat from x; with epi the last one carries the feature epilogue.
 template <int XT, bool VEC, int YT>
 hipError_t col_passes(int M, float* data, int64_t rows, const void* x, int d, const float* Bv, bool epi,
-                      const float* Sh, float cs, int e, int E, void* phi, hipStream_t st)
+                      const float* Sh, float cs, int e, int E, void* phi, hipStream_t st,
+                      const int8_t* xexp = nullptr)
 {
     const int64_t n = int64_t(1) << M;
     int s = kRowM;
@@ -383,7 +390,7 @@ hipError_t col_passes(int M, float* data, int64_t rows, const void* x, int d, co
         const bool last = rem == B;
         hipError_t err;
         if (first && x != nullptr)
-            err = col_pass_x<XT, VEC>(B, data, x, d, Bv, rows, n, s, st);
+            err = col_pass_x<XT, VEC>(B, data, x, d, Bv, rows, n, s, xexp, st);
         else if (epi && last)
             err = col_pass<true, YT>(B, data, rows, n, s, Sh, cs, e, E, phi, st);
         else
@@ -427,14 +434,15 @@ hipError_t row_pass(bool vec, const RowArgs& a, hipStream_t st)
 template <int XT, int YT>
 hipError_t forward_long(int M, bool vec, const void* x, int64_t batch, int d, int64_t E, const float* B,
                         const uint32_t* packA, const uint16_t* dstB, const int32_t* pdelta, const float* Gx,
-                        const float* Sh, float cs, void* phi, float* u, float* w, hipStream_t st)
+                        const float* Sh, float cs, void* phi, float* u, float* w, hipStream_t st,
+                        const int8_t* xexp)
 {
     const int64_t n = int64_t(1) << M, C = n >> kRowM;
     for (int64_t e = 0; e < E; ++e) {
         hipError_t err = vec ? col_passes<XT, true, kF32>(M, u, batch, x, d, B + e * n, false, nullptr, 0.f, 0, 0,
-                                                          nullptr, st)
+                                                          nullptr, st, xexp)
                              : col_passes<XT, false, kF32>(M, u, batch, x, d, B + e * n, false, nullptr, 0.f, 0, 0,
-                                                           nullptr, st);
+                                                           nullptr, st, xexp);
         const RowArgs a{w, u, batch, C, nullptr, packA + e * n, pdelta + e * C * C, nullptr};
         if (err == hipSuccess)
             err = row_pass<kInRow, kOutBucket>(true, a, st);
@@ -570,11 +578,11 @@ hipError_t launch_fwht_long(int M, float* data, int64_t batch, bool vec, hipStre
 hipError_t launch_forward_long(int M, bool vec, int xt, int yt, const void* x, int64_t batch, int d, int64_t E,
                                const float* B, const uint32_t* packA, const uint16_t* dstB, const int32_t* pdelta,
                                const float* Gx, const float* Sh, float cs, void* phi, float* u, float* w,
-                               hipStream_t s)
+                               hipStream_t s, const int8_t* xexp)
 {
     if (M <= kRowM || M > 24)
         return hipErrorInvalidValue;
-#define MCK_FL_ARGS M, vec, x, batch, d, E, B, packA, dstB, pdelta, Gx, Sh, cs, phi, u, w, s
+#define MCK_FL_ARGS M, vec, x, batch, d, E, B, packA, dstB, pdelta, Gx, Sh, cs, phi, u, w, s, xexp
     if (xt == kF32 && yt == kF32)
         return forward_long<kF32, kF32>(MCK_FL_ARGS);
     if (xt == kF32 && yt == kBF16)

@@ -621,7 +621,8 @@ static int64_t long_rows_per(int64_t batch, int64_t n)
 // Launches of the long-vector feature map with caller-provided scratch u
 // (2 x long_rows_per(batch, n) x n floats).
 static mck_status forward_long_launch(const Plan* p, const void* x, int xt, int64_t batch, int64_t d, int64_t n,
-                                      int64_t E, void* phi, int yt, float* u, hipStream_t s, float cs)
+                                      int64_t E, void* phi, int yt, float* u, hipStream_t s, float cs,
+                                      const int8_t* xexp = nullptr)
 {
     const int64_t xb = xt == 0 ? 4 : 2, yb = yt == 0 ? 4 : 2;
     const int64_t row_phi = 2 * n * E * yb;
@@ -634,7 +635,8 @@ static mck_status forward_long_launch(const Plan* p, const void* x, int xt, int6
         const int64_t rows = batch - r0 < rows_per ? batch - r0 : rows_per;
         err = mck::launch_forward_long(log2i(n), vec, xt, yt, static_cast<const char*>(x) + r0 * d * xb, rows,
                                        (int)d, E, p->B, p->packA, p->dstB, p->pdelta, p->Gx, p->Sh, cs,
-                                       static_cast<char*>(phi) + r0 * row_phi, u, w, s);
+                                       static_cast<char*>(phi) + r0 * row_phi, u, w, s,
+                                       xexp ? xexp + r0 : nullptr);
     }
     return err == hipSuccess ? MCK_OK : hip_fail(err, "long-vector forward launch");
 }
@@ -644,7 +646,7 @@ static mck_status forward_long_launch(const Plan* p, const void* x, int xt, int6
 // in equal chunks of at most 2^27 floats per FP32 scratch buffer (u, w,
 // stream-ordered).
 static mck_status forward_long(const Plan* p, const void* x, int xt, int64_t batch, int64_t d, int64_t n, int64_t E,
-                               void* phi, int yt, hipStream_t s, float cs)
+                               void* phi, int yt, hipStream_t s, float cs, const int8_t* xexp = nullptr)
 {
     const int64_t yb = yt == 0 ? 4 : 2;
     if (2 * n * E * yb > (int64_t(1) << 31) - 4096)
@@ -656,7 +658,7 @@ static mck_status forward_long(const Plan* p, const void* x, int xt, int64_t bat
     hipError_t err = hipMallocAsync(reinterpret_cast<void**>(&u), (size_t)(2 * rows_per * n) * sizeof(float), s);
     if (err != hipSuccess)
         return fail(MCK_ERR_NO_MEMORY, std::string("long-vector scratch: ") + hipGetErrorString(err));
-    const mck_status st = forward_long_launch(p, x, xt, batch, d, n, E, phi, yt, u, s, cs);
+    const mck_status st = forward_long_launch(p, x, xt, batch, d, n, E, phi, yt, u, s, cs, xexp);
     (void)hipFreeAsync(u, s);
     return st;
 }
@@ -877,8 +879,6 @@ mck_status mck_fastfood_forward_scaled(const void* x, mck_dtype x_type, const in
     mck_status st = check_common(batch, d, E, &n);
     if (st != MCK_OK)
         return st;
-    if (n > MCK_MAX_N && x_exp != nullptr)
-        return fail(MCK_ERR_UNSUPPORTED, "per-row x exponents are supported for n <= MCK_MAX_N");
     st = check_sigma(sigma);
     if (st != MCK_OK)
         return st;
@@ -904,7 +904,7 @@ mck_status mck_fastfood_forward_scaled(const void* x, mck_dtype x_type, const in
         ++j;
     const float cs = std::ldexp(feature_scale(n, E), j);
     if (n > MCK_MAX_N) {
-        st = forward_long(p.get(), x, xt, batch, d, n, E, phi, yt, s, cs);
+        st = forward_long(p.get(), x, xt, batch, d, n, E, phi, yt, s, cs, x_exp);
         if (st == MCK_OK && phi_exp != nullptr) {
             const hipError_t ferr = mck::launch_fill_i8(phi_exp, batch, (int8_t)j, s);
             if (ferr != hipSuccess)

@@ -164,7 +164,7 @@ def test_scaled_forward_validation_without_gpu(lib):
     # unknown storage type, unsupported pair, n too large, NULL x; empty batch is a no-op
     assert _st(lib, sc, p16, 3, null, 2, 8, 1, 1, 1.0, 0, p16, 0, null, null) == 1
     assert _st(lib, sc, p16, 1, null, 2, 8, 1, 1, 1.0, 0, p16, 2, null, null) == 2
-    assert _st(lib, sc, p16, 0, p16, 2, 40000, 1, 1, 1.0, 0, p16, 0, null, null) == 2  # x exponents, n > 2^15
+    assert _st(lib, sc, p16, 0, p16, 2, (1 << 24) + 1, 1, 1, 1.0, 0, p16, 0, null, null) == 2  # n too large
     assert _st(lib, sc, null, 0, null, 2, 8, 1, 1, 1.0, 0, p16, 0, null, null) == 1
     assert _st(lib, sc, null, 0, null, 0, 8, 1, 1, 1.0, 0, null, 0, null, null) == 0
 

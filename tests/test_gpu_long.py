@@ -142,3 +142,59 @@ def test_long_single_pass_only_calls_refuse(mk):
         mk.project(x, 1, 1, 1.0)
     with pytest.raises(mk.MckError):
         mk.backward(x, torch.zeros((2, 2 * 65536), device="cuda"), 1, 1, 1.0)
+
+
+def scale_rows(x, k):
+    """Stored 16-bit-ready rows x 2^-k (exact), k per row."""
+    return (x.astype(np.float64) * (2.0 ** -k.astype(np.float64))[:, None]).astype(np.float32)
+
+
+@pytest.mark.parametrize("name", ["bfloat16", "float16"])
+def test_long_vector_scaled_16bit_x_and_phi(mk, orc, name):
+    # the long-vector reduced-precision configuration as stated: batch 64 of
+    # N(0,1) rows, n = 2^20, E = 4, sigma = sqrt(n), x stored in 16 bits with
+    # a per-row power-of-2 exponent (stored row max in [0.5, 1)), phi in 16
+    # bits times 2^phi_exp.  Sampled rows against the oracle on the input
+    # the stored values represent, and bit for bit the rounding of 2^j times
+    # the FP32 map of that input.
+    import torch
+
+    dt = getattr(torch, name)
+    n, E, batch = 1 << 20, 4, 64
+    sigma = float(np.sqrt(n))
+    x = workloads.normal(batch, n, seed=20)
+    k = np.ceil(np.log2(np.abs(x).max(axis=1))).astype(np.int8)
+    x16 = torch.from_numpy(scale_rows(x, k)).cuda().to(dt)
+    ke = torch.from_numpy(k).cuda()
+    phi, pexp = mk.forward_scaled(x16, E, workloads.FASTFOOD_SEED, sigma, x_exp=ke, out_dtype=dt)
+    j = int(pexp[0].item())
+    assert torch.equal(pexp, torch.full((batch,), j, dtype=torch.int8, device="cuda"))
+    rows = [0, 31, 63]
+    x_true = x16[rows].float().cpu().numpy().astype(np.float64) * (2.0 ** k[rows].astype(np.float64))[:, None]
+    ref, _, _ = orc.forward(x_true, E, workloads.FASTFOOD_SEED, sigma)
+    got = phi[rows].float().cpu().numpy().astype(np.float64) * 2.0 ** (-j)
+    tol = {"bfloat16": 2.5e-3, "float16": 3e-4}[name]
+    err = rowwise_rel(got, ref).max()
+    print("%s x and phi, per-row exponents: max row error %.3e" % (name, err))
+    assert err <= tol
+    phi32 = mk.forward(torch.from_numpy(x_true.astype(np.float32)).cuda(), E, workloads.FASTFOOD_SEED, sigma)
+    assert torch.equal((phi32.double() * 2.0 ** j).float().to(dt), phi[rows])
+
+
+def test_long_vector_x_exponents_of_every_size(mk, orc):
+    # rows of very different magnitude (2^-6 .. 2^7 times N(0,1)) carried in
+    # half precision with their exponents, at a ragged d past 2^16
+    import torch
+
+    d, E, batch = 70001, 2, 8
+    n = mk.padded_dim(d)
+    sigma = float(np.sqrt(n))
+    mag = np.array([-6, -2, 0, 3, 7, -1, 5, 1], np.int8)
+    x = workloads.normal(batch, d, seed=31) * (2.0 ** mag.astype(np.float64))[:, None].astype(np.float32)
+    k = np.ceil(np.log2(np.abs(x).max(axis=1))).astype(np.int8)
+    x16 = torch.from_numpy(scale_rows(x, k)).cuda().to(torch.float16)
+    phi, pexp = mk.forward_scaled(x16, E, 5, sigma, x_exp=torch.from_numpy(k).cuda(), out_dtype=torch.float16)
+    j = int(pexp[0].item())
+    x_true = x16.float().cpu().numpy().astype(np.float64) * (2.0 ** k.astype(np.float64))[:, None]
+    ref, _, _ = orc.forward(x_true, E, 5, sigma)
+    assert rowwise_rel(phi.float().cpu().numpy().astype(np.float64) * 2.0 ** (-j), ref).max() <= 3e-4
