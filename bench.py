@@ -20,6 +20,7 @@ work is skipped inside a timed region.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import math
@@ -378,6 +379,7 @@ def main():
             for _ in range(3):  # plans built and cached; the first calls after that run slower
                 fn()
             torch.cuda.synchronize()
+            gc.collect()  # host timing: no collector pause left pending from the setup above
             t0.record(stream)
             for _ in range(10):
                 fn()

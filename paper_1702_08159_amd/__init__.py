@@ -164,27 +164,45 @@ def forward_scaled(x: torch.Tensor, E: int, seed: int = PAPER_SEED, sigma: float
 
 
 def _instances(maps, outs):
-    """mck_instance array, the phi list and the device of a batched call."""
-    arr = (_lib.Instance * len(maps))()
-    arr = (_lib.Instance * len(maps))()
+    """mck_instance array, the phi list and the device of a batched call.
+    Fields are written into one preallocated ctypes array (no per-map ctypes
+    temporaries), so marshalling many small maps stays cheap."""
+    count = len(maps)
+    arr = (_lib.Instance * count)()
     res = []
-    dev = None
-    for k, m in enumerate(maps):
-        x, E, seed, sigma = m[:4]
+    dev = maps[0][0].device if count else None
+    f32 = torch.float32
+    for k in range(count):
+        m = maps[k]
+        x, E, seed, sigma = m[0], m[1], m[2], m[3]
         mt = m[4] if len(m) > 4 else 0
-        _check(x, "x")
-        dev = dev or x.device
+        if not isinstance(x, torch.Tensor) or not x.is_cuda or x.dtype != f32 or not x.is_contiguous():
+            _check(x, "x")  # raises with the reason
         if x.device != dev:
             raise ValueError("all maps must be on one device")
-        batch, d = _rows(x)
-        n = padded_dim(d)
-        if n == 0:
+        if x.dim() != 2:
+            raise ValueError("x must be 2-D (batch x d)")
+        batch, d = x.shape
+        if not 1 <= d <= 1 << 24:
             raise ValueError("d out of range")
-        phi = outs[k] if outs is not None else torch.empty((batch, 2 * n * E), dtype=torch.float32, device=dev)
-        _check(phi, "phi")
-        if phi.shape != (batch, 2 * n * E):
-            raise ValueError("phi must be batch x 2nE")
-        arr[k] = _lib.Instance(_ptr(x), batch, d, E, seed & 0xFFFFFFFF, float(sigma), calibration(mt), _ptr(phi))
+        n = max(2, 1 << (d - 1).bit_length())
+        if outs is not None:
+            phi = outs[k]
+            if not isinstance(phi, torch.Tensor) or not phi.is_cuda or phi.dtype != f32 or not phi.is_contiguous():
+                _check(phi, "phi")
+            if phi.shape != (batch, 2 * n * E):
+                raise ValueError("phi must be batch x 2nE")
+        else:
+            phi = torch.empty((batch, 2 * n * E), dtype=f32, device=dev)
+        q = arr[k]
+        q.x = x.data_ptr()
+        q.batch = batch
+        q.d = d
+        q.E = E
+        q.seed = seed & 0xFFFFFFFF
+        q.sigma = sigma
+        q.calib = MCK_CALIB_RBF if mt == 0 else calibration(mt)
+        q.phi = phi.data_ptr()
         res.append(phi)
     return arr, res, dev
 

@@ -199,6 +199,247 @@ __global__ void __launch_bounds__(RG::BLOCK) k_rows(RowArgs a)
     }
 }
 
+// ------------------------------------------------------------------ n = 2^16 in one block
+// A whole row of n = 2^16 = two 2^15 halves per 1024-lane block: 32 values
+// per lane and half in VGPRs (a lane holds the same positions of both
+// halves, so the butterflies on index bit 15 are register-local), and each
+// half's relayouts through the one 2^15-float LDS buffer in turn.  Per work
+// item (row, expansion):
+//   1. B o xhat (sign words), the bit-15 butterfly, H_{2^15} on each half;
+//   2. Pi through the block's own exchange row in global memory (L2): each
+//      source half leaves grouped by destination half (packA, pdelta), then
+//      every destination half comes back as one contiguous run, scaled by G
+//      in that order (Gx) and placed by dstB in LDS;
+//   3. the bit-15 butterfly, H_{2^15} on each half, S / (2 pi), [cos, sin].
+// Against the multi-pass path this keeps u and w of the row pass and the
+// column passes out of HBM: per item x is read (from L2 after the first
+// expansion), phi written, and the exchange row stays near the CU.  The
+// block's exchange row is written and read by the block alone, so the
+// block barrier orders it (all waves of a block share one CU's caches).
+//
+// Work items: XCD x (blocks b with b % 8 = x, `slots` of them) takes rows
+// x, x + 8, x + 16, ... in groups of 8 rows; within a group the items are
+// ordered expansion-major, so the group's x rows and one expansion's plan
+// words are shared in that XCD's L2.
+struct PairArgs {
+    const void* x;
+    int64_t rows;
+    int d;
+    int E;
+    const uint32_t* Bw;     // sign words [e][h][t]: bit r set where B is -1 at register r of lane t
+    const uint32_t* packA;  // exchange plan of the expansion (C = 2 chunks), launch.hpp
+    const int32_t* pdelta;
+    const uint16_t* dstB;
+    const float* Gx;
+    const float* Sh;
+    float cs;
+    void* phi;
+    float* exch;            // gridDim.x rows of 2^16 floats
+    const int8_t* xexp;     // nullable per-row exponents of x
+    int slots;              // blocks per XCD
+};
+
+constexpr int kPairRows = 8;  // rows per group within an XCD
+
+template <int XT, int YT, bool VEC>
+__global__ void __launch_bounds__(RG::BLOCK, 1) k_forward_pair(PairArgs a)
+{
+    constexpr int M = kRowM, P = kRowP, EPL = RG::EPL, BLOCK = RG::BLOCK, NQ = EPL / 4;
+    constexpr int64_t CH = RG::n, n = 2 * CH;
+    constexpr uint32_t XB = elem_bytes<XT>(), YB = elem_bytes<YT>();
+    __shared__ float lds[RG::LDS_FLOATS];
+    const uint32_t t = threadIdx.x;
+    const uint32_t tb = tpart<M, P, 0>(t);
+    const int xcd = (int)(blockIdx.x % kXcds), slot = (int)(blockIdx.x / kXcds);
+    const int64_t kx = a.rows > xcd ? (a.rows - xcd + kXcds - 1) / kXcds : 0;  // rows of this XCD
+    const int64_t jx = (kx + kPairRows - 1) / kPairRows * kPairRows * a.E;
+    const rsrc_t rex = make_rsrc(a.exch + (int64_t)blockIdx.x * n, (uint32_t)(n * 4));
+    const int64_t nE = n * a.E;
+
+    // work item j -> (row, e); k >= kx marks the empty tail of a row group
+    struct Item {
+        int64_t row;
+        int e;
+        bool live;
+    };
+    auto item = [&](int64_t j) {
+        const int64_t kin = j % kPairRows, q = j / kPairRows;
+        const int64_t k = (q / a.E) * kPairRows + kin;
+        return Item{xcd + (int64_t)kXcds * k, (int)(q % a.E), k < kx};
+    };
+    auto next = [&](int64_t j) {
+        for (j += a.slots; j < jx; j += a.slots)
+            if (item(j).live)
+                break;
+        return j;
+    };
+    auto xrsrc = [&](int64_t row) {
+        return make_rsrc(static_cast<const char*>(a.x) + row * a.d * XB, (uint32_t)(a.d * XB));
+    };
+    // x (lower half) and the sign words of an item, loaded one item ahead:
+    // before the previous item's feature stores, so that their drain (the
+    // vector-memory counter is shared by loads and stores) overlaps the
+    // lower half's first transform instead of stalling it
+    float xl[EPL];
+    uint32_t w0 = 0, w1 = 0;
+    auto prefetch = [&](int64_t j) {
+        const Item it = item(j);
+        bload_row_t<M, P, VEC, XT>(xl, xrsrc(it.row), 0u, a.d, t, true);
+        w0 = a.Bw[(2 * it.e) * BLOCK + t];
+        w1 = a.Bw[(2 * it.e + 1) * BLOCK + t];
+    };
+
+    int64_t j = slot;
+    if (j < jx && !item(j).live)
+        j = next(j);
+    if (j < jx)
+        prefetch(j);
+    for (; j < jx;) {  // uniform over the block
+        const Item it = item(j);
+        const int64_t row = it.row;
+        const int e = it.e;
+        const int64_t eo = (int64_t)e * n;
+        const float xs = a.xexp != nullptr ? __builtin_ldexpf(1.f, (int)a.xexp[row]) : 1.f;
+
+        // 1. H_{2^16} (B o xhat) = the bit-15 butterfly after H_{2^15} on
+        //    each half (the two factors commute): the lower half first, from
+        //    the prefetched x, then the upper half
+        float lo[EPL], hi[EPL];
+#pragma unroll
+        for (int r = 0; r < EPL; ++r)
+            lo[r] = __uint_as_float(__float_as_uint(xl[r] * xs) ^ ((w0 << (31 - r)) & 0x80000000u));
+        fwht_up<M, P>(lo, lds, lds_lane<M, P>(t));
+        bload_row_t<M, P, VEC, XT>(hi, xrsrc(row), (uint32_t)(CH * XB), a.d - (int)CH, t, true);
+#pragma unroll
+        for (int r = 0; r < EPL; ++r)
+            hi[r] = __uint_as_float(__float_as_uint(hi[r] * xs) ^ ((w1 << (31 - r)) & 0x80000000u));
+        fwht_up<M, P>(hi, lds, lds_lane<M, P>(t));
+#pragma unroll
+        for (int r = 0; r < EPL; ++r) {
+            const float p0 = lo[r], p1 = hi[r];
+            lo[r] = p0 + p1;
+            hi[r] = p0 - p1;
+        }
+
+        // 2. Pi out: each source half, grouped by destination half, to the
+        //    exchange row.  Both halves' plan words are loaded before the
+        //    first exchange store (same counter as above).
+        {
+            uint32_t pk0[EPL], pk1[EPL];
+            lds_put<M, P, RG::GL>(lds, lds_lane<M, P>(t), lo);
+            const rsrc_t ra = make_rsrc(a.packA + eo, (uint32_t)(n * 4));
+#pragma unroll
+            for (int jj = 0; jj < NQ; ++jj) {
+                bload4u(&pk0[4 * jj], ra, 16u * (jj * BLOCK + t), 0u);
+                bload4u(&pk1[4 * jj], ra, 16u * (jj * BLOCK + t), (uint32_t)(CH * 4));
+            }
+            auto send = [&](const uint32_t (&pk)[EPL], int h) {
+                const int32_t d0 = a.pdelta[e * 4 + 2 * h], d1 = a.pdelta[e * 4 + 2 * h + 1];
+#pragma unroll
+                for (int r = 0; r < EPL; ++r) {
+                    const int32_t qq = 4 * ((r / 4) * BLOCK + (int)t) + (r % 4);
+                    const int32_t pos = qq + (((pk[r] >> kRowM) & 1u) ? d1 : d0);
+                    bstore1(rex, 4u * (uint32_t)pos, 0u, lds[phys<P>(pk[r] & 0x7fffu)]);
+                }
+            };
+            __syncthreads();
+            send(pk0, 0);
+            __syncthreads();
+            lds_put<M, P, RG::GL>(lds, lds_lane<M, P>(t), hi);
+            __syncthreads();
+            send(pk1, 1);
+        }
+        __syncthreads();  // the whole exchange row is written (and visible to the block)
+
+        // 3. Pi in: each destination half in the gather layout, G applied
+        auto recv = [&](float (&v)[EPL], int co) {
+            const rsrc_t rg = make_rsrc(a.Gx + eo + co * CH, (uint32_t)(CH * 4));
+            const rsrc_t rd = make_rsrc(a.dstB + eo + co * CH, (uint32_t)(CH * 2));
+#pragma unroll
+            for (int jj = 0; jj < NQ; ++jj) {
+                float tv[4], gx[4];
+                bload4(tv, rex, 16u * (jj * BLOCK + t), (uint32_t)(co * CH * 4));
+                bload4(gx, rg, 16u * (jj * BLOCK + t), 0u);
+                const u32x2_t di =
+                    __builtin_bit_cast(u32x2_t, __builtin_amdgcn_raw_buffer_load_b64(rd, (int)(8u * (jj * BLOCK + t)), 0, 0));
+                lds[phys<P>(di.x & 0x7fffu)] = tv[0] * gx[0];
+                lds[phys<P>((di.x >> 16) & 0x7fffu)] = tv[1] * gx[1];
+                lds[phys<P>(di.y & 0x7fffu)] = tv[2] * gx[2];
+                lds[phys<P>((di.y >> 16) & 0x7fffu)] = tv[3] * gx[3];
+            }
+            __syncthreads();
+            lds_get<M, P, RG::GL>(lds, lds_lane<M, P>(t), v);
+            __syncthreads();
+        };
+        recv(lo, 0);
+        recv(hi, 1);
+
+        // 4. H_{2^16} G Pi v1: the bit-15 butterfly, H_{2^15} on each half;
+        //    z in revolutions (S / 2 pi) for both halves before any store
+#pragma unroll
+        for (int r = 0; r < EPL; ++r) {
+            const float p0 = lo[r], p1 = hi[r];
+            lo[r] = p0 + p1;
+            hi[r] = p0 - p1;
+        }
+        fwht_down<M, P>(lo, lds, lds_lane<M, P>(t));
+        fwht_down<M, P>(hi, lds, lds_lane<M, P>(t));
+        {
+            const rsrc_t rs = make_rsrc(a.Sh + eo, (uint32_t)(n * 4));
+            float sx[EPL];
+            bload_coal<M, P>(sx, rs, 0u, t);
+#pragma unroll
+            for (int r = 0; r < EPL; ++r)
+                lo[r] *= sx[r];
+            bload_coal<M, P>(sx, rs, (uint32_t)(CH * 4), t);
+#pragma unroll
+            for (int r = 0; r < EPL; ++r)
+                hi[r] *= sx[r];
+        }
+        const int64_t jn = next(j);
+        if (jn < jx)
+            prefetch(jn);
+
+        // 5. c cos z, c sin z
+        const rsrc_t ry = make_rsrc(static_cast<char*>(a.phi) + row * 2 * nE * YB, (uint32_t)(2 * nE * YB));
+        auto features = [&](const float (&v)[EPL], int h) {
+            const uint32_t yc = YB * (uint32_t)(eo + h * CH + tb), ysn = yc + YB * (uint32_t)nE;
+#pragma unroll
+            for (int jj = 0; jj < EPL / 4; ++jj) {
+                float c4[4], s4[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+                    cossin_rev(v[4 * jj + m], a.cs, c4[m], s4[m]);
+                const uint32_t so = YB * rpart(M, P, 0, 4 * jj);
+                bstore_quad<YT>(ry, yc + so, c4[0], c4[1], c4[2], c4[3]);
+                bstore_quad<YT>(ry, ysn + so, s4[0], s4[1], s4[2], s4[3]);
+            }
+        };
+        features(lo, 0);
+        features(hi, 1);
+        j = jn;
+    }
+}
+
+// Sign words of B for k_forward_pair: word (e, h, t) has bit r set where
+// B_e is -1 at element h 2^15 + (the index register r of lane t holds in
+// the coalesced layout of the 2^15 engine).
+__global__ void k_pair_signs(const float* __restrict__ B, int64_t E, uint32_t* __restrict__ Bw)
+{
+    constexpr int M = kRowM, P = kRowP, EPL = RG::EPL, BLOCK = RG::BLOCK;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // (e, h, t)
+    if (i >= E * 2 * BLOCK)
+        return;
+    const uint32_t t = (uint32_t)(i % BLOCK);
+    const int64_t eh = i / BLOCK;  // 2 e + h
+    const float* src = B + (eh / 2) * 2 * RG::n + (eh % 2) * RG::n;
+    const uint32_t tb = tpart<M, P, 0>(t);
+    uint32_t w = 0;
+    for (int r = 0; r < EPL; ++r)
+        w |= (src[tb | rpart(M, P, 0, r)] < 0.f ? 1u : 0u) << r;
+    Bw[i] = w;
+}
+
 // Sh = S / (2 pi) (S in revolutions), from the FP64 S.
 __global__ void k_sh(const double* __restrict__ S64, float* __restrict__ Sh, int64_t count)
 {
@@ -594,6 +835,57 @@ hipError_t launch_forward_long(int M, bool vec, int xt, int yt, const void* x, i
     if (xt == kF16 && yt == kF16)
         return forward_long<kF16, kF16>(MCK_FL_ARGS);
 #undef MCK_FL_ARGS
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_pair_signs(const float* B, int64_t E, uint32_t* Bw, hipStream_t s)
+{
+    const int64_t total = E * 2 * RG::BLOCK;
+    k_pair_signs<<<dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s>>>(B, E, Bw);
+    return hipGetLastError();
+}
+
+int64_t pair_blocks(int64_t rows, int64_t E, int cus)
+{
+    // one block per CU (the LDS holds one), all XCDs equally; never more
+    // slots per XCD than that XCD has work items
+    int64_t per_xcd = cus / kXcds;
+    per_xcd = per_xcd < 1 ? 1 : per_xcd;
+    const int64_t items = (rows + kXcds - 1) / kXcds * E;
+    if (items < per_xcd)
+        per_xcd = items < 1 ? 1 : items;
+    return per_xcd * kXcds;
+}
+
+hipError_t launch_forward_pair(bool vec, int xt, int yt, const void* x, int64_t batch, int d, int64_t E,
+                               const uint32_t* Bw, const uint32_t* packA, const uint16_t* dstB,
+                               const int32_t* pdelta, const float* Gx, const float* Sh, float cs, void* phi,
+                               float* exch, int64_t blocks, hipStream_t s, const int8_t* xexp)
+{
+    if (blocks % kXcds != 0 || blocks < kXcds)
+        return hipErrorInvalidValue;
+    const PairArgs a{x, batch, d, (int)E, Bw, packA, pdelta, dstB, Gx, Sh, cs, phi, exch, xexp,
+                     (int)(blocks / kXcds)};
+    const dim3 grid((unsigned)blocks), blk(RG::BLOCK);
+#define MCK_PAIR(XT_, YT_)                                                                                      \
+    do {                                                                                                       \
+        if (vec)                                                                                               \
+            k_forward_pair<XT_, YT_, true><<<grid, blk, 0, s>>>(a);                                            \
+        else                                                                                                   \
+            k_forward_pair<XT_, YT_, false><<<grid, blk, 0, s>>>(a);                                           \
+        return hipGetLastError();                                                                              \
+    } while (0)
+    if (xt == kF32 && yt == kF32)
+        MCK_PAIR(kF32, kF32);
+    if (xt == kF32 && yt == kBF16)
+        MCK_PAIR(kF32, kBF16);
+    if (xt == kF32 && yt == kF16)
+        MCK_PAIR(kF32, kF16);
+    if (xt == kBF16 && yt == kBF16)
+        MCK_PAIR(kBF16, kBF16);
+    if (xt == kF16 && yt == kF16)
+        MCK_PAIR(kF16, kF16);
+#undef MCK_PAIR
     return hipErrorInvalidValue;
 }
 

@@ -171,6 +171,7 @@ struct Plan {
     int32_t* pdelta = nullptr;
     float* Gx = nullptr;
     int32_t* bscratch = nullptr;  // build scratch
+    uint32_t* Bw = nullptr;       // n = 2^16: sign words of B for the one-block row kernel
 };
 
 std::mutex g_mutex;
@@ -230,12 +231,13 @@ mck_status get_plan(uint32_t seed, int64_t n, int64_t E, double sigma, int calib
     const size_t ecc = (size_t)E * C * C * 4;
     const int M = log2i(n);
     const bool two = n <= MCK_MAX_N && mck::fwd_split_ok(M, alt_split(M));
-    size_t off[18], total = 0;
-    const size_t sz[18] = {en * 4, en * 4, en * 4, en * 8, en * 4, (size_t)E * 8,
+    const bool pair = n == 2 * MCK_MAX_N;
+    size_t off[19], total = 0;
+    const size_t sz[19] = {en * 4, en * 4, en * 4, en * 8, en * 4, (size_t)E * 8,
                            (size_t)gf * E * 4, en * 4, (size_t)gb * E * 4, en * 4, en * 4,
                            C ? en * 4 : 0, C ? en * 2 : 0, ecc, 3 * ecc + (size_t)E * C * 8, C ? en * 4 : 0,
-                           two ? (size_t)gf * E * 4 : 0, two ? en * 4 : 0};
-    for (int i = 0; i < 18; ++i) {
+                           two ? (size_t)gf * E * 4 : 0, two ? en * 4 : 0, pair ? en / 8 : 0};
+    for (int i = 0; i < 19; ++i) {
         off[i] = total;
         total += align_up(sz[i]);
     }
@@ -270,6 +272,8 @@ mck_status get_plan(uint32_t seed, int64_t n, int64_t E, double sigma, int calib
         p.goffF2 = reinterpret_cast<uint32_t*>(b + off[16]);
         p.GsF2 = reinterpret_cast<float*>(b + off[17]);
     }
+    if (pair)
+        p.Bw = reinterpret_cast<uint32_t*>(b + off[18]);
     int matern_t = 0;
     {
         const mck_status cst = check_calib(calib, n, &matern_t);
@@ -287,6 +291,8 @@ mck_status get_plan(uint32_t seed, int64_t n, int64_t E, double sigma, int calib
         err = mck::launch_derive_fwd(M, alt_split(M), E, p.perm, p.G, p.B, p.goffF2, p.GsF2, stream);
     if (err == hipSuccess && n > MCK_MAX_N)
         err = mck::launch_buckets(log2i(n), E, p.perm, p.G, p.packA, p.dstB, p.pdelta, p.Gx, p.bscratch, stream);
+    if (err == hipSuccess && pair)
+        err = mck::launch_pair_signs(p.B, E, p.Bw, stream);
     if (err == hipSuccess)
         err = hipStreamSynchronize(stream);  // the plan may be used from other streams next
     if (err != hipSuccess) {
@@ -606,11 +612,12 @@ mck_status mck_fastfood_params(uint32_t seed, int64_t n, int64_t E, double sigma
 }
 
 // Feature map for n > MCK_MAX_N.  The kernels address phi, x and the
-// scratch per row, so only a row of phi must stay below 2^31 bytes; rows go
-// in equal chunks of at most 2^27 floats per FP32 scratch buffer (u, w,
-// stream-ordered).
-// Rows per launch of the long-vector path (the FP32 scratch rows u, w hold
-// at most 2^27 floats each).
+// scratch per row, so only a row of phi must stay below 2^31 bytes.
+// n = 2^16 takes the one-block row kernel (k_forward_pair): one exchange row
+// of n floats per block.  Longer rows take the multi-pass path, in equal
+// chunks of rows through two FP32 scratch buffers u, w of at most 2^27
+// floats each.
+// Rows per launch of the multi-pass path.
 static int64_t long_rows_per(int64_t batch, int64_t n)
 {
     const int64_t max_rows = ((int64_t)1 << 27) / n;
@@ -618,19 +625,54 @@ static int64_t long_rows_per(int64_t batch, int64_t n)
     return (batch + nchunks - 1) / nchunks;
 }
 
+// Compute units of the current device (cached per device).
+static int device_cus()
+{
+    static std::mutex mu;
+    static std::map<int, int> cus;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return 256;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cus.find(dev);
+    if (it != cus.end())
+        return it->second;
+    int c = 0;
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c < 8)
+        c = 256;
+    cus[dev] = c;
+    return c;
+}
+
+// Blocks of the one-block row kernel for n = 2^16 (a multiple of 8).
+static int64_t pair_blocks(int64_t batch, int64_t E) { return mck::pair_blocks(batch, E, device_cus()); }
+
+// Scratch floats a long-vector feature map needs.
+static int64_t long_scratch_floats(int64_t batch, int64_t n, int64_t E)
+{
+    if (n == 2 * MCK_MAX_N)
+        return pair_blocks(batch, E) * n;
+    return 2 * long_rows_per(batch, n) * n;
+}
+
 // Launches of the long-vector feature map with caller-provided scratch u
-// (2 x long_rows_per(batch, n) x n floats).
+// (long_scratch_floats(batch, n, E) floats).
 static mck_status forward_long_launch(const Plan* p, const void* x, int xt, int64_t batch, int64_t d, int64_t n,
                                       int64_t E, void* phi, int yt, float* u, hipStream_t s, float cs,
                                       const int8_t* xexp = nullptr)
 {
     const int64_t xb = xt == 0 ? 4 : 2, yb = yt == 0 ? 4 : 2;
     const int64_t row_phi = 2 * n * E * yb;
-    const int64_t rows_per = long_rows_per(batch, n);
-    float* w = u + rows_per * n;
     const uintptr_t xa = (uintptr_t)(4 * xb);
     const bool vec = reinterpret_cast<uintptr_t>(x) % xa == 0 && d % 4 == 0;
     hipError_t err = hipSuccess;
+    if (n == 2 * MCK_MAX_N) {
+        err = mck::launch_forward_pair(vec, xt, yt, x, batch, (int)d, E, p->Bw, p->packA, p->dstB, p->pdelta, p->Gx,
+                                       p->Sh, cs, phi, u, pair_blocks(batch, E), s, xexp);
+        return err == hipSuccess ? MCK_OK : hip_fail(err, "long-vector forward launch");
+    }
+    const int64_t rows_per = long_rows_per(batch, n);
+    float* w = u + rows_per * n;
     for (int64_t r0 = 0; r0 < batch && err == hipSuccess; r0 += rows_per) {
         const int64_t rows = batch - r0 < rows_per ? batch - r0 : rows_per;
         err = mck::launch_forward_long(log2i(n), vec, xt, yt, static_cast<const char*>(x) + r0 * d * xb, rows,
@@ -641,10 +683,6 @@ static mck_status forward_long_launch(const Plan* p, const void* x, int xt, int6
     return err == hipSuccess ? MCK_OK : hip_fail(err, "long-vector forward launch");
 }
 
-// Feature map for n > MCK_MAX_N.  The kernels address phi, x and the
-// scratch per row, so only a row of phi must stay below 2^31 bytes; rows go
-// in equal chunks of at most 2^27 floats per FP32 scratch buffer (u, w,
-// stream-ordered).
 static mck_status forward_long(const Plan* p, const void* x, int xt, int64_t batch, int64_t d, int64_t n, int64_t E,
                                void* phi, int yt, hipStream_t s, float cs, const int8_t* xexp = nullptr)
 {
@@ -653,9 +691,9 @@ static mck_status forward_long(const Plan* p, const void* x, int xt, int64_t bat
         return fail(MCK_ERR_UNSUPPORTED, "one row of phi exceeds 2^31 bytes");
     if (batch == 0)
         return MCK_OK;
-    const int64_t rows_per = long_rows_per(batch, n);
     float* u = nullptr;
-    hipError_t err = hipMallocAsync(reinterpret_cast<void**>(&u), (size_t)(2 * rows_per * n) * sizeof(float), s);
+    hipError_t err = hipMallocAsync(reinterpret_cast<void**>(&u),
+                                    (size_t)long_scratch_floats(batch, n, E) * sizeof(float), s);
     if (err != hipSuccess)
         return fail(MCK_ERR_NO_MEMORY, std::string("long-vector scratch: ") + hipGetErrorString(err));
     const mck_status st = forward_long_launch(p, x, xt, batch, d, n, E, phi, yt, u, s, cs, xexp);
@@ -1179,7 +1217,7 @@ mck_status mck_batched_graph_create(const mck_instance* inst, int64_t count, mck
             graph_release(g);
             return fail(MCK_ERR_UNSUPPORTED, "one row of phi exceeds 2^31 bytes");
         }
-        const size_t need = (size_t)(2 * long_rows_per(m.q->batch, m.n) * m.n) * sizeof(float);
+        const size_t need = (size_t)long_scratch_floats(m.q->batch, m.n, m.q->E) * sizeof(float);
         long_bytes = need > long_bytes ? need : long_bytes;
     }
     if (long_bytes > 0) {

@@ -198,3 +198,21 @@ def test_long_vector_x_exponents_of_every_size(mk, orc):
     x_true = x16.float().cpu().numpy().astype(np.float64) * (2.0 ** k.astype(np.float64))[:, None]
     ref, _, _ = orc.forward(x_true, E, 5, sigma)
     assert rowwise_rel(phi.float().cpu().numpy().astype(np.float64) * 2.0 ** (-j), ref).max() <= 3e-4
+
+
+@pytest.mark.parametrize("d,E,batch", [(65536, 5, 37), (50000, 3, 300), (32769, 16, 9), (65533, 1, 1)])
+def test_forward_2_16_one_block_rows(mk, orc, d, E, batch):
+    # n = 2^16 runs the whole row in one block per (row, expansion): many
+    # rows and expansions (several work items per block, partial row groups
+    # per XCD), ragged d, d just past 2^15; sampled rows against the oracle
+    import torch
+
+    n = mk.padded_dim(d)
+    assert n == 65536
+    sigma = float(np.sqrt(n))
+    x = workloads.normal(batch, d, seed=d + batch)
+    phi = mk.forward(torch.from_numpy(x).cuda(), E, 77, sigma)
+    rows = sorted({0, batch // 2, batch - 1, min(8, batch - 1), min(15, batch - 1)})
+    got = phi[rows].cpu().numpy()
+    ref, _, _ = orc.forward(x[rows].astype(np.float64), E, 77, sigma)
+    assert rowwise_rel(got, ref).max() <= 1e-5
