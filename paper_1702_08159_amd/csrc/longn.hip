@@ -22,8 +22,8 @@
 //      c cos, c sin in the storage type of phi.
 // A direct gather u[perm[i]] over the whole row would read one 4-byte value
 // per 64-byte line from L2; the exchange moves every value twice, in full
-// lines.  Row-pass blocks are mapped so that an XCD works on one row at a
-// time.
+// lines.  Row-pass blocks are mapped so that an XCD works on a fixed set of
+// chunks, whose plan words then stay in its L2 across rows.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -57,14 +57,22 @@ struct RowArgs {
 };
 
 // XCD-aware (row slot, chunk) of a row-pass block: blocks are dealt to the
-// 8 XCDs round robin; XCD x takes slots x, x + 8, ... one after another, all
-// chunks of a slot together.
+// 8 XCDs round robin.  With 8 or more chunks, XCD x takes the chunks
+// c = x (mod 8) of every row slot, so the plan words of its C / 8 chunks
+// (the exchange positions, G, the placement: 320 KB per chunk) are read
+// from HBM once and then served by that XCD's L2 for all rows; with fewer
+// chunks every XCD's L2 holds them all.
 __device__ __forceinline__ void slot_chunk(int64_t chunks, int64_t& slot, int64_t& c)
 {
     const int64_t b = blockIdx.x;
-    const int64_t xcd = b % kXcds, q = b / kXcds;
-    slot = (q / chunks) * kXcds + xcd;
-    c = q % chunks;
+    if (chunks >= kXcds) {
+        const int64_t xcd = b % kXcds, q = b / kXcds, per = chunks / kXcds;
+        c = xcd + kXcds * (q % per);
+        slot = q / per;
+    } else {
+        c = b % chunks;
+        slot = b / chunks;
+    }
 }
 
 // One 2^15 chunk c of RB consecutive rows per block: H_{2^15} of each row's
