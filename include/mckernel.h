@@ -429,9 +429,13 @@ mck_status mck_head_backward(const float* phi, const float* dlogits, const float
  * logits (batch x C) is written when non-NULL; W, dW: C x F, 16-byte
  * aligned; C in [1, 16]; batch >= 1.  The gradients are those of the
  * parameters before the update.  One plan derivation serves the forward
- * and the adjoint; scratch (2 batch F floats for phi and dphi, plus
- * partial sums) is allocated on `stream` (stream-ordered).  Every sum has
- * a fixed order: the step is deterministic.
+ * and the adjoint.  For n = 1024 and C <= 10 the head is fused into the
+ * feature-map kernels and phi never reaches device memory: the logits come
+ * out of the forward, and phi is recomputed for dW and dphi; scratch is
+ * batch F floats for dphi plus partial sums.  Otherwise phi and dphi are
+ * materialised (2 batch F floats of scratch).  Scratch is allocated on
+ * `stream` (stream-ordered).  Every sum has a fixed order: the step is
+ * deterministic.
  */
 mck_status mck_fastfood_train_step(const float* x, const int32_t* labels, int64_t batch, int64_t d, int64_t n,
                                    int64_t E, int64_t C, float* W, float* b, float* B, const int32_t* perm, float* G,

@@ -27,6 +27,7 @@ COMMON = ["--offload-arch=" + ARCH, "-O3", "-fPIC", "-std=c++17",
 SOURCES = {
     "kernels.hip": [],
     "head.hip": [],
+    "train.hip": [],
     "forward16.hip": [],
     "longn.hip": [],
     "generator.hip": ["-ffp-contract=off"],

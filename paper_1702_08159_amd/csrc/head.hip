@@ -354,6 +354,14 @@ hipError_t launch_head_logits(const float* phi, const float* W, const float* b, 
     return hipGetLastError();
 }
 
+hipError_t launch_logits_finish(const float* part, const float* b, int64_t slabs, int64_t batch, int C,
+                                float* logits, hipStream_t s)
+{
+    const unsigned blocks = (unsigned)((batch * C + kHeadThreads - 1) / kHeadThreads);
+    k_logits_finish<<<dim3(blocks), dim3(kHeadThreads), 0, s>>>(part, b, slabs, batch, C, logits);
+    return hipGetLastError();
+}
+
 void head_bwd_geometry(int64_t batch, int64_t F, bool need_dW, int64_t* slabs, int64_t* groups, int64_t* rows_per_group)
 {
     const int64_t F4 = F / 4;

@@ -183,5 +183,26 @@ hipError_t launch_head_bwd(const float* phi, const float* dl, const float* W, in
                            int64_t slabs, int64_t groups, int64_t rows_per_group, float* dphi, float* part,
                            hipStream_t s);
 hipError_t launch_sum_groups(const float* part, int64_t groups, int64_t count, float* out, hipStream_t s);
+// logits[r][c] = b[c] (b nullable) + sum over slabs of part[slab][r][c].
+hipError_t launch_logits_finish(const float* part, const float* b, int64_t slabs, int64_t batch, int C,
+                                float* logits, hipStream_t s);
+
+// The training step with the head fused into the feature map (train.hip):
+// n = 1024 and C <= kFusedHeadMaxC, the explicit-parameter forward arrays of
+// register split 4 (goff, Gs) and Sh.  launch_forward_logits writes
+// esplit x batch x C partial logits (summed by launch_logits_finish);
+// launch_head_bwd_fused writes dphi (batch x 2nE) and ranges x C x 2nE
+// partials of dW (summed by launch_sum_groups).
+constexpr int kFusedHeadMaxC = 10;
+bool fused_head_ok(int64_t n, int64_t C);
+int64_t fused_logits_esplit(int64_t batch, int64_t E);
+void fused_bwd_geometry(int64_t batch, int64_t E, int64_t* ranges, int64_t* rows_per_range);
+hipError_t launch_forward_logits(bool vec, const float* x, int64_t batch, int d, int64_t E, const float* B,
+                                 const uint32_t* goff, const float* Gs, const float* Sh, float cs, const float* W,
+                                 int C, int64_t esplit, float* part, hipStream_t s);
+hipError_t launch_head_bwd_fused(bool vec, const float* x, int64_t batch, int d, int64_t E, const float* B,
+                                 const uint32_t* goff, const float* Gs, const float* Sh, float cs, const float* dl,
+                                 const float* W, int C, int64_t ranges, int64_t rows_per_range, float* dphi,
+                                 float* part, hipStream_t s);
 
 }  // namespace mck

@@ -256,8 +256,6 @@ __global__ void __launch_bounds__(RG::BLOCK, 1) k_forward_pair(PairArgs a)
     constexpr int64_t CH = RG::n, n = 2 * CH;
     constexpr uint32_t XB = elem_bytes<XT>(), YB = elem_bytes<YT>();
     __shared__ float lds[RG::LDS_FLOATS];
-    const uint32_t t = threadIdx.x;
-    const uint32_t tb = tpart<M, P, 0>(t);
     const int xcd = (int)(blockIdx.x % kXcds), slot = (int)(blockIdx.x / kXcds);
     const int64_t kx = a.rows > xcd ? (a.rows - xcd + kXcds - 1) / kXcds : 0;  // rows of this XCD
     const int64_t jx = (kx + kPairRows - 1) / kPairRows * kPairRows * a.E;
@@ -284,25 +282,15 @@ __global__ void __launch_bounds__(RG::BLOCK, 1) k_forward_pair(PairArgs a)
     auto xrsrc = [&](int64_t row) {
         return make_rsrc(static_cast<const char*>(a.x) + row * a.d * XB, (uint32_t)(a.d * XB));
     };
-    // x (lower half) and the sign words of an item, loaded one item ahead:
-    // before the previous item's feature stores, so that their drain (the
-    // vector-memory counter is shared by loads and stores) overlaps the
-    // lower half's first transform instead of stalling it
-    float xl[EPL];
-    uint32_t w0 = 0, w1 = 0;
-    auto prefetch = [&](int64_t j) {
-        const Item it = item(j);
-        bload_row_t<M, P, VEC, XT>(xl, xrsrc(it.row), 0u, a.d, t, true);
-        w0 = a.Bw[(2 * it.e) * BLOCK + t];
-        w1 = a.Bw[(2 * it.e + 1) * BLOCK + t];
-    };
-
     int64_t j = slot;
     if (j < jx && !item(j).live)
         j = next(j);
-    if (j < jx)
-        prefetch(j);
     for (; j < jx;) {  // uniform over the block
+        // the lane index laundered per item: addresses derived from it are
+        // formed where they are used instead of being hoisted out of the
+        // item loop, where they would stay live across it
+        const uint32_t t = lane_opaque(threadIdx.x);
+        const uint32_t tb = tpart<M, P, 0>(t);
         const Item it = item(j);
         const int64_t row = it.row;
         const int e = it.e;
@@ -310,12 +298,14 @@ __global__ void __launch_bounds__(RG::BLOCK, 1) k_forward_pair(PairArgs a)
         const float xs = a.xexp != nullptr ? __builtin_ldexpf(1.f, (int)a.xexp[row]) : 1.f;
 
         // 1. H_{2^16} (B o xhat) = the bit-15 butterfly after H_{2^15} on
-        //    each half (the two factors commute): the lower half first, from
-        //    the prefetched x, then the upper half
+        //    each half (the two factors commute): the lower half first, then
+        //    the upper half, whose x loads overlap the lower transform
         float lo[EPL], hi[EPL];
+        bload_row_t<M, P, VEC, XT>(lo, xrsrc(row), 0u, a.d, t, true);
+        const uint32_t w0 = a.Bw[(2 * e) * BLOCK + t], w1 = a.Bw[(2 * e + 1) * BLOCK + t];
 #pragma unroll
         for (int r = 0; r < EPL; ++r)
-            lo[r] = __uint_as_float(__float_as_uint(xl[r] * xs) ^ ((w0 << (31 - r)) & 0x80000000u));
+            lo[r] = __uint_as_float(__float_as_uint(lo[r] * xs) ^ ((w0 << (31 - r)) & 0x80000000u));
         fwht_up<M, P>(lo, lds, lds_lane<M, P>(t));
         bload_row_t<M, P, VEC, XT>(hi, xrsrc(row), (uint32_t)(CH * XB), a.d - (int)CH, t, true);
 #pragma unroll
@@ -330,33 +320,29 @@ __global__ void __launch_bounds__(RG::BLOCK, 1) k_forward_pair(PairArgs a)
         }
 
         // 2. Pi out: each source half, grouped by destination half, to the
-        //    exchange row.  Both halves' plan words are loaded before the
-        //    first exchange store (same counter as above).
-        {
-            uint32_t pk0[EPL], pk1[EPL];
-            lds_put<M, P, RG::GL>(lds, lds_lane<M, P>(t), lo);
-            const rsrc_t ra = make_rsrc(a.packA + eo, (uint32_t)(n * 4));
+        //    exchange row
+        auto send = [&](const float (&v)[EPL], int h) {
+            lds_put<M, P, RG::GL>(lds, lds_lane<M, P>(t), v);
+            __syncthreads();
+            const int32_t d0 = a.pdelta[e * 4 + 2 * h], d1 = a.pdelta[e * 4 + 2 * h + 1];
+            const rsrc_t ra = make_rsrc(a.packA + eo + h * CH, (uint32_t)(CH * 4));
 #pragma unroll
             for (int jj = 0; jj < NQ; ++jj) {
-                bload4u(&pk0[4 * jj], ra, 16u * (jj * BLOCK + t), 0u);
-                bload4u(&pk1[4 * jj], ra, 16u * (jj * BLOCK + t), (uint32_t)(CH * 4));
-            }
-            auto send = [&](const uint32_t (&pk)[EPL], int h) {
-                const int32_t d0 = a.pdelta[e * 4 + 2 * h], d1 = a.pdelta[e * 4 + 2 * h + 1];
+                if (jj == NQ / 2)
+                    __builtin_amdgcn_sched_barrier(0);
+                uint32_t pk[4];
+                bload4u(pk, ra, 16u * (jj * BLOCK + t), 0u);
 #pragma unroll
-                for (int r = 0; r < EPL; ++r) {
-                    const int32_t qq = 4 * ((r / 4) * BLOCK + (int)t) + (r % 4);
-                    const int32_t pos = qq + (((pk[r] >> kRowM) & 1u) ? d1 : d0);
-                    bstore1(rex, 4u * (uint32_t)pos, 0u, lds[phys<P>(pk[r] & 0x7fffu)]);
+                for (int m = 0; m < 4; ++m) {
+                    const int32_t qq = 4 * (jj * BLOCK + (int)t) + m;
+                    const int32_t pos = qq + (((pk[m] >> kRowM) & 1u) ? d1 : d0);
+                    bstore1(rex, 4u * (uint32_t)pos, 0u, lds[phys<P>(pk[m] & 0x7fffu)]);
                 }
-            };
-            __syncthreads();
-            send(pk0, 0);
-            __syncthreads();
-            lds_put<M, P, RG::GL>(lds, lds_lane<M, P>(t), hi);
-            __syncthreads();
-            send(pk1, 1);
-        }
+            }
+            __syncthreads();  // LDS free for the next half
+        };
+        send(lo, 0);
+        send(hi, 1);
         __syncthreads();  // the whole exchange row is written (and visible to the block)
 
         // 3. Pi in: each destination half in the gather layout, G applied
@@ -365,6 +351,8 @@ __global__ void __launch_bounds__(RG::BLOCK, 1) k_forward_pair(PairArgs a)
             const rsrc_t rd = make_rsrc(a.dstB + eo + co * CH, (uint32_t)(CH * 2));
 #pragma unroll
             for (int jj = 0; jj < NQ; ++jj) {
+                if (jj == NQ / 2)
+                    __builtin_amdgcn_sched_barrier(0);
                 float tv[4], gx[4];
                 bload4(tv, rex, 16u * (jj * BLOCK + t), (uint32_t)(co * CH * 4));
                 bload4(gx, rg, 16u * (jj * BLOCK + t), 0u);
@@ -405,8 +393,6 @@ __global__ void __launch_bounds__(RG::BLOCK, 1) k_forward_pair(PairArgs a)
                 hi[r] *= sx[r];
         }
         const int64_t jn = next(j);
-        if (jn < jx)
-            prefetch(jn);
 
         // 5. c cos z, c sin z
         const rsrc_t ry = make_rsrc(static_cast<char*>(a.phi) + row * 2 * nE * YB, (uint32_t)(2 * nE * YB));

@@ -358,7 +358,7 @@ struct TempPlan {
 };
 
 mck_status make_temp_plan(int64_t n, int64_t E, const int32_t* perm, const float* G, const float* S,
-                          hipStream_t s, TempPlan* tp)
+                          hipStream_t s, TempPlan* tp, int force_p = 0)
 {
     const size_t en = (size_t)(n * E);
     int64_t gf = 0, gb = 0;
@@ -375,7 +375,7 @@ mck_status make_temp_plan(int64_t n, int64_t E, const int32_t* perm, const float
     tp->GsF = reinterpret_cast<float*>(b + af + ab);
     tp->GkB = reinterpret_cast<float*>(b + af + ab + a);
     tp->Sh = reinterpret_cast<float*>(b + af + ab + 2 * a);
-    tp->PF = current_tuning(log2i(n)).P;
+    tp->PF = force_p ? force_p : current_tuning(log2i(n)).P;
     err = mck::launch_derive(log2i(n), tp->PF, E, perm, G, nullptr, nullptr, S, tp->goffF, tp->GsF, tp->goffB,
                              tp->GkB, tp->Sh, s);
     if (err != hipSuccess) {
@@ -1468,6 +1468,76 @@ mck_status mck_fastfood_backward_p_noalloc(const float* x, const float* dphi, in
 
 static mck_status check_head(int64_t batch, int64_t F, int64_t C);
 
+namespace {
+
+// The training step with the head fused into the feature-map kernels: phi
+// never goes to HBM.  Forward + logits (k_forward_logits), softmax
+// cross-entropy, phi recomputed for dW and dphi (k_head_bwd_fused), the
+// adjoint, the SGD update.  Arguments checked by the caller.
+mck_status train_step_fused(const float* x, const int32_t* labels, int64_t batch, int64_t d, int64_t n, int64_t E,
+                            int64_t C, float* W, float* b, float* B, const int32_t* perm, float* G, float* S,
+                            float lr, float* loss, float* logits, float* dW, float* db, float* dB, float* dG,
+                            float* dS, float* dx, hipStream_t s)
+{
+    const int64_t F = 2 * n * E;
+    const int64_t esplit = mck::fused_logits_esplit(batch, E);
+    int64_t ranges = 0, rpr = 0;
+    mck::fused_bwd_geometry(batch, E, &ranges, &rpr);
+    // scratch: dphi, logits (when the caller passes none), dlogits, row
+    // losses, the logits' and dW's partials
+    const int64_t lpart = esplit * batch * C, wpart = ranges > 1 ? ranges * C * F : 0;
+    const size_t zf = align_up((size_t)(batch * F) * 4), zl = align_up((size_t)(batch * C) * 4),
+                 zr = align_up((size_t)batch * 4), zp = align_up((size_t)(lpart > wpart ? lpart : wpart) * 4);
+    void* block = nullptr;
+    hipError_t err = hipMallocAsync(&block, zf + 2 * zl + zr + zp, s);
+    if (err != hipSuccess)
+        return fail(MCK_ERR_NO_MEMORY, std::string("training step scratch: ") + hipGetErrorString(err));
+    char* base = static_cast<char*>(block);
+    float* dphi = reinterpret_cast<float*>(base);
+    float* lg = logits ? logits : reinterpret_cast<float*>(base + zf);
+    float* dl = reinterpret_cast<float*>(base + zf + zl);
+    float* row_loss = reinterpret_cast<float*>(base + zf + 2 * zl);
+    float* part = reinterpret_cast<float*>(base + zf + 2 * zl + zr);
+    TempPlan tp;
+    mck_status st = make_temp_plan(n, E, perm, G, S, s, &tp, 4);
+    if (st != MCK_OK) {
+        (void)hipFreeAsync(block, s);
+        return st;
+    }
+    const bool vec = aligned16(x) && d % 4 == 0;
+    const float cs = feature_scale(n, E);
+    err = mck::launch_forward_logits(vec, x, batch, (int)d, E, B, tp.goffF, tp.GsF, tp.Sh, cs, W, (int)C, esplit,
+                                     part, s);
+    if (err == hipSuccess)
+        err = mck::launch_logits_finish(part, b, esplit, batch, (int)C, lg, s);
+    if (err == hipSuccess)
+        err = mck::launch_softmax_xent(lg, labels, batch, (int)C, row_loss, dl, loss, db, s);
+    if (err == hipSuccess)
+        err = mck::launch_head_bwd_fused(vec, x, batch, (int)d, E, B, tp.goffF, tp.GsF, tp.Sh, cs, dl, W, (int)C,
+                                         ranges, rpr, dphi, ranges > 1 ? part : dW, s);
+    if (err == hipSuccess && ranges > 1)
+        err = mck::launch_sum_groups(part, ranges, C * F, dW, s);
+    if (err == hipSuccess) {
+        st = run_backward(x, dphi, batch, d, n, E, B, tp.goffB, tp.GkB, S, tp.Sh, dx, dB, dG, dS, s);
+        if (st != MCK_OK) {
+            (void)hipFreeAsync(tp.block, s);
+            (void)hipFreeAsync(block, s);
+            return st;
+        }
+    }
+    if (err == hipSuccess && lr != 0.f) {
+        float* const ys[5] = {W, b, B, G, S};
+        const float* const xs[5] = {dW, db, dB, dG, dS};
+        const int64_t cnt[5] = {C * F, C, n * E, n * E, n * E};
+        err = mck::launch_axpy_multi(ys, xs, cnt, 5, -lr, s);
+    }
+    (void)hipFreeAsync(tp.block, s);
+    (void)hipFreeAsync(block, s);
+    return err == hipSuccess ? MCK_OK : hip_fail(err, "training step launch");
+}
+
+}  // namespace
+
 mck_status mck_fastfood_train_step(const float* x, const int32_t* labels, int64_t batch, int64_t d, int64_t n,
                                    int64_t E, int64_t C, float* W, float* b, float* B, const int32_t* perm, float* G,
                                    float* S, float lr, float* loss, float* logits, float* dW, float* db, float* dB,
@@ -1489,6 +1559,9 @@ mck_status mck_fastfood_train_step(const float* x, const int32_t* labels, int64_
     if (!std::isfinite(lr))
         return fail(MCK_ERR_INVALID_ARG, "lr must be finite");
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (mck::fused_head_ok(n, C))
+        return train_step_fused(x, labels, batch, d, n, E, C, W, b, B, perm, G, S, lr, loss, logits, dW, db, dB, dG,
+                                dS, dx, s);
     // scratch: phi, dphi, logits (when the caller passes none), dlogits, row
     // losses, head partials
     int64_t slabs = 0, groups = 0, rpg = 0;

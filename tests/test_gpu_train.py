@@ -31,8 +31,8 @@ def rel(a, ref):
     return float(np.linalg.norm(a - ref) / max(np.linalg.norm(ref), 1e-300))
 
 
-def _problem(orc, batch, E, C=10, sigma=1.0, seed=3):
-    x = workloads.mnist_sparse(batch)
+def _problem(orc, batch, E, C=10, sigma=1.0, seed=3, d=784):
+    x = workloads.mnist_sparse(batch) if d == 784 else workloads.normal(batch, d, seed=d) * np.float32(0.05)
     n = orc.padded_dim(x.shape[1])
     p = orc.params(workloads.FASTFOOD_SEED, n, E, sigma)
     rng = np.random.default_rng(seed)
@@ -80,11 +80,14 @@ def test_axpy(mk):
         np.testing.assert_allclose(yt.cpu().numpy(), ref, rtol=2e-7, atol=1e-7)
 
 
-@pytest.mark.parametrize("batch,E", [(64, 2), (1024, 16)])
-def test_train_step_matches_oracle(mk, orc, batch, E):
+# n = 1024 with C <= 10 takes the step with the head fused into the feature
+# map (phi never in HBM); other n or C take the unfused kernels
+@pytest.mark.parametrize("batch,E,C,d", [(64, 2, 10, 784), (1024, 16, 10, 784), (1001, 3, 7, 784), (13, 1, 1, 1000),
+                                         (300, 4, 12, 784), (200, 3, 10, 300)])
+def test_train_step_matches_oracle(mk, orc, batch, E, C, d):
     import torch
 
-    x, y, W, b, p = _problem(orc, batch, E)
+    x, y, W, b, p = _problem(orc, batch, E, C=C, d=d)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     B, G, S = dev(p["B"]), dev(p["G"]), dev(p["S32"])
     perm = dev(p["perm"])
