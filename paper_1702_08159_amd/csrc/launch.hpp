@@ -76,15 +76,18 @@ hipError_t launch_forward_long(int M, bool vec, int xt, int yt, const void* x, i
                                const float* Gx, const float* Sh, float cs, void* phi, float* u, float* w,
                                hipStream_t s, const int8_t* xexp = nullptr);
 // n = 2^16 (longn.hip): the whole feature map of a row in one 1024-lane
-// block per (row, expansion) work item, Pi through the block's exchange row
-// (exch: `blocks` rows of 2^16 floats); blocks from pair_blocks (a multiple
-// of 8).  Bw: sign words of B from launch_pair_signs (E x 2 x 1024 words).
+// block per (row, expansion) work item, Pi split by the outer stage of a
+// Benes network (register-pair switches around two 2^15 permutations through
+// LDS); blocks from pair_blocks (a multiple of 8).  The plan arrays come from
+// launch_pair_plan: Bw (sign words of B, E x 2 x 1024), Pw (switch words,
+// E x 2 x 1024), Po (gather indices, E n / 2 words), Pg (G, E n floats).
 int64_t pair_blocks(int64_t rows, int64_t E, int cus);
-hipError_t launch_pair_signs(const float* B, int64_t E, uint32_t* Bw, hipStream_t s);
+hipError_t launch_pair_plan(int64_t E, const int32_t* perm, const float* G, const float* B, uint32_t* Bw,
+                            uint32_t* Pw, uint32_t* Po, float* Pg, hipStream_t s);
 hipError_t launch_forward_pair(bool vec, int xt, int yt, const void* x, int64_t batch, int d, int64_t E,
-                               const uint32_t* Bw, const uint32_t* packA, const uint16_t* dstB,
-                               const int32_t* pdelta, const float* Gx, const float* Sh, float cs, void* phi,
-                               float* exch, int64_t blocks, hipStream_t s, const int8_t* xexp = nullptr);
+                               const uint32_t* Bw, const uint32_t* Pw, const uint32_t* Po, const float* Pg,
+                               const float* Sh, float cs, void* phi, int64_t blocks, hipStream_t s,
+                               const int8_t* xexp = nullptr);
 // Pi (destination i takes source perm[i]) of each expansion as an exchange
 // between the C = n / 2^15 chunks of 2^15 elements.  The exchange buffer T
 // holds, for each destination chunk co, the elements it receives, grouped

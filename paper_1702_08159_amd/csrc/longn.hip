@@ -210,20 +210,21 @@ __global__ void __launch_bounds__(RG::BLOCK) k_rows(RowArgs a)
 // ------------------------------------------------------------------ n = 2^16 in one block
 // A whole row of n = 2^16 = two 2^15 halves per 1024-lane block: 32 values
 // per lane and half in VGPRs (a lane holds the same positions of both
-// halves, so the butterflies on index bit 15 are register-local), and each
-// half's relayouts through the one 2^15-float LDS buffer in turn.  Per work
-// item (row, expansion):
-//   1. B o xhat (sign words), the bit-15 butterfly, H_{2^15} on each half;
-//   2. Pi through the block's own exchange row in global memory (L2): each
-//      source half leaves grouped by destination half (packA, pdelta), then
-//      every destination half comes back as one contiguous run, scaled by G
-//      in that order (Gx) and placed by dstB in LDS;
+// halves, so everything that pairs element j with j + 2^15 is
+// register-local), and each half's relayouts through the one 2^15-float LDS
+// buffer in turn.  Pi is split by the outer stage of a Benes network:
+//   Pi = S_out (Pi_top (+) Pi_bot) S_in,
+// where S_in and S_out exchange, pair by pair, the elements j and j + 2^15
+// (register selects), and Pi_top, Pi_bot permute each half within itself
+// (a gather through LDS, one half after the other).  The switch settings
+// come from a 2-colouring of the source elements computed at plan time
+// (k_pair_colour).  Per work item (row, expansion):
+//   1. B o xhat (sign words), H_{2^15} on each half, the bit-15 butterfly;
+//   2. S_in, Pi_top on the lower half and Pi_bot on the upper half through
+//      LDS, S_out, G at the destinations;
 //   3. the bit-15 butterfly, H_{2^15} on each half, S / (2 pi), [cos, sin].
-// Against the multi-pass path this keeps u and w of the row pass and the
-// column passes out of HBM: per item x is read (from L2 after the first
-// expansion), phi written, and the exchange row stays near the CU.  The
-// block's exchange row is written and read by the block alone, so the
-// block barrier orders it (all waves of a block share one CU's caches).
+// Per item only x is read (from L2 after the first expansion), the plan
+// words of the expansion, and phi written: nothing of the row leaves the CU.
 //
 // Work items: XCD x (blocks b with b % 8 = x, `slots` of them) takes rows
 // x, x + 8, x + 16, ... in groups of 8 rows; within a group the items are
@@ -234,32 +235,30 @@ struct PairArgs {
     int64_t rows;
     int d;
     int E;
-    const uint32_t* Bw;     // sign words [e][h][t]: bit r set where B is -1 at register r of lane t
-    const uint32_t* packA;  // exchange plan of the expansion (C = 2 chunks), launch.hpp
-    const int32_t* pdelta;
-    const uint16_t* dstB;
-    const float* Gx;
+    const uint32_t* Bw;  // sign words [e][h][t]: bit r set where B is -1 at register r of lane t
+    const uint32_t* Pw;  // switch words [e][in / out][t]: bit r set where the pair of register r is exchanged
+    const uint32_t* Po;  // gather sources [e][h][q][t][4]: 16-bit LDS float indices, two registers per word
+    const float* Pg;     // G at the destinations [e][h][q][t][4], register r = 4 q + m
     const float* Sh;
     float cs;
     void* phi;
-    float* exch;            // gridDim.x rows of 2^16 floats
-    const int8_t* xexp;     // nullable per-row exponents of x
-    int slots;              // blocks per XCD
+    const int8_t* xexp;  // nullable per-row exponents of x
+    int slots;           // blocks per XCD
 };
 
 constexpr int kPairRows = 8;  // rows per group within an XCD
+constexpr int64_t kPairN = 2 * RG::n;
 
 template <int XT, int YT, bool VEC>
 __global__ void __launch_bounds__(RG::BLOCK, 1) k_forward_pair(PairArgs a)
 {
-    constexpr int M = kRowM, P = kRowP, EPL = RG::EPL, BLOCK = RG::BLOCK, NQ = EPL / 4;
+    constexpr int M = kRowM, P = kRowP, EPL = RG::EPL, BLOCK = RG::BLOCK;
     constexpr int64_t CH = RG::n, n = 2 * CH;
     constexpr uint32_t XB = elem_bytes<XT>(), YB = elem_bytes<YT>();
     __shared__ float lds[RG::LDS_FLOATS];
     const int xcd = (int)(blockIdx.x % kXcds), slot = (int)(blockIdx.x / kXcds);
     const int64_t kx = a.rows > xcd ? (a.rows - xcd + kXcds - 1) / kXcds : 0;  // rows of this XCD
     const int64_t jx = (kx + kPairRows - 1) / kPairRows * kPairRows * a.E;
-    const rsrc_t rex = make_rsrc(a.exch + (int64_t)blockIdx.x * n, (uint32_t)(n * 4));
     const int64_t nE = n * a.E;
 
     // work item j -> (row, e); k >= kx marks the empty tail of a row group
@@ -312,6 +311,7 @@ __global__ void __launch_bounds__(RG::BLOCK, 1) k_forward_pair(PairArgs a)
         for (int r = 0; r < EPL; ++r)
             hi[r] = __uint_as_float(__float_as_uint(hi[r] * xs) ^ ((w1 << (31 - r)) & 0x80000000u));
         fwht_up<M, P>(hi, lds, lds_lane<M, P>(t));
+        const uint32_t sw_in = a.Pw[(2 * e) * BLOCK + t];
 #pragma unroll
         for (int r = 0; r < EPL; ++r) {
             const float p0 = lo[r], p1 = hi[r];
@@ -319,58 +319,48 @@ __global__ void __launch_bounds__(RG::BLOCK, 1) k_forward_pair(PairArgs a)
             hi[r] = p0 - p1;
         }
 
-        // 2. Pi out: each source half, grouped by destination half, to the
-        //    exchange row
-        auto send = [&](const float (&v)[EPL], int h) {
+        // 2. G Pi: S_in; each half's permutation through LDS; S_out; G
+        auto exchange = [&](uint32_t w) {
+#pragma unroll
+            for (int r = 0; r < EPL; ++r) {
+                const bool s = ((w >> r) & 1u) != 0u;
+                const float p0 = lo[r], p1 = hi[r];
+                lo[r] = s ? p1 : p0;
+                hi[r] = s ? p0 : p1;
+            }
+        };
+        auto permute_half = [&](float (&v)[EPL], int h) {
+            const rsrc_t ro = make_rsrc(a.Po + (int64_t)(2 * e + h) * (EPL / 2) * BLOCK, (uint32_t)(EPL / 2 * BLOCK * 4));
+            uint32_t op[EPL / 2];
+#pragma unroll
+            for (int q = 0; q < EPL / 8; ++q)
+                bload4u(&op[4 * q], ro, 16u * (q * BLOCK + t), 0u);
             lds_put<M, P, RG::GL>(lds, lds_lane<M, P>(t), v);
             __syncthreads();
-            const int32_t d0 = a.pdelta[e * 4 + 2 * h], d1 = a.pdelta[e * 4 + 2 * h + 1];
-            const rsrc_t ra = make_rsrc(a.packA + eo + h * CH, (uint32_t)(CH * 4));
 #pragma unroll
-            for (int jj = 0; jj < NQ; ++jj) {
-                if (jj == NQ / 2)
-                    __builtin_amdgcn_sched_barrier(0);
-                uint32_t pk[4];
-                bload4u(pk, ra, 16u * (jj * BLOCK + t), 0u);
-#pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    const int32_t qq = 4 * (jj * BLOCK + (int)t) + m;
-                    const int32_t pos = qq + (((pk[m] >> kRowM) & 1u) ? d1 : d0);
-                    bstore1(rex, 4u * (uint32_t)pos, 0u, lds[phys<P>(pk[m] & 0x7fffu)]);
-                }
-            }
+            for (int r = 0; r < EPL; ++r)
+                v[r] = lds[(op[r >> 1] >> (16 * (r & 1))) & 0xFFFFu];
             __syncthreads();  // LDS free for the next half
         };
-        send(lo, 0);
-        send(hi, 1);
-        __syncthreads();  // the whole exchange row is written (and visible to the block)
-
-        // 3. Pi in: each destination half in the gather layout, G applied
-        auto recv = [&](float (&v)[EPL], int co) {
-            const rsrc_t rg = make_rsrc(a.Gx + eo + co * CH, (uint32_t)(CH * 4));
-            const rsrc_t rd = make_rsrc(a.dstB + eo + co * CH, (uint32_t)(CH * 2));
+        auto scale_g = [&](float (&v)[EPL], int h) {
+            const rsrc_t rg = make_rsrc(a.Pg + (int64_t)(2 * e + h) * CH, (uint32_t)(CH * 4));
 #pragma unroll
-            for (int jj = 0; jj < NQ; ++jj) {
-                if (jj == NQ / 2)
-                    __builtin_amdgcn_sched_barrier(0);
-                float tv[4], gx[4];
-                bload4(tv, rex, 16u * (jj * BLOCK + t), (uint32_t)(co * CH * 4));
-                bload4(gx, rg, 16u * (jj * BLOCK + t), 0u);
-                const u32x2_t di =
-                    __builtin_bit_cast(u32x2_t, __builtin_amdgcn_raw_buffer_load_b64(rd, (int)(8u * (jj * BLOCK + t)), 0, 0));
-                lds[phys<P>(di.x & 0x7fffu)] = tv[0] * gx[0];
-                lds[phys<P>((di.x >> 16) & 0x7fffu)] = tv[1] * gx[1];
-                lds[phys<P>(di.y & 0x7fffu)] = tv[2] * gx[2];
-                lds[phys<P>((di.y >> 16) & 0x7fffu)] = tv[3] * gx[3];
+            for (int q = 0; q < EPL / 4; ++q) {
+                float g4[4];
+                bload4(g4, rg, 16u * (q * BLOCK + t), 0u);
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+                    v[4 * q + m] *= g4[m];
             }
-            __syncthreads();
-            lds_get<M, P, RG::GL>(lds, lds_lane<M, P>(t), v);
-            __syncthreads();
         };
-        recv(lo, 0);
-        recv(hi, 1);
+        exchange(sw_in);
+        permute_half(lo, 0);
+        permute_half(hi, 1);
+        exchange(a.Pw[(2 * e + 1) * BLOCK + t]);
+        scale_g(lo, 0);
+        scale_g(hi, 1);
 
-        // 4. H_{2^16} G Pi v1: the bit-15 butterfly, H_{2^15} on each half;
+        // 3. H_{2^16} G Pi v1: the bit-15 butterfly, H_{2^15} on each half;
         //    z in revolutions (S / 2 pi) for both halves before any store
 #pragma unroll
         for (int r = 0; r < EPL; ++r) {
@@ -394,7 +384,7 @@ __global__ void __launch_bounds__(RG::BLOCK, 1) k_forward_pair(PairArgs a)
         }
         const int64_t jn = next(j);
 
-        // 5. c cos z, c sin z
+        // 4. c cos z, c sin z
         const rsrc_t ry = make_rsrc(static_cast<char*>(a.phi) + row * 2 * nE * YB, (uint32_t)(2 * nE * YB));
         auto features = [&](const float (&v)[EPL], int h) {
             const uint32_t yc = YB * (uint32_t)(eo + h * CH + tb), ysn = yc + YB * (uint32_t)nE;
@@ -412,6 +402,134 @@ __global__ void __launch_bounds__(RG::BLOCK, 1) k_forward_pair(PairArgs a)
         features(lo, 0);
         features(hi, 1);
         j = jn;
+    }
+}
+
+// ---- plan of k_forward_pair: the outer Benes stage of Pi (gather form,
+// v_out[i] = v_in[perm[i]], n = 2N, N = 2^15).  Source element y travels
+// through the top subnetwork (colour 0) or the bottom one (colour 1).  The
+// input switch of pair j sends j and j + N to different subnetworks, and the
+// output switch of pair i takes destinations i and i + N from different ones:
+// so y and y ^ N differ in colour, and so do perm[i] and perm[i ^ N].  These
+// constraints form disjoint cycles that alternate between the two kinds of
+// pair, hence of even length, and colouring a cycle alternately satisfies
+// them all (the looping algorithm of Benes network routing).  With
+//   link(y) = perm[perm^-1[y ^ N] ^ N]
+// (y's input partner, then that element's output partner), the cycle through
+// y visits y, y ^ N, link(y), link(y) ^ N, ...: link keeps the colour.
+
+// inv[e][perm[e][i]] = i
+__global__ void k_pair_inverse(const int32_t* __restrict__ perm, int64_t E, uint16_t* __restrict__ inv)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= E * kPairN)
+        return;
+    const int64_t e = i / kPairN;
+    inv[e * kPairN + ((uint32_t)perm[i] & (uint32_t)(kPairN - 1))] = (uint16_t)(i % kPairN);
+}
+
+__global__ void k_pair_link(const int32_t* __restrict__ perm, const uint16_t* __restrict__ inv, int64_t E,
+                            uint16_t* __restrict__ link)
+{
+    constexpr uint32_t N = RG::n;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= E * kPairN)
+        return;
+    const int64_t e = i / kPairN;
+    const uint32_t y = (uint32_t)(i % kPairN);
+    const uint32_t k = (uint32_t)inv[e * kPairN + (y ^ N)] ^ N;
+    link[i] = (uint16_t)((uint32_t)perm[e * kPairN + k] & (uint32_t)(kPairN - 1));
+}
+
+// One block per expansion: colour[e][j / 32] bit j % 32 = colour of source
+// element j < N (that of j + N is the other one).  One lane walks every
+// cycle through link, held in LDS; a walk colours the pair {y, y ^ N} per
+// step, so a permutation takes N steps in all, and the step budget ends the
+// walk even if link were not a bijection.
+__global__ void __launch_bounds__(256) k_pair_colour(const uint16_t* __restrict__ link, int64_t E,
+                                                     uint32_t* __restrict__ colour)
+{
+    constexpr uint32_t N = RG::n, W = N / 32;
+    __shared__ uint16_t lk[kPairN];
+    __shared__ uint32_t seen[W], col[W];
+    const int64_t e = blockIdx.x;
+    for (uint32_t i = threadIdx.x; i < (uint32_t)kPairN; i += blockDim.x)
+        lk[i] = link[e * kPairN + i];
+    for (uint32_t i = threadIdx.x; i < W; i += blockDim.x) {
+        seen[i] = 0u;
+        col[i] = 0u;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t budget = (int32_t)N;
+        for (uint32_t w = 0; w < W && budget > 0; ++w) {
+            while (seen[w] != 0xFFFFFFFFu && budget > 0) {
+                const uint32_t y0 = 32u * w + (uint32_t)__builtin_ctz(~seen[w]);  // colour 0
+                uint32_t y = y0;
+                do {
+                    const uint32_t jj = y & (N - 1u);
+                    seen[jj >> 5] |= 1u << (jj & 31u);
+                    if (y >= N)
+                        col[jj >> 5] |= 1u << (jj & 31u);  // y = jj + N has colour 0
+                    y = lk[y];
+                } while (y != y0 && --budget > 0);
+            }
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < W; i += blockDim.x)
+        colour[e * W + i] = col[i];
+}
+
+// Per expansion e and lane t of k_forward_pair (gather layout GL of the
+// 2^15 engine: register r of lane t holds position i(t, r) of each half):
+//   Pw[e][0][t] bit r: colour of source i (the input pair travels swapped);
+//   Pw[e][1][t] bit r: colour of perm[i] (the output pair arrives swapped);
+//   Po[e][h][q][t][m], registers 2(4q+m) and 2(4q+m)+1: LDS float index of
+//     the position within the half that Pi_top (h = 0) / Pi_bot (h = 1)
+//     gathers for i;
+//   Pg[e][h][q][t][m]: G[e][h N + i] for register r = 4q + m.
+__global__ void k_pair_plan(const int32_t* __restrict__ perm, const float* __restrict__ G,
+                            const uint32_t* __restrict__ colour, int64_t E, uint32_t* __restrict__ Pw,
+                            uint32_t* __restrict__ Po, float* __restrict__ Pg)
+{
+    constexpr int M = kRowM, P = kRowP, EPL = RG::EPL, BLOCK = RG::BLOCK;
+    constexpr uint32_t N = RG::n;
+    const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gi >= E * BLOCK)
+        return;
+    const int64_t e = gi / BLOCK;
+    const uint32_t t = (uint32_t)(gi % BLOCK);
+    const int32_t* pe = perm + e * kPairN;
+    const float* ge = G + e * kPairN;
+    const uint32_t* ce = colour + e * (N / 32);
+    auto colour_of = [&](uint32_t y) {
+        const uint32_t jj = y & (N - 1u);
+        return ((ce[jj >> 5] >> (jj & 31u)) & 1u) ^ (y >= N ? 1u : 0u);
+    };
+    uint32_t win = 0, wout = 0, ot[EPL / 2], ob[EPL / 2];
+    for (int w = 0; w < EPL / 2; ++w)
+        ot[w] = ob[w] = 0u;
+    const uint32_t tb = tpart<M, P, RG::GL>(t);
+    for (int r = 0; r < EPL; ++r) {
+        const uint32_t i = tb | rpart(M, P, RG::GL, r);
+        win |= colour_of(i) << r;
+        const uint32_t y = (uint32_t)pe[i] & (uint32_t)(kPairN - 1), z = (uint32_t)pe[i + N] & (uint32_t)(kPairN - 1);
+        const uint32_t s = colour_of(y);  // 1: perm[i] comes through the bottom subnetwork
+        wout |= s << r;
+        const uint32_t top = s ? z : y, bot = s ? y : z;
+        ot[r >> 1] |= phys<P>(top & (N - 1u)) << (16 * (r & 1));
+        ob[r >> 1] |= phys<P>(bot & (N - 1u)) << (16 * (r & 1));
+        const int64_t go = ((e * 2) * (EPL / 4) + r / 4) * BLOCK * 4 + t * 4 + r % 4;
+        Pg[go] = ge[i];
+        Pg[go + (EPL / 4) * BLOCK * 4] = ge[i + N];
+    }
+    Pw[(e * 2) * BLOCK + t] = win;
+    Pw[(e * 2 + 1) * BLOCK + t] = wout;
+    for (int w = 0; w < EPL / 2; ++w) {
+        const int64_t oo = ((e * 2) * (EPL / 8) + w / 4) * BLOCK * 4 + t * 4 + w % 4;
+        Po[oo] = ot[w];
+        Po[oo + (EPL / 8) * BLOCK * 4] = ob[w];
     }
 }
 
@@ -832,8 +950,19 @@ hipError_t launch_forward_long(int M, bool vec, int xt, int yt, const void* x, i
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_pair_signs(const float* B, int64_t E, uint32_t* Bw, hipStream_t s)
+hipError_t launch_pair_plan(int64_t E, const int32_t* perm, const float* G, const float* B, uint32_t* Bw,
+                            uint32_t* Pw, uint32_t* Po, float* Pg, hipStream_t s)
 {
+    // the inverse and the links are built in Pg's space, the colours in
+    // Bw's; both are overwritten last
+    uint16_t* inv = reinterpret_cast<uint16_t*>(Pg);
+    uint16_t* link = inv + E * kPairN;
+    uint32_t* colour = Bw;
+    const unsigned eb = (unsigned)((E * kPairN + 255) / 256);
+    k_pair_inverse<<<dim3(eb), dim3(256), 0, s>>>(perm, E, inv);
+    k_pair_link<<<dim3(eb), dim3(256), 0, s>>>(perm, inv, E, link);
+    k_pair_colour<<<dim3((unsigned)E), dim3(256), 0, s>>>(link, E, colour);
+    k_pair_plan<<<dim3((unsigned)((E * RG::BLOCK + 255) / 256)), dim3(256), 0, s>>>(perm, G, colour, E, Pw, Po, Pg);
     const int64_t total = E * 2 * RG::BLOCK;
     k_pair_signs<<<dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s>>>(B, E, Bw);
     return hipGetLastError();
@@ -852,14 +981,13 @@ int64_t pair_blocks(int64_t rows, int64_t E, int cus)
 }
 
 hipError_t launch_forward_pair(bool vec, int xt, int yt, const void* x, int64_t batch, int d, int64_t E,
-                               const uint32_t* Bw, const uint32_t* packA, const uint16_t* dstB,
-                               const int32_t* pdelta, const float* Gx, const float* Sh, float cs, void* phi,
-                               float* exch, int64_t blocks, hipStream_t s, const int8_t* xexp)
+                               const uint32_t* Bw, const uint32_t* Pw, const uint32_t* Po, const float* Pg,
+                               const float* Sh, float cs, void* phi, int64_t blocks, hipStream_t s,
+                               const int8_t* xexp)
 {
     if (blocks % kXcds != 0 || blocks < kXcds)
         return hipErrorInvalidValue;
-    const PairArgs a{x, batch, d, (int)E, Bw, packA, pdelta, dstB, Gx, Sh, cs, phi, exch, xexp,
-                     (int)(blocks / kXcds)};
+    const PairArgs a{x, batch, d, (int)E, Bw, Pw, Po, Pg, Sh, cs, phi, xexp, (int)(blocks / kXcds)};
     const dim3 grid((unsigned)blocks), blk(RG::BLOCK);
 #define MCK_PAIR(XT_, YT_)                                                                                      \
     do {                                                                                                       \

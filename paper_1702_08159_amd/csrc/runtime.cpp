@@ -171,7 +171,12 @@ struct Plan {
     int32_t* pdelta = nullptr;
     float* Gx = nullptr;
     int32_t* bscratch = nullptr;  // build scratch
-    uint32_t* Bw = nullptr;       // n = 2^16: sign words of B for the one-block row kernel
+    // n = 2^16 (the one-block row kernel): sign words of B, and Pi as the
+    // outer Benes stage (switch words, gather indices of each half, G)
+    uint32_t* Bw = nullptr;
+    uint32_t* Pw = nullptr;
+    uint32_t* Po = nullptr;
+    float* Pg = nullptr;
 };
 
 std::mutex g_mutex;
@@ -227,17 +232,18 @@ mck_status get_plan(uint32_t seed, int64_t n, int64_t E, double sigma, int calib
     const size_t en = (size_t)(n * E);
     int64_t gf = 0, gb = 0;
     mck::plan_elems(log2i(n), &gf, &gb);
-    const size_t C = n > MCK_MAX_N ? (size_t)(n / MCK_MAX_N) : 0;
+    const bool pair = n == 2 * MCK_MAX_N;
+    const size_t C = n > MCK_MAX_N && !pair ? (size_t)(n / MCK_MAX_N) : 0;
     const size_t ecc = (size_t)E * C * C * 4;
     const int M = log2i(n);
     const bool two = n <= MCK_MAX_N && mck::fwd_split_ok(M, alt_split(M));
-    const bool pair = n == 2 * MCK_MAX_N;
-    size_t off[19], total = 0;
-    const size_t sz[19] = {en * 4, en * 4, en * 4, en * 8, en * 4, (size_t)E * 8,
+    size_t off[22], total = 0;
+    const size_t sz[22] = {en * 4, en * 4, en * 4, en * 8, en * 4, (size_t)E * 8,
                            (size_t)gf * E * 4, en * 4, (size_t)gb * E * 4, en * 4, en * 4,
                            C ? en * 4 : 0, C ? en * 2 : 0, ecc, 3 * ecc + (size_t)E * C * 8, C ? en * 4 : 0,
-                           two ? (size_t)gf * E * 4 : 0, two ? en * 4 : 0, pair ? en / 8 : 0};
-    for (int i = 0; i < 19; ++i) {
+                           two ? (size_t)gf * E * 4 : 0, two ? en * 4 : 0, pair ? en / 8 : 0,
+                           pair ? en / 8 : 0, pair ? en * 2 : 0, pair ? en * 4 : 0};
+    for (int i = 0; i < 22; ++i) {
         off[i] = total;
         total += align_up(sz[i]);
     }
@@ -272,8 +278,12 @@ mck_status get_plan(uint32_t seed, int64_t n, int64_t E, double sigma, int calib
         p.goffF2 = reinterpret_cast<uint32_t*>(b + off[16]);
         p.GsF2 = reinterpret_cast<float*>(b + off[17]);
     }
-    if (pair)
+    if (pair) {
         p.Bw = reinterpret_cast<uint32_t*>(b + off[18]);
+        p.Pw = reinterpret_cast<uint32_t*>(b + off[19]);
+        p.Po = reinterpret_cast<uint32_t*>(b + off[20]);
+        p.Pg = reinterpret_cast<float*>(b + off[21]);
+    }
     int matern_t = 0;
     {
         const mck_status cst = check_calib(calib, n, &matern_t);
@@ -289,10 +299,10 @@ mck_status get_plan(uint32_t seed, int64_t n, int64_t E, double sigma, int calib
                                                  p.goffF, p.GsF, p.goffB, p.GkB, p.Sh, stream);
     if (err == hipSuccess && two)
         err = mck::launch_derive_fwd(M, alt_split(M), E, p.perm, p.G, p.B, p.goffF2, p.GsF2, stream);
-    if (err == hipSuccess && n > MCK_MAX_N)
+    if (err == hipSuccess && C)
         err = mck::launch_buckets(log2i(n), E, p.perm, p.G, p.packA, p.dstB, p.pdelta, p.Gx, p.bscratch, stream);
     if (err == hipSuccess && pair)
-        err = mck::launch_pair_signs(p.B, E, p.Bw, stream);
+        err = mck::launch_pair_plan(E, p.perm, p.G, p.B, p.Bw, p.Pw, p.Po, p.Pg, stream);
     if (err == hipSuccess)
         err = hipStreamSynchronize(stream);  // the plan may be used from other streams next
     if (err != hipSuccess) {
@@ -613,10 +623,9 @@ mck_status mck_fastfood_params(uint32_t seed, int64_t n, int64_t E, double sigma
 
 // Feature map for n > MCK_MAX_N.  The kernels address phi, x and the
 // scratch per row, so only a row of phi must stay below 2^31 bytes.
-// n = 2^16 takes the one-block row kernel (k_forward_pair): one exchange row
-// of n floats per block.  Longer rows take the multi-pass path, in equal
-// chunks of rows through two FP32 scratch buffers u, w of at most 2^27
-// floats each.
+// n = 2^16 takes the one-block row kernel (k_forward_pair), which needs no
+// scratch.  Longer rows take the multi-pass path, in equal chunks of rows
+// through two FP32 scratch buffers u, w of at most 2^27 floats each.
 // Rows per launch of the multi-pass path.
 static int64_t long_rows_per(int64_t batch, int64_t n)
 {
@@ -651,7 +660,7 @@ static int64_t pair_blocks(int64_t batch, int64_t E) { return mck::pair_blocks(b
 static int64_t long_scratch_floats(int64_t batch, int64_t n, int64_t E)
 {
     if (n == 2 * MCK_MAX_N)
-        return pair_blocks(batch, E) * n;
+        return 0;
     return 2 * long_rows_per(batch, n) * n;
 }
 
@@ -667,8 +676,8 @@ static mck_status forward_long_launch(const Plan* p, const void* x, int xt, int6
     const bool vec = reinterpret_cast<uintptr_t>(x) % xa == 0 && d % 4 == 0;
     hipError_t err = hipSuccess;
     if (n == 2 * MCK_MAX_N) {
-        err = mck::launch_forward_pair(vec, xt, yt, x, batch, (int)d, E, p->Bw, p->packA, p->dstB, p->pdelta, p->Gx,
-                                       p->Sh, cs, phi, u, pair_blocks(batch, E), s, xexp);
+        err = mck::launch_forward_pair(vec, xt, yt, x, batch, (int)d, E, p->Bw, p->Pw, p->Po, p->Pg, p->Sh, cs, phi,
+                                       pair_blocks(batch, E), s, xexp);
         return err == hipSuccess ? MCK_OK : hip_fail(err, "long-vector forward launch");
     }
     const int64_t rows_per = long_rows_per(batch, n);
@@ -692,12 +701,15 @@ static mck_status forward_long(const Plan* p, const void* x, int xt, int64_t bat
     if (batch == 0)
         return MCK_OK;
     float* u = nullptr;
-    hipError_t err = hipMallocAsync(reinterpret_cast<void**>(&u),
-                                    (size_t)long_scratch_floats(batch, n, E) * sizeof(float), s);
-    if (err != hipSuccess)
-        return fail(MCK_ERR_NO_MEMORY, std::string("long-vector scratch: ") + hipGetErrorString(err));
+    const size_t ub = (size_t)long_scratch_floats(batch, n, E) * sizeof(float);
+    if (ub > 0) {
+        const hipError_t err = hipMallocAsync(reinterpret_cast<void**>(&u), ub, s);
+        if (err != hipSuccess)
+            return fail(MCK_ERR_NO_MEMORY, std::string("long-vector scratch: ") + hipGetErrorString(err));
+    }
     const mck_status st = forward_long_launch(p, x, xt, batch, d, n, E, phi, yt, u, s, cs, xexp);
-    (void)hipFreeAsync(u, s);
+    if (u != nullptr)
+        (void)hipFreeAsync(u, s);
     return st;
 }
 
