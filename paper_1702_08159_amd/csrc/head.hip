@@ -285,9 +285,11 @@ __global__ void __launch_bounds__(kHeadThreads)
     }
 }
 
-// out[i] = sum over g of part[g count + i], g ascending (zero for no groups).
+// out[i] = sum over g of part[g count + i], g ascending (zero for no groups);
+// with y, also y[i] += alpha out[i].
 __global__ void __launch_bounds__(kHeadThreads)
-    k_sum_groups(const float* __restrict__ part, int64_t groups, int64_t count, float* __restrict__ out)
+    k_sum_groups(const float* __restrict__ part, int64_t groups, int64_t count, float* __restrict__ out,
+                 float* __restrict__ y, float alpha)
 {
     const int64_t i = (int64_t)blockIdx.x * kHeadThreads + threadIdx.x;
     if (i >= count)
@@ -296,6 +298,111 @@ __global__ void __launch_bounds__(kHeadThreads)
     for (int64_t g = 0; g < groups; ++g)
         s += part[g * count + i];
     out[i] = s;
+    if (y != nullptr)
+        y[i] += alpha * s;
+}
+
+// One block of 1024 lanes: the logits from the expansion-group partials and
+// b, then per row the steps of k_softmax_xent (lane t takes rows t, t + 1024,
+// ...); the mean loss and db are summed in a fixed order (each lane's rows in
+// order, an xor butterfly within each wave, the 16 waves in order).  b is
+// read by every lane before the barrier and updated after it.
+constexpr int kTailThreads = 1024;
+
+template <int C>
+__global__ void __launch_bounds__(kTailThreads)
+    k_head_tail(const float* __restrict__ part, float* __restrict__ b, int64_t esplit, int64_t batch,
+                const int32_t* __restrict__ labels, float inv_batch, float* __restrict__ logits,
+                float* __restrict__ dlogits, float* __restrict__ loss, float* __restrict__ db, float alpha)
+{
+    constexpr int NW = kTailThreads / 64;
+    __shared__ float red[NW][C + 1];
+    const int t = (int)threadIdx.x;
+    float bias[C], acc[C + 1];
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+        bias[c] = b ? b[c] : 0.f;
+#pragma unroll
+    for (int c = 0; c <= C; ++c)
+        acc[c] = 0.f;
+    for (int64_t r = t; r < batch; r += kTailThreads) {
+        float l[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            l[c] = 0.f;
+        for (int64_t sl = 0; sl < esplit; ++sl) {
+            const float* p = part + (sl * batch + r) * C;
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                l[c] += p[c];
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            l[c] += bias[c];
+            logits[r * C + c] = l[c];
+        }
+        const int y = labels[r];
+        float* g = dlogits + r * C;
+        if (y < 0 || y >= C) {
+            acc[C] += __builtin_nanf("");
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                g[c] = __builtin_nanf("");
+                acc[c] += __builtin_nanf("");
+            }
+            continue;
+        }
+        float m = l[0];
+#pragma unroll
+        for (int c = 1; c < C; ++c)
+            m = fmaxf(m, l[c]);
+        float s = 0.f;
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            s += expf(l[c] - m);
+        const float lse = logf(s) + m;
+        float ly = l[0];
+#pragma unroll
+        for (int c = 1; c < C; ++c)
+            ly = c == y ? l[c] : ly;
+        acc[C] += lse - ly;
+        const float inv_s = 1.f / s;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const float p = expf(l[c] - m) * inv_s;
+            const float gc = (p - (c == y ? 1.f : 0.f)) * inv_batch;
+            g[c] = gc;
+            acc[c] += gc;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c <= C; ++c) {
+        float v = acc[c];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1)
+            v += __shfl_xor(v, o);
+        acc[c] = v;
+    }
+    if ((t & 63) == 0) {
+#pragma unroll
+        for (int c = 0; c <= C; ++c)
+            red[t >> 6][c] = acc[c];
+    }
+    __syncthreads();
+    if (t <= C) {
+        float s = 0.f;
+        for (int w = 0; w < NW; ++w)
+            s += red[w][t];
+        if (t == C) {
+            if (loss)
+                *loss = s * inv_batch;
+        } else {
+            if (db)
+                db[t] = s;
+            if (b && alpha != 0.f)
+                b[t] += alpha * s;
+        }
+    }
 }
 
 template <int C>
@@ -408,13 +515,42 @@ hipError_t launch_head_bwd(const float* phi, const float* dl, const float* W, in
 #undef MCK_HBWD
 }
 
-hipError_t launch_sum_groups(const float* part, int64_t groups, int64_t count, float* out, hipStream_t s)
+hipError_t launch_sum_groups(const float* part, int64_t groups, int64_t count, float* out, hipStream_t s, float* y,
+                             float alpha)
 {
     if (count == 0)
         return hipSuccess;
     const unsigned blocks = (unsigned)((count + kHeadThreads - 1) / kHeadThreads);
-    k_sum_groups<<<dim3(blocks), dim3(kHeadThreads), 0, s>>>(part, groups, count, out);
+    k_sum_groups<<<dim3(blocks), dim3(kHeadThreads), 0, s>>>(part, groups, count, out, y, alpha);
     return hipGetLastError();
+}
+
+hipError_t launch_head_tail(const float* part, float* b, int64_t esplit, int64_t batch, int C,
+                            const int32_t* labels, float* logits, float* dlogits, float* loss, float* db, float alpha,
+                            hipStream_t s)
+{
+    if (batch < 1 || batch > kHeadTailRows)
+        return hipErrorInvalidValue;
+    const float inv = 1.f / (float)batch;
+#define MCK_TAIL(CC)                                                                                            \
+    case CC:                                                                                                   \
+        k_head_tail<CC><<<dim3(1), dim3(kTailThreads), 0, s>>>(part, b, esplit, batch, labels, inv, logits,     \
+                                                                dlogits, loss, db, alpha);                     \
+        return hipGetLastError();
+    switch (C) {
+        MCK_TAIL(1)
+        MCK_TAIL(2)
+        MCK_TAIL(3)
+        MCK_TAIL(4)
+        MCK_TAIL(5)
+        MCK_TAIL(6)
+        MCK_TAIL(7)
+        MCK_TAIL(8)
+        MCK_TAIL(9)
+        MCK_TAIL(10)
+    default: return hipErrorInvalidValue;
+    }
+#undef MCK_TAIL
 }
 
 hipError_t launch_softmax_xent(const float* logits, const int32_t* labels, int64_t batch, int C, float* row_loss,

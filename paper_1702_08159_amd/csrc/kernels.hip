@@ -565,7 +565,8 @@ constexpr int kRedSlices = 4;
 
 __global__ void __launch_bounds__(64 * kRedSlices)
     k_reduce(const float* __restrict__ partial, int64_t blocks, int64_t E, int64_t n, float* __restrict__ dS,
-             float* __restrict__ dG, float* __restrict__ dB)
+             float* __restrict__ dG, float* __restrict__ dB, float* __restrict__ uS, float* __restrict__ uG,
+             float* __restrict__ uB, float alpha)
 {
     __shared__ float part[kRedSlices][64];
     const int64_t en = E * n;
@@ -599,6 +600,9 @@ __global__ void __launch_bounds__(64 * kRedSlices)
         float* out = a == 0 ? dS : (a == 1 ? dG : dB);
         if (out != nullptr)
             out[e * n + i] = s;
+        float* upd = a == 0 ? uS : (a == 1 ? uG : uB);
+        if (upd != nullptr)
+            upd[e * n + i] += alpha * s;
     }
 }
 
@@ -845,6 +849,12 @@ struct RunDerive {
                           const double* S64, const float* S32, uint32_t* goff_f, float* Gs_f, uint32_t* goff_b,
                           float* Gk_b, float* Sh, hipStream_t s)
     {
+        if (goff_b == goff_f) {
+            // one unpacked layout serves both directions: one launch
+            if (PF != bwd_p(M) || Bsign != nullptr)
+                return hipErrorInvalidValue;
+            return derive_one<M, bwd_p(M)>(E, perm, G, nullptr, S64, S32, goff_f, Gk_b, Gs_f, Sh, s);
+        }
         const hipError_t err = derive_fwd<M>(PF, E, perm, G, Bsign, S64, S32, goff_f, Gs_f, Sh, s);
         if (err != hipSuccess)
             return err;
@@ -875,7 +885,7 @@ struct RunSplit {
     static hipError_t run(int P, bool* ok, int* def)
     {
         *ok = fwd_p_ok(M, P);
-        *def = fwd_p(M);
+        *def = P < 0 ? bwd_p(M) : fwd_p(M);
         return hipSuccess;
     }
 };
@@ -907,6 +917,14 @@ int fwd_split_default(int M)
     bool ok = false;
     int def = 0;
     (void)dispatch_m<RunSplit>(M, 0, &ok, &def);
+    return def;
+}
+
+int bwd_split(int M)
+{
+    bool ok = false;
+    int def = 0;
+    (void)dispatch_m<RunSplit>(M, -1, &ok, &def);
     return def;
 }
 
@@ -999,11 +1017,11 @@ hipError_t launch_backward(int M, bool vec, const float* x, const float* dphi, i
 }
 
 hipError_t launch_reduce(const float* partial, int64_t blocks, int64_t E, int64_t n, float* dS, float* dG,
-                         float* dB, hipStream_t s)
+                         float* dB, hipStream_t s, float* uS, float* uG, float* uB, float alpha)
 {
     const int64_t total = 3 * E * n;
     k_reduce<<<dim3((unsigned)((total + 63) / 64)), dim3(64 * kRedSlices), 0, s>>>(partial, blocks, E, n, dS, dG,
-                                                                                  dB);
+                                                                                  dB, uS, uG, uB, alpha);
     return hipGetLastError();
 }
 

@@ -44,6 +44,7 @@ hipError_t launch_derive_fwd(int M, int PF, int64_t E, const int32_t* perm, cons
 // n = 2^M, and the default one.
 bool fwd_split_ok(int M, int P);
 int fwd_split_default(int M);
+int bwd_split(int M);  // register split of the backward
 constexpr int kFwdWavesDefault = 16384;
 
 // In-place batched Walsh-Hadamard transform, n = 2^M, 1 <= M <= 15.
@@ -146,9 +147,12 @@ hipError_t launch_backward(int M, bool vec, const float* x, const float* dphi, i
                            const BwdGeometry& geo, hipStream_t s);
 
 // Fixed-order sum of the partials: out_a[e][i] = sum_b partial[b][e][a][i]
-// for a = 0 (S), 1 (G), 2 (B); null outputs skipped.
+// for a = 0 (S), 1 (G), 2 (B); null outputs skipped.  With uS, uG, uB
+// (nullable) each sum also updates u_a[e][i] += alpha out_a[e][i] (the SGD
+// step of the training step, after every reader of those arrays).
 hipError_t launch_reduce(const float* partial, int64_t blocks, int64_t E, int64_t n, float* dS, float* dG,
-                         float* dB, hipStream_t s);
+                         float* dB, hipStream_t s, float* uS = nullptr, float* uG = nullptr, float* uB = nullptr,
+                         float alpha = 0.f);
 
 // Classifier head (head.hip): per-row softmax cross-entropy and its
 // gradient (dlogits = (softmax - onehot) / batch), then the mean loss and
@@ -185,7 +189,18 @@ void head_bwd_geometry(int64_t batch, int64_t F, bool need_dW, int64_t* slabs, i
 hipError_t launch_head_bwd(const float* phi, const float* dl, const float* W, int64_t batch, int64_t F, int C,
                            int64_t slabs, int64_t groups, int64_t rows_per_group, float* dphi, float* part,
                            hipStream_t s);
-hipError_t launch_sum_groups(const float* part, int64_t groups, int64_t count, float* out, hipStream_t s);
+// out[i] = sum over groups of part[g count + i]; with y (nullable) also
+// y[i] += alpha out[i].
+hipError_t launch_sum_groups(const float* part, int64_t groups, int64_t count, float* out, hipStream_t s,
+                             float* y = nullptr, float alpha = 0.f);
+// The end of the fused training step's head for batch <= kHeadTailRows and
+// C <= kFusedHeadMaxC, in one block: logits = b + the esplit partials, the
+// softmax cross-entropy per row (dlogits), the mean loss and db in a fixed
+// order, and b += alpha db (alpha may be 0).
+constexpr int64_t kHeadTailRows = 4096;
+hipError_t launch_head_tail(const float* part, float* b, int64_t esplit, int64_t batch, int C,
+                            const int32_t* labels, float* logits, float* dlogits, float* loss, float* db, float alpha,
+                            hipStream_t s);
 // logits[r][c] = b[c] (b nullable) + sum over slabs of part[slab][r][c].
 hipError_t launch_logits_finish(const float* part, const float* b, int64_t slabs, int64_t batch, int C,
                                 float* logits, hipStream_t s);

@@ -367,29 +367,53 @@ struct TempPlan {
     float* Sh = nullptr;
 };
 
-mck_status make_temp_plan(int64_t n, int64_t E, const int32_t* perm, const float* G, const float* S,
-                          hipStream_t s, TempPlan* tp, int force_p = 0)
+// Bytes of a temporary plan of register split PF: forward gather offsets,
+// backward ones (none when both directions use PF), G in both layouts, Sh.
+struct TempPlanSizes {
+    size_t a = 0, af = 0, ab = 0;
+    size_t bytes() const { return af + ab + 3 * a; }
+};
+
+TempPlanSizes temp_plan_sizes(int64_t n, int64_t E, int PF)
 {
-    const size_t en = (size_t)(n * E);
     int64_t gf = 0, gb = 0;
     mck::plan_elems(log2i(n), &gf, &gb);
-    const size_t a = align_up(en * 4), af = align_up((size_t)gf * E * 4), ab = align_up((size_t)gb * E * 4);
-    hipError_t err = hipMallocAsync(&tp->block, af + ab + 3 * a, s);
-    if (err != hipSuccess) {
-        tp->block = nullptr;
-        return fail(MCK_ERR_NO_MEMORY, std::string("temporary plan: ") + hipGetErrorString(err));
+    TempPlanSizes z;
+    z.a = align_up((size_t)(n * E) * 4);
+    z.af = align_up((size_t)gf * E * 4);
+    z.ab = PF == mck::bwd_split(log2i(n)) ? 0 : align_up((size_t)gb * E * 4);
+    return z;
+}
+
+// The arrays in mem (temp_plan_sizes(n, E, PF).bytes(), owned by the
+// caller; tp->block stays null) or in an allocation of their own (tp->block).
+mck_status make_temp_plan(int64_t n, int64_t E, const int32_t* perm, const float* G, const float* S,
+                          hipStream_t s, TempPlan* tp, int force_p = 0, char* mem = nullptr)
+{
+    tp->PF = force_p ? force_p : current_tuning(log2i(n)).P;
+    const TempPlanSizes z = temp_plan_sizes(n, E, tp->PF);
+    const size_t a = z.a, af = z.af, ab = z.ab;
+    const bool shared = ab == 0;  // the same register split in both directions: one set of offsets
+    hipError_t err = hipSuccess;
+    if (mem == nullptr) {
+        err = hipMallocAsync(&tp->block, z.bytes(), s);
+        if (err != hipSuccess) {
+            tp->block = nullptr;
+            return fail(MCK_ERR_NO_MEMORY, std::string("temporary plan: ") + hipGetErrorString(err));
+        }
     }
-    char* b = static_cast<char*>(tp->block);
+    char* b = mem ? mem : static_cast<char*>(tp->block);
     tp->goffF = reinterpret_cast<uint32_t*>(b);
-    tp->goffB = reinterpret_cast<uint32_t*>(b + af);
+    tp->goffB = shared ? tp->goffF : reinterpret_cast<uint32_t*>(b + af);
     tp->GsF = reinterpret_cast<float*>(b + af + ab);
     tp->GkB = reinterpret_cast<float*>(b + af + ab + a);
     tp->Sh = reinterpret_cast<float*>(b + af + ab + 2 * a);
-    tp->PF = force_p ? force_p : current_tuning(log2i(n)).P;
     err = mck::launch_derive(log2i(n), tp->PF, E, perm, G, nullptr, nullptr, S, tp->goffF, tp->GsF, tp->goffB,
                              tp->GkB, tp->Sh, s);
     if (err != hipSuccess) {
-        (void)hipFreeAsync(tp->block, s);
+        if (tp->block)
+            (void)hipFreeAsync(tp->block, s);
+        tp->block = nullptr;
         return hip_fail(err, "derive kernel");
     }
     return MCK_OK;
@@ -441,9 +465,12 @@ BwdScratch backward_scratch(int64_t batch, int64_t d, int64_t n, int64_t E, bool
 
 // The adjoint's launches.  ws: the call's temporaries (BwdScratch layout:
 // partials, then dx slices), or null to allocate them on the stream.
+// With uB, uG, uS (nullable; the training step's B, G, S) the final
+// partial-sum pass also applies u += alpha (dB, dG, dS).
 mck_status run_backward(const float* x, const float* dphi, int64_t batch, int64_t d, int64_t n, int64_t E,
                         const float* B, const uint32_t* goff, const float* Gk, const float* S32, const float* Sh,
-                        float* dx, float* dB, float* dG, float* dS, hipStream_t s, char* ws = nullptr)
+                        float* dx, float* dB, float* dG, float* dS, hipStream_t s, char* ws = nullptr,
+                        float* uB = nullptr, float* uG = nullptr, float* uS = nullptr, float alpha = 0.f)
 {
     const int M = log2i(n);
     const bool want_params = dB || dG || dS;
@@ -497,7 +524,7 @@ mck_status run_backward(const float* x, const float* dphi, int64_t batch, int64_
         done_blocks += geo.rowblocks;
     }
     if (err == hipSuccess && want_params)
-        err = mck::launch_reduce(partial, need.total_blocks, E, n, dS, dG, dB, s);
+        err = mck::launch_reduce(partial, need.total_blocks, E, n, dS, dG, dB, s, uS, uG, uB, alpha);
     release(partial);
     if (err != hipSuccess)
         return hip_fail(err, "backward launch");
@@ -1425,12 +1452,20 @@ mck_status mck_fastfood_backward_p(const float* x, const float* dphi, int64_t ba
                 err = mck::launch_sum_groups(nullptr, 0, n * E, o, s);  // a fill kernel: zeros
         return err == hipSuccess ? MCK_OK : hip_fail(err, "zero gradients");
     }
+    // one allocation: the parameter copies, then the adjoint's temporaries
+    const int PF = current_tuning(log2i(n)).P;
+    const size_t zt = align_up(temp_plan_sizes(n, E, PF).bytes());
+    const BwdScratch bs = backward_scratch(batch, d, n, E, dx != nullptr, dB || dG || dS);
+    void* block = nullptr;
+    hipError_t err = hipMallocAsync(&block, zt + bs.bytes(), s);
+    if (err != hipSuccess)
+        return fail(MCK_ERR_NO_MEMORY, std::string("backward temporaries: ") + hipGetErrorString(err));
     TempPlan tp;
-    st = make_temp_plan(n, E, perm, G, S, s, &tp);
-    if (st != MCK_OK)
-        return st;
-    st = run_backward(x, dphi, batch, d, n, E, B, tp.goffB, tp.GkB, S, tp.Sh, dx, dB, dG, dS, s);
-    (void)hipFreeAsync(tp.block, s);
+    st = make_temp_plan(n, E, perm, G, S, s, &tp, PF, static_cast<char*>(block));
+    if (st == MCK_OK)
+        st = run_backward(x, dphi, batch, d, n, E, B, tp.goffB, tp.GkB, S, tp.Sh, dx, dB, dG, dS, s,
+                          static_cast<char*>(block) + zt);
+    (void)hipFreeAsync(block, s);
     return st;
 }
 
@@ -1498,10 +1533,15 @@ mck_status train_step_fused(const float* x, const int32_t* labels, int64_t batch
     // scratch: dphi, logits (when the caller passes none), dlogits, row
     // losses, the logits' and dW's partials
     const int64_t lpart = esplit * batch * C, wpart = ranges > 1 ? ranges * C * F : 0;
+    constexpr int kPF = 4;  // register split of the fused kernels
+    const BwdScratch bs = backward_scratch(batch, d, n, E, dx != nullptr, true);
     const size_t zf = align_up((size_t)(batch * F) * 4), zl = align_up((size_t)(batch * C) * 4),
-                 zr = align_up((size_t)batch * 4), zp = align_up((size_t)(lpart > wpart ? lpart : wpart) * 4);
+                 zr = align_up((size_t)batch * 4), zp = align_up((size_t)(lpart > wpart ? lpart : wpart) * 4),
+                 zt = align_up(temp_plan_sizes(n, E, kPF).bytes());
+    // one allocation for every temporary of the step (each stream-ordered
+    // free costs the host tens of microseconds while the GPU is busy)
     void* block = nullptr;
-    hipError_t err = hipMallocAsync(&block, zf + 2 * zl + zr + zp, s);
+    hipError_t err = hipMallocAsync(&block, zf + 2 * zl + zr + zp + zt + bs.bytes(), s);
     if (err != hipSuccess)
         return fail(MCK_ERR_NO_MEMORY, std::string("training step scratch: ") + hipGetErrorString(err));
     char* base = static_cast<char*>(block);
@@ -1510,40 +1550,58 @@ mck_status train_step_fused(const float* x, const int32_t* labels, int64_t batch
     float* dl = reinterpret_cast<float*>(base + zf + zl);
     float* row_loss = reinterpret_cast<float*>(base + zf + 2 * zl);
     float* part = reinterpret_cast<float*>(base + zf + 2 * zl + zr);
+    char* tmem = base + zf + 2 * zl + zr + zp;
+    char* bws = tmem + zt;
     TempPlan tp;
-    mck_status st = make_temp_plan(n, E, perm, G, S, s, &tp, 4);
+    mck_status st = make_temp_plan(n, E, perm, G, S, s, &tp, kPF, tmem);
     if (st != MCK_OK) {
         (void)hipFreeAsync(block, s);
         return st;
     }
     const bool vec = aligned16(x) && d % 4 == 0;
     const float cs = feature_scale(n, E);
+    // the SGD step rides in the last pass over each gradient: b in the head
+    // tail (or one update launch), W in the sum of its partials, B, G, S in
+    // the adjoint's partial sums; every reader of a parameter runs before
+    const float alpha = -lr;
+    const bool tail = batch <= mck::kHeadTailRows;
     err = mck::launch_forward_logits(vec, x, batch, (int)d, E, B, tp.goffF, tp.GsF, tp.Sh, cs, W, (int)C, esplit,
                                      part, s);
-    if (err == hipSuccess)
+    if (err == hipSuccess && tail) {
+        err = mck::launch_head_tail(part, b, esplit, batch, (int)C, labels, lg, dl, loss, db, alpha, s);
+    } else if (err == hipSuccess) {
         err = mck::launch_logits_finish(part, b, esplit, batch, (int)C, lg, s);
-    if (err == hipSuccess)
-        err = mck::launch_softmax_xent(lg, labels, batch, (int)C, row_loss, dl, loss, db, s);
+        if (err == hipSuccess)
+            err = mck::launch_softmax_xent(lg, labels, batch, (int)C, row_loss, dl, loss, db, s);
+    }
     if (err == hipSuccess)
         err = mck::launch_head_bwd_fused(vec, x, batch, (int)d, E, B, tp.goffF, tp.GsF, tp.Sh, cs, dl, W, (int)C,
                                          ranges, rpr, dphi, ranges > 1 ? part : dW, s);
     if (err == hipSuccess && ranges > 1)
-        err = mck::launch_sum_groups(part, ranges, C * F, dW, s);
+        err = mck::launch_sum_groups(part, ranges, C * F, dW, s, lr != 0.f ? W : nullptr, alpha);
     if (err == hipSuccess) {
-        st = run_backward(x, dphi, batch, d, n, E, B, tp.goffB, tp.GkB, S, tp.Sh, dx, dB, dG, dS, s);
+        st = run_backward(x, dphi, batch, d, n, E, B, tp.goffB, tp.GkB, S, tp.Sh, dx, dB, dG, dS, s, bws,
+                          lr != 0.f ? B : nullptr, lr != 0.f ? G : nullptr, lr != 0.f ? S : nullptr, alpha);
         if (st != MCK_OK) {
-            (void)hipFreeAsync(tp.block, s);
             (void)hipFreeAsync(block, s);
             return st;
         }
     }
     if (err == hipSuccess && lr != 0.f) {
-        float* const ys[5] = {W, b, B, G, S};
-        const float* const xs[5] = {dW, db, dB, dG, dS};
-        const int64_t cnt[5] = {C * F, C, n * E, n * E, n * E};
-        err = mck::launch_axpy_multi(ys, xs, cnt, 5, -lr, s);
+        // what the passes above did not update
+        float* ys[2];
+        const float* xs[2];
+        int64_t cnt[2];
+        int k = 0;
+        if (ranges <= 1) {
+            ys[k] = W, xs[k] = dW, cnt[k++] = C * F;
+        }
+        if (!tail) {
+            ys[k] = b, xs[k] = db, cnt[k++] = C;
+        }
+        if (k > 0)
+            err = mck::launch_axpy_multi(ys, xs, cnt, k, alpha, s);
     }
-    (void)hipFreeAsync(tp.block, s);
     (void)hipFreeAsync(block, s);
     return err == hipSuccess ? MCK_OK : hip_fail(err, "training step launch");
 }
@@ -1580,10 +1638,14 @@ mck_status mck_fastfood_train_step(const float* x, const int32_t* labels, int64_
     mck::head_bwd_geometry(batch, F, true, &slabs, &groups, &rpg);
     const int64_t lpart = mck::head_logit_slabs(F) * batch * C;
     const int64_t hpart = groups > 1 ? groups * C * F : 0;
+    const int PF = current_tuning(log2i(n)).P;
+    const BwdScratch bs = backward_scratch(batch, d, n, E, dx != nullptr, true);
     const size_t zf = align_up((size_t)(batch * F) * 4), zl = align_up((size_t)(batch * C) * 4),
-                 zr = align_up((size_t)batch * 4), zp = align_up((size_t)(lpart > hpart ? lpart : hpart) * 4);
+                 zr = align_up((size_t)batch * 4), zp = align_up((size_t)(lpart > hpart ? lpart : hpart) * 4),
+                 zt = align_up(temp_plan_sizes(n, E, PF).bytes());
+    // one allocation for every temporary of the step
     void* block = nullptr;
-    hipError_t err = hipMallocAsync(&block, 2 * zf + 2 * zl + zr + zp, s);
+    hipError_t err = hipMallocAsync(&block, 2 * zf + 2 * zl + zr + zp + zt + bs.bytes(), s);
     if (err != hipSuccess)
         return fail(MCK_ERR_NO_MEMORY, std::string("training step scratch: ") + hipGetErrorString(err));
     char* base = static_cast<char*>(block);
@@ -1593,8 +1655,10 @@ mck_status mck_fastfood_train_step(const float* x, const int32_t* labels, int64_
     float* dl = reinterpret_cast<float*>(base + 2 * zf + zl);
     float* row_loss = reinterpret_cast<float*>(base + 2 * zf + 2 * zl);
     float* part = reinterpret_cast<float*>(base + 2 * zf + 2 * zl + zr);
+    char* tmem = base + 2 * zf + 2 * zl + zr + zp;
+    char* bws = tmem + zt;
     TempPlan tp;
-    st = make_temp_plan(n, E, perm, G, S, s, &tp);
+    st = make_temp_plan(n, E, perm, G, S, s, &tp, PF, tmem);
     if (st != MCK_OK) {
         (void)hipFreeAsync(block, s);
         return st;
@@ -1611,9 +1675,8 @@ mck_status mck_fastfood_train_step(const float* x, const int32_t* labels, int64_
     if (err == hipSuccess && groups > 1)
         err = mck::launch_sum_groups(part, groups, C * F, dW, s);
     if (err == hipSuccess) {
-        st = run_backward(x, dphi, batch, d, n, E, B, tp.goffB, tp.GkB, S, tp.Sh, dx, dB, dG, dS, s);
+        st = run_backward(x, dphi, batch, d, n, E, B, tp.goffB, tp.GkB, S, tp.Sh, dx, dB, dG, dS, s, bws);
         if (st != MCK_OK) {
-            (void)hipFreeAsync(tp.block, s);
             (void)hipFreeAsync(block, s);
             return st;
         }
@@ -1625,7 +1688,6 @@ mck_status mck_fastfood_train_step(const float* x, const int32_t* labels, int64_
         const int64_t cnt[5] = {C * F, C, n * E, n * E, n * E};
         err = mck::launch_axpy_multi(ys, xs, cnt, 5, -lr, s);
     }
-    (void)hipFreeAsync(tp.block, s);
     (void)hipFreeAsync(block, s);
     return err == hipSuccess ? MCK_OK : hip_fail(err, "training step launch");
 }

@@ -82,8 +82,10 @@ def test_axpy(mk):
 
 # n = 1024 with C <= 10 takes the step with the head fused into the feature
 # map (phi never in HBM); other n or C take the unfused kernels
+# (5 rows: dW without row-range partials; 4500 rows: past the one-block head
+# tail, the separate logits, softmax and sum launches)
 @pytest.mark.parametrize("batch,E,C,d", [(64, 2, 10, 784), (1024, 16, 10, 784), (1001, 3, 7, 784), (13, 1, 1, 1000),
-                                         (300, 4, 12, 784), (200, 3, 10, 300)])
+                                         (5, 3, 4, 784), (4500, 2, 3, 784), (300, 4, 12, 784), (200, 3, 10, 300)])
 def test_train_step_matches_oracle(mk, orc, batch, E, C, d):
     import torch
 
@@ -120,4 +122,27 @@ def test_sgd_steps_reduce_loss(mk, orc):
     out = mk.train_step(xs, ys, Wt, bt, B, perm, G, S, lr=0.5)
     for k, t in (("W", Wt), ("b", bt), ("B", B), ("G", G), ("S", S)):
         want = (before[k] - 0.5 * out["d" + k]).cpu().numpy()
+        np.testing.assert_allclose(t.cpu().numpy(), want, rtol=0, atol=1e-6 * max(1.0, np.abs(want).max()))
+
+
+# The SGD step is applied inside the passes that finish each gradient (the
+# head tail for b, the dW partial sum for W, the adjoint's partial sums for
+# B, G, S) or by one update launch: check w - lr grad on each of those forms.
+@pytest.mark.parametrize("batch,E,C,d", [(1024, 16, 10, 784), (5, 3, 4, 784), (4500, 2, 3, 784), (300, 4, 12, 784)])
+def test_sgd_update_rule(mk, orc, batch, E, C, d):
+    import torch
+
+    x, y, W, b, p = _problem(orc, batch, E, C=C, d=d, seed=5)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    Wt, bt = dev(W), dev(b)
+    B, G, S, perm = dev(p["B"]), dev(p["G"]), dev(p["S32"]), dev(p["perm"])
+    before = {k: t.clone() for k, t in (("W", Wt), ("b", bt), ("B", B), ("G", G), ("S", S))}
+    grads = mk.train_step(dev(x), dev(y), Wt, bt, B, perm, G, S)
+    for k in before:  # lr = 0 leaves the parameters alone
+        assert torch.equal(before[k], {"W": Wt, "b": bt, "B": B, "G": G, "S": S}[k]), k
+    out = mk.train_step(dev(x), dev(y), Wt, bt, B, perm, G, S, lr=0.25)
+    for k in ("loss", "dW", "db", "dB", "dG", "dS"):
+        assert torch.equal(out[k], grads[k]), k  # the gradients are taken before the update
+    for k, t in (("W", Wt), ("b", bt), ("B", B), ("G", G), ("S", S)):
+        want = (before[k] - 0.25 * out["d" + k]).cpu().numpy()
         np.testing.assert_allclose(t.cpu().numpy(), want, rtol=0, atol=1e-6 * max(1.0, np.abs(want).max()))
