@@ -216,3 +216,28 @@ def test_forward_2_16_one_block_rows(mk, orc, d, E, batch):
     got = phi[rows].cpu().numpy()
     ref, _, _ = orc.forward(x[rows].astype(np.float64), E, 77, sigma)
     assert rowwise_rel(got, ref).max() <= 1e-5
+
+
+def test_forward_2_16_many_expansions(mk, orc):
+    # E = 40 routings of Pi through the outer Benes stage (one colouring walk
+    # per expansion at plan time); every row against the oracle
+    import torch
+
+    d, E, batch = 65536, 40, 5
+    sigma = float(np.sqrt(d))
+    x = workloads.normal(batch, d, seed=40)
+    phi = mk.forward(torch.from_numpy(x).cuda(), E, 2024, sigma).cpu().numpy()
+    ref, _, _ = orc.forward(x.astype(np.float64), E, 2024, sigma)
+    assert rowwise_rel(phi, ref).max() <= 1e-5
+
+
+def test_forward_2_16_every_row_unit_norm(mk):
+    # ||phi(x)|| = 1 for every row (cos^2 + sin^2 per feature pair, scaled by
+    # 1 / sqrt(nE)): a row or expansion that no work item wrote shows here
+    import torch
+
+    d, E, batch = 60000, 3, 600
+    x = torch.from_numpy(workloads.normal(batch, d, seed=6)).cuda()
+    phi = mk.forward(x, E, 8, 256.0)
+    norms = torch.linalg.vector_norm(phi.double(), dim=1).cpu().numpy()
+    assert np.abs(norms - 1.0).max() <= 1e-5
