@@ -98,7 +98,7 @@ def test_every_hip_source_is_checked():
 def test_wide_buffer_stores_have_no_data_hazard(src):
     extra = hip_build.SOURCES.get(src, [])
     n_wide, bad = _exposed_stores(_assembly(src, extra))
-    if src in ("kernels.hip", "longn.hip", "head.hip"):
+    if src in ("kernels.hip", "longn.hip", "head.hip", "train.hip"):
         assert n_wide > 0, src  # these issue 128-bit stores: the check must see them
     assert not bad, "\n".join("%s: %s" % b for b in bad[:10])
 
