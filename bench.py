@@ -25,6 +25,7 @@ import hashlib
 import json
 import math
 import os
+import statistics
 import sys
 import time
 
@@ -192,6 +193,8 @@ def main():
         del a, b
 
     fwd_ms = bwd_ms = float("nan")
+    fwd_block_stats = None
+    stream_GBs = None
     bwd_check = bwd_shape = None
     preheat_ms = {}
     sync = torch.cuda.synchronize
@@ -201,12 +204,41 @@ def main():
         preheat_ms["fwd"] = preheat(gblock.replay, args.preheat_ms, sync)
         run_steps(gblock.replay, one.replay, args.warmup)
         torch.cuda.synchronize()
+        # an event after every graph of GRAPH_STEPS launches: the median and
+        # the minimum per-step time over those blocks come with the mean
+        marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps // GRAPH_STEPS)]
         t0.record(stream)
-        run_steps(gblock.replay, one.replay, args.steps)
+        for ev in marks:
+            gblock.replay()
+            ev.record(stream)
+        for _ in range(args.steps % GRAPH_STEPS):
+            one.replay()
         t1.record(stream)
         torch.cuda.synchronize()
         fwd_ms = t0.elapsed_time(t1) / args.steps
+        blocks = [a.elapsed_time(b) / GRAPH_STEPS for a, b in zip([t0] + marks[:-1], marks)]
+        if blocks:
+            fwd_block_stats = {"blocks": len(blocks), "median_ms_per_step": statistics.median(blocks),
+                               "min_ms_per_step": min(blocks)}
         log("forward %.4f ms/step over %d steps" % (fwd_ms, args.steps))
+        # a device-to-device copy and a fill of 1 GiB on the same card: the
+        # bandwidth plain streaming kernels reach here, beside the 8 TB/s
+        # peak (the forward's bytes are 97 % writes, like the fill's)
+        ca = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        cb = torch.empty_like(ca)
+        stream_GBs = {}
+        for name, fn, nbytes in (("copy", lambda: cb.copy_(ca), 2 << 30), ("fill", lambda: cb.fill_(2.0), 1 << 30)):
+            for _ in range(3):
+                fn()
+            torch.cuda.synchronize()
+            t0.record(stream)
+            for _ in range(10):
+                fn()
+            t1.record(stream)
+            torch.cuda.synchronize()
+            stream_GBs[name] = nbytes / (t0.elapsed_time(t1) / 10 * 1e-3) / 1e9
+        del ca, cb
+        log("device copy of 1 GiB: %.0f GB/s; fill: %.0f GB/s" % (stream_GBs["copy"], stream_GBs["fill"]))
     fwht_leg = None
     if args.only in ("fwd", "all") and args.fwht_steps > 0:
         # mck_fwht alone, in place on 2^18 rows of n = 1024 (1 GiB): reads and
@@ -649,6 +681,9 @@ def main():
         "config": {"workload": "fastfood-forward mnist-shaped 8192x784 (80% zeros) n=1024 E=16 sigma=2",
                    "batch": BATCH, "d": D, "n": N, "E": E, "sigma": SIGMA, "graph_steps": GRAPH_STEPS},
         "fwd_hbm_frac": fwd_gbs / HBM_PEAK_GBS,
+        "fwd_step_blocks": fwd_block_stats,
+        "device_stream_GBs": stream_GBs,
+        "fwd_frac_of_device_fill": fwd_gbs / stream_GBs["fill"] if stream_GBs else None,
         "fwd_bwd_vectors_per_s": fb_vps,
         "fwd_bwd_ms_per_step": fb_ms,
         "fwd_bwd_hbm_frac": fb_gbs / HBM_PEAK_GBS,
