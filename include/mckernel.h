@@ -97,7 +97,9 @@ typedef enum mck_dtype {
  * Largest n of mck_fwht and of the seed-mode feature map
  * (mck_fastfood_forward, mck_fastfood_forward_t): beyond MCK_MAX_N they run
  * as a row pass over 2^15-element chunks plus column passes over the high
- * index bits, through FP32 scratch rows allocated on the stream.
+ * index bits, through FP32 scratch rows allocated on the stream (the feature
+ * map at n = 2^16 instead keeps each row in one workgroup, with Pi split by
+ * the outer stage of a Benes network, and needs no scratch).
  */
 #define MCK_MAX_N_LONG 16777216
 
@@ -137,9 +139,10 @@ mck_status mck_fastfood_params(uint32_t seed, int64_t n, int64_t E, double sigma
  * Feature map.  x: batch x d (d >= 1, n = mck_padded_dim(d) <= MCK_MAX_N_LONG),
  * E >= 1, sigma finite > 0.  phi: batch x (2 n E), per row the E cosine
  * blocks of length n (expansion-major) followed by the E sine blocks.  For
- * n > MCK_MAX_N the call allocates two FP32 scratch buffers of up to
- * 2^27 floats each on `stream` (stream-ordered) and one row of phi must stay
- * below 2^31 bytes.
+ * n > MCK_MAX_N one row of phi must stay below 2^31 bytes; n = 2^16 runs in
+ * one workgroup per row and expansion with no scratch, and n >= 2^17
+ * allocates two FP32 scratch buffers of up to 2^27 floats each on `stream`
+ * (stream-ordered).
  */
 mck_status mck_fastfood_forward(const float* x, int64_t batch, int64_t d, int64_t E, uint32_t seed,
                                 double sigma, mck_calibration calib, float* phi, mck_stream stream);
