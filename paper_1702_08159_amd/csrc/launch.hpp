@@ -94,9 +94,10 @@ hipError_t launch_forward_pair(bool vec, int xt, int yt, const void* x, int64_t 
 // holds, for each destination chunk co, the elements it receives, grouped
 // by source chunk ci (ascending), ascending destination within a group.
 // Per expansion (arrays of expansion e start at e n and e C C):
-//   packA [ci 2^15 + q] = co << 15 | s: the q-th element leaving source
-//       chunk ci (grouped by co, the same order within a group) is its
-//       element s and goes to destination chunk co;
+//   packA [ci 2^15 + slot(q)] = co << 15 | s: the q-th element leaving
+//       source chunk ci (grouped by co, the same order within a group) is
+//       its element s and goes to destination chunk co; slot(q) orders the
+//       positions for the row pass's lanes (pack_slot in longn.hip);
 //   pdelta [ci C + co]: its position in T is q + pdelta[ci][co];
 //   dstB [co 2^15 + p]: T position co 2^15 + p lands at element dstB of
 //       destination chunk co;

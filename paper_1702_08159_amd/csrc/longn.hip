@@ -56,6 +56,17 @@ struct RowArgs {
     const uint16_t* dstB;    // kInBucket
 };
 
+// Storage slot of exchange position q (0 <= q < 2^15) of a source chunk in
+// packA: lane t of the row pass handles the positions q = (4 j + m) 1024 + t
+// (j < 8, m < 4), so that the 64 lanes of a wave store 64 consecutive
+// exchange positions per instruction, and reads its four positions of j as
+// one 16-byte word at slot (j 1024 + t) 4 + m.
+__host__ __device__ constexpr uint32_t pack_slot(uint32_t q)
+{
+    return (((q >> 10) >> 2) * 1024u + (q & 1023u)) * 4u + ((q >> 10) & 3u);
+}
+static_assert(RG::BLOCK == 1024 && RG::EPL == 32, "pack_slot assumes the 1024-lane, 32-register row pass");
+
 // XCD-aware (row slot, chunk) of a row-pass block: blocks are dealt to the
 // 8 XCDs round robin.  With 8 or more chunks, XCD x takes the chunks
 // c = x (mod 8) of every row slot, so the plan words of its C / 8 chunks
@@ -185,7 +196,7 @@ __global__ void __launch_bounds__(RG::BLOCK) k_rows(RowArgs a)
             for (int j = 0; j < NQ; ++j)
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
-                    const uint32_t q = 4u * (j * BLOCK + t) + m;
+                    const uint32_t q = (uint32_t)((4 * j + m) * BLOCK) + t;  // pk[j][m] is packA at pack_slot(q)
                     const uint32_t w = pk[j][m];
                     const int32_t pos = (int32_t)q + sdel[(w >> kRowM) & (kMaxChunks - 1)];
                     bstore1(ro, 4u * (uint32_t)pos, 0u, lds[phys<P>(w & 0x7fffu)]);
@@ -877,8 +888,10 @@ __global__ void __launch_bounds__(512)
     const int ci = threadIdx.x;
     const int32_t* pc = perm + e * n + (int64_t)co * RG::n;
     int64_t qa = 0, pb = 0;
+    uint32_t q = 0;  // exchange position within source chunk ci
     if (ci < C) {
-        qa = e * n + (int64_t)ci * RG::n + seg[(e * C + ci) * C + co];
+        qa = e * n + (int64_t)ci * RG::n;
+        q = (uint32_t)seg[(e * C + ci) * C + co];
         pb = e * n + (int64_t)co * RG::n + pre[(e * C + co) * C + ci];
     }
     for (int base = 0; base < RG::n; base += TILE) {
@@ -890,7 +903,7 @@ __global__ void __launch_bounds__(512)
             for (int j = 0; j < TILE; ++j) {
                 const int32_t src = tile[j];
                 if ((src >> kRowM) == ci) {
-                    packA[qa++] = ((uint32_t)co << kRowM) | (uint32_t)(src & (RG::n - 1));
+                    packA[qa + pack_slot(q++)] = ((uint32_t)co << kRowM) | (uint32_t)(src & (RG::n - 1));
                     dstB[pb++] = (uint16_t)(base + j);
                 }
             }
