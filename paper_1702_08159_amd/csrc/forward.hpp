@@ -33,6 +33,14 @@ constexpr bool fwd_p_tunable(int M) { return M >= 9 && M <= 14; }
 constexpr int fwd_p_alt(int M) { return fwd_p(M) == 4 ? 5 : 4; }
 constexpr bool fwd_p_ok(int M, int P) { return P == fwd_p(M) || (fwd_p_tunable(M) && P == fwd_p_alt(M)); }
 
+// Where the forward applies G.  At P = 4 (the pipelined forward and the
+// training step's tile kernels) G multiplies the gathered values in
+// destination order, and the compiler fuses that product into the first
+// butterfly of the second transform (one multiply and two multiply-adds
+// per pair instead of two multiplies and two adds); at P = 5 G multiplies
+// the transformed values in source order before the gather.
+constexpr bool fwd_g_after_gather(int P) { return P == 4; }
+
 // With P = 5 the parameters of the next expansion fit in VGPRs beside the
 // 32 values per lane only in packed form: B as one sign word per lane and
 // the gather sources as 16-bit LDS float indices (two per word).  The packed
@@ -196,8 +204,8 @@ __device__ __forceinline__ void forward_packed(rsrc_t rx, rsrc_t rG, rsrc_t rS, 
     }
 }
 
-// Per expansion e: v = B_e xhat; H; scale by G_e in source order and write to
-// LDS; gather v[perm[i]]; H; z = S_e v; phi blocks written with float4
+// Per expansion e: v = B_e xhat; H; write to LDS; gather v[perm[i]] and scale
+// by G_e (fwd_g_after_gather); H; z = S_e v; phi blocks written with float4
 // streaming stores.  On gfx9-family GPUs the vector-memory counter counts
 // stores as well as loads, so a load issued after an expansion's 2n-float
 // feature stores cannot complete (be waited for) before those stores do.
@@ -291,17 +299,25 @@ __device__ __forceinline__ void forward_body(const void* __restrict__ x, uint32_
         if constexpr (!PIPE)
             bload_lane<M, P, uint32_t>(off, rO, 4u * (uint32_t)e * kGoffE, lane);
 
-        // G Pi v1 = Pi (G' v1) with G' = G in source order: scale, write v1 to
-        // LDS in natural order, gather v1[perm[i]]
+        // G Pi v1: write v1 to LDS in natural order, gather v1[perm[i]]; G
+        // in destination order after the gather (P = 4), or moved to source
+        // order before it (Pi (G' v1), P = 5)
+        if constexpr (!fwd_g_after_gather(P)) {
 #pragma unroll
-        for (int r = 0; r < EPL; ++r)
-            v[r] *= gs[r];
+            for (int r = 0; r < EPL; ++r)
+                v[r] *= gs[r];
+        }
         lds_put<M, P, g::GL>(buf, lds_lane<M, P>(t), v);
         lds_sync<M, P>();
 #pragma unroll
         for (int r = 0; r < EPL; ++r)
             v[r] = *reinterpret_cast<const float*>(lbytes + off[r]);
         lds_sync<M, P>();
+        if constexpr (fwd_g_after_gather(P)) {
+#pragma unroll
+            for (int r = 0; r < EPL; ++r)
+                v[r] *= gs[r];
+        }
         if constexpr (!PIPE)
             bload_coal<M, P>(sx, rS, eo4, t);
 

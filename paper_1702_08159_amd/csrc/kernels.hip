@@ -611,8 +611,10 @@ __global__ void __launch_bounds__(64 * kRedSlices)
 //   goff[e][lane][r] = byte offset in the block's LDS of the gather source of
 //     register r of lane `lane` (row region included);
 //   Gk[e][t][r] = G[e][i] for the element i held there (destination order);
-//   Gs[e][q] = G[e][j] for the destination j whose gather source perm[j]
-//     sits at lane-major slot q (G moved to source order);
+//   Gs[e][q] (forward G): at P = 5, G[e][j] for the destination j whose
+//     gather source perm[j] sits at lane-major slot q (G moved to source
+//     order, applied before the gather); at P = 4, as Gk (destination order,
+//     applied after the gather, where it fuses into the first butterfly);
 // and Sh = S / (2 pi) (S in revolutions) in natural order.
 template <int M, int P>
 __device__ __forceinline__ uint32_t lane_major_slot(uint32_t i)
@@ -671,8 +673,12 @@ __global__ void k_derive(int64_t E, const int32_t* __restrict__ perm, const floa
         if (Gk)
             Gk[e * n + q] = G[e * n + iq];
         if (Gs) {
-            const uint32_t srcq = (uint32_t)perm[e * n + q] & (uint32_t)(n - 1);
-            Gs[e * n + lane_major_slot<M, P>(srcq)] = G[e * n + q];
+            if constexpr (fwd_g_after_gather(P)) {
+                Gs[e * n + q] = G[e * n + iq];
+            } else {
+                const uint32_t srcq = (uint32_t)perm[e * n + q] & (uint32_t)(n - 1);
+                Gs[e * n + lane_major_slot<M, P>(srcq)] = G[e * n + q];
+            }
         }
         if (Sh) {
             // S in revolutions for the feature map, from the FP64 value when present

@@ -158,7 +158,7 @@ struct Plan {
     float* S32 = nullptr;
     double* norm2 = nullptr;
     uint32_t* goffF = nullptr;  // forward gather offsets (default register split)
-    float* GsF = nullptr;       // G in source order, forward layout
+    float* GsF = nullptr;       // forward G (destination order at P = 4, source order at P = 5)
     uint32_t* goffF2 = nullptr; // the same for the other compiled split (null if none)
     float* GsF2 = nullptr;
     uint32_t* goffB = nullptr;  // backward gather offsets

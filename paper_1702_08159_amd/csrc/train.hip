@@ -33,11 +33,11 @@ static_assert(kTF == 4 * kTW * 64, "four features per lane of the block");
 static_assert(!TG::kMulti && TG::RPB == 1, "one row per wave");
 
 struct TileParams {
-    rsrc_t rB, rG, rO, rS;  // B (natural), G' (source order), gather offsets, S / 2 pi
+    rsrc_t rB, rG, rO, rS;  // B (natural), G (destination order), gather offsets, S / 2 pi
 };
 
 // One expansion's parameters in a lane's registers (coalesced layout for B
-// and S / 2 pi, lane-major for G' and the gather offsets).
+// and S / 2 pi, lane-major for G and the gather offsets).
 struct ExpParams {
     float b[16], g[16], s[16];
     uint32_t off[16];
@@ -54,7 +54,7 @@ __device__ __forceinline__ void load_exp(ExpParams& q, const TileParams& p, int 
 }
 
 // z (in revolutions) of one row and expansion, coalesced layout:
-// v = B xhat; H; G' (G in source order); gather v[perm[i]] in LDS; H; S/2pi.
+// v = B xhat; H; gather v[perm[i]] in LDS; G (destination order); H; S/2pi.
 __device__ __forceinline__ void row_z(float (&v)[16], const float (&xh)[16], const ExpParams& q, float* buf,
                                       uint32_t lane)
 {
@@ -64,14 +64,12 @@ __device__ __forceinline__ void row_z(float (&v)[16], const float (&xh)[16], con
     for (int r = 0; r < EPL; ++r)
         v[r] = xh[r] * q.b[r];
     fwht_up<kTM, kTP>(v, buf, lane);
-#pragma unroll
-    for (int r = 0; r < EPL; ++r)
-        v[r] *= q.g[r];
+    static_assert(fwd_g_after_gather(kTP), "the forward arrays hold G in destination order");
     lds_put<kTM, kTP, TG::GL>(buf, lane, v);
     wave_fence();
 #pragma unroll
     for (int r = 0; r < EPL; ++r)
-        v[r] = *reinterpret_cast<const float*>(lbytes + q.off[r]);
+        v[r] = *reinterpret_cast<const float*>(lbytes + q.off[r]) * q.g[r];
     wave_fence();
     fwht_down<kTM, kTP>(v, buf, lane);
 #pragma unroll
