@@ -325,7 +325,10 @@ __global__ void __launch_bounds__(BwdGeo<M>::THREADS)
     float* dxl = reinterpret_cast<float*>(dxl4);
     const int d4 = (d + 3) & ~3;
 
-    const uint32_t wave = threadIdx.x / 64u;
+    // the wave index is the same for all lanes of a wave: held in a scalar
+    // register, so row indices, bounds and row offsets of one-row-per-wave
+    // geometries are scalar work
+    const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64u));
     const uint32_t lane = threadIdx.x % 64u;
     const uint32_t grp = lane >> g::T;
     const uint32_t t = lane & (g::LPR - 1);
@@ -343,8 +346,24 @@ __global__ void __launch_bounds__(BwdGeo<M>::THREADS)
         const int64_t row = row_base + (int64_t)p * bg::ROWS;
         const bool valid = e < e1 && row < batch;
         const uint32_t doff = valid ? (uint32_t)(row * 2 * (int64_t)nE) * 4u + 4u * (uint32_t)e * n : 0u;
-        bload_row<M, P, VEC, 2>(cn, rD, doff, n, t, valid);
-        bload_row<M, P, VEC, 2>(sn, rD, doff + 4u * nE, n, t, valid);
+        if constexpr (g::RPB == 1 && VEC && EPL >= 4) {
+            // one row per wave: the row is uniform, and its offset goes to the
+            // loads' scalar offset beside the lane's fixed part.  A row past
+            // the batch reads the last row's dphi instead of zeros: its xhat is
+            // zero, so its v3, w and g-products with xhat are zero and it adds
+            // nothing to dS, dG, dB for finite dphi (and its dx is not written)
+            const int64_t rowc = row < batch ? row : batch - 1;
+            const uint32_t dcl = e < e1 ? (uint32_t)(rowc * 2 * (int64_t)nE) * 4u + 4u * (uint32_t)e * n : 0u;
+#pragma unroll
+            for (int j = 0; j < EPL / 4; ++j) {
+                const uint32_t lo = 4u * (ct | rpart(M, P, 0, 4 * j));
+                bload4<2>(&cn[4 * j], rD, lo, dcl);
+                bload4<2>(&sn[4 * j], rD, lo, dcl + 4u * nE);
+            }
+        } else {
+            bload_row<M, P, VEC, 2>(cn, rD, doff, n, t, valid);
+            bload_row<M, P, VEC, 2>(sn, rD, doff + 4u * nE, n, t, valid);
+        }
     };
     prefetch(e0, 0);
 
