@@ -447,13 +447,17 @@ __global__ void __launch_bounds__(BwdGeo<M>::THREADS)
             fwht_up<M, P>(v, buf, t);
             lds_put<M, P, g::GL>(buf, t, v);
             lds_sync<M, P>();
+            // the gather positions serve the adjoint's scatter of this pass too
             float w[EPL];
+            char* gp[EPL];
             {
                 float of[EPL];
                 ld_lane(of, PO, lane, 64);
 #pragma unroll
-                for (int r = 0; r < EPL; ++r)
-                    w[r] = *reinterpret_cast<const float*>(lbytes + __float_as_uint(of[r]));
+                for (int r = 0; r < EPL; ++r) {
+                    gp[r] = lbytes + __float_as_uint(of[r]);
+                    w[r] = *reinterpret_cast<const float*>(gp[r]);
+                }
             }
             lds_sync<M, P>();
             ld_lane(q, PG, t, g::LPR);
@@ -498,13 +502,9 @@ __global__ void __launch_bounds__(BwdGeo<M>::THREADS)
                     aG[r] += v[r] * w[r];
                 v[r] *= q[r];
             }
-            {
-                float of[EPL];
-                ld_lane(of, PO, lane, 64);
 #pragma unroll
-                for (int r = 0; r < EPL; ++r)
-                    *reinterpret_cast<float*>(lbytes + __float_as_uint(of[r])) = v[r];
-            }
+            for (int r = 0; r < EPL; ++r)
+                *reinterpret_cast<float*>(gp[r]) = v[r];
             lds_sync<M, P>();
             lds_get<M, P, g::GL>(buf, t, v);
             lds_sync<M, P>();
