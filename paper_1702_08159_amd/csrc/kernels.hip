@@ -401,29 +401,65 @@ __global__ void __launch_bounds__(BwdGeo<M>::THREADS)
         }
     };
 
-    for (int e = e0; e < e1; ++e) {
-        // stage the expansion's parameters (all earlier readers are done:
-        // the previous expansion ended with a block barrier)
-        {
-            const float* srcB = B + (int64_t)e * n;
-            const float* srcS = S32 + (int64_t)e * n;
-            const float* srcH = Sh + (int64_t)e * n;
-            const float* srcG = Gk + (int64_t)e * n;
-            const uint32_t* srcO = goff + (int64_t)e * GOFF_E;
-            for (int i = threadIdx.x; i < n; i += bg::THREADS) {
-                prm[PB + i] = srcB[i];
-                prm[PS + i] = cs * srcS[i];
-                prm[PH + i] = srcH[i];
+    // the parameter stage of an expansion goes through registers: its loads
+    // are issued before the previous expansion's partial sums, which hide
+    // their latency, and written to LDS once every wave is done with that
+    // expansion
+    constexpr int NSP = (n + bg::THREADS - 1) / bg::THREADS, NSO = (GOFF_E + bg::THREADS - 1) / bg::THREADS;
+    float sB[NSP], sS[NSP], sH[NSP], sG[NSP];
+    uint32_t sO[NSO];
+    auto stage_load = [&](int e) {
+        const float* srcB = B + (int64_t)e * n;
+        const float* srcS = S32 + (int64_t)e * n;
+        const float* srcH = Sh + (int64_t)e * n;
+        const float* srcG = Gk + (int64_t)e * n;
+        const uint32_t* srcO = goff + (int64_t)e * GOFF_E;
+#pragma unroll
+        for (int k = 0; k < NSP; ++k) {
+            const int i = (int)threadIdx.x + k * bg::THREADS;
+            if (n % bg::THREADS == 0 || i < n) {
+                sB[k] = srcB[i];
+                sS[k] = srcS[i];
+                sH[k] = srcH[i];
+                sG[k] = srcG[i];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NSO; ++k) {
+            const int i = (int)threadIdx.x + k * bg::THREADS;
+            if (GOFF_E % bg::THREADS == 0 || i < GOFF_E)
+                sO[k] = srcO[i];
+        }
+    };
+    auto stage_store = [&]() {
+#pragma unroll
+        for (int k = 0; k < NSP; ++k) {
+            const int i = (int)threadIdx.x + k * bg::THREADS;
+            if (n % bg::THREADS == 0 || i < n) {
+                prm[PB + i] = sB[k];
+                prm[PS + i] = cs * sS[k];
+                prm[PH + i] = sH[k];
                 // lane-major source (t * EPL + r) to float4-major
                 const int tq = i / EPL, r = i % EPL;
-                prm[PG + ((r / 4) * g::LPR + tq) * 4 + (r % 4)] = srcG[i];
+                prm[PG + ((r / 4) * g::LPR + tq) * 4 + (r % 4)] = sG[k];
             }
-            for (int i = threadIdx.x; i < GOFF_E; i += bg::THREADS) {
-                const int lq = i / EPL, r = i % EPL;
-                prm[PO + ((r / 4) * 64 + lq) * 4 + (r % 4)] = __uint_as_float(srcO[i]);
-            }
-            __syncthreads();
         }
+#pragma unroll
+        for (int k = 0; k < NSO; ++k) {
+            const int i = (int)threadIdx.x + k * bg::THREADS;
+            if (GOFF_E % bg::THREADS == 0 || i < GOFF_E) {
+                const int lq = i / EPL, r = i % EPL;
+                prm[PO + ((r / 4) * 64 + lq) * 4 + (r % 4)] = __uint_as_float(sO[k]);
+            }
+        }
+    };
+    if (e0 < e1) {
+        stage_load(e0);
+        stage_store();
+        __syncthreads();
+    }
+
+    for (int e = e0; e < e1; ++e) {
         float aS[EPL], aG[EPL], aB[EPL];
         if constexpr (PARAMS) {
 #pragma unroll
@@ -555,10 +591,17 @@ __global__ void __launch_bounds__(BwdGeo<M>::THREADS)
                 }
             }
         }
+        if (e + 1 < e1)
+            stage_load(e + 1);
         if constexpr (PARAMS)
             block_partials<M>(lds, aS, aG, aB, partial + ((rb * E + e) * 3) * n, wave, grp, t, cs);
         else
-            __syncthreads();  // the parameter stage is rewritten next
+            __syncthreads();
+        // every wave is done with this expansion's stage (the barrier above)
+        if (e + 1 < e1) {
+            stage_store();
+            __syncthreads();
+        }
     }
     if (dx != nullptr) {
         // every wave has added its last expansion: copy the rows out (to
