@@ -408,27 +408,25 @@ __global__ void __launch_bounds__(BwdGeo<M>::THREADS)
     constexpr int NSP = (n + bg::THREADS - 1) / bg::THREADS, NSO = (GOFF_E + bg::THREADS - 1) / bg::THREADS;
     float sB[NSP], sS[NSP], sH[NSP], sG[NSP];
     uint32_t sO[NSO];
+    const rsrc_t rPB = make_rsrc(B, 4u * nE), rPS = make_rsrc(S32, 4u * nE), rPH = make_rsrc(Sh, 4u * nE),
+                 rPG = make_rsrc(Gk, 4u * nE), rPO = make_rsrc(goff, 4u * (uint32_t)GOFF_E * (uint32_t)E);
     auto stage_load = [&](int e) {
-        const float* srcB = B + (int64_t)e * n;
-        const float* srcS = S32 + (int64_t)e * n;
-        const float* srcH = Sh + (int64_t)e * n;
-        const float* srcG = Gk + (int64_t)e * n;
-        const uint32_t* srcO = goff + (int64_t)e * GOFF_E;
+        const uint32_t se = 4u * (uint32_t)e * n, so = 4u * (uint32_t)e * GOFF_E;
 #pragma unroll
         for (int k = 0; k < NSP; ++k) {
-            const int i = (int)threadIdx.x + k * bg::THREADS;
-            if (n % bg::THREADS == 0 || i < n) {
-                sB[k] = srcB[i];
-                sS[k] = srcS[i];
-                sH[k] = srcH[i];
-                sG[k] = srcG[i];
+            const uint32_t i = threadIdx.x + (uint32_t)(k * bg::THREADS);
+            if (n % bg::THREADS == 0 || i < (uint32_t)n) {
+                sB[k] = bload1(rPB, 4u * i, se);
+                sS[k] = bload1(rPS, 4u * i, se);
+                sH[k] = bload1(rPH, 4u * i, se);
+                sG[k] = bload1(rPG, 4u * i, se);
             }
         }
 #pragma unroll
         for (int k = 0; k < NSO; ++k) {
-            const int i = (int)threadIdx.x + k * bg::THREADS;
-            if (GOFF_E % bg::THREADS == 0 || i < GOFF_E)
-                sO[k] = srcO[i];
+            const uint32_t i = threadIdx.x + (uint32_t)(k * bg::THREADS);
+            if (GOFF_E % bg::THREADS == 0 || i < (uint32_t)GOFF_E)
+                sO[k] = __float_as_uint(bload1(rPO, 4u * i, so));
         }
     };
     auto stage_store = [&]() {
