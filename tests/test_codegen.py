@@ -16,6 +16,7 @@ import shutil
 import subprocess
 import sys
 import tempfile
+from functools import lru_cache
 
 import pytest
 
@@ -28,6 +29,7 @@ WIDE_STORE = re.compile(r"^(buffer|global|flat)_store_dwordx[34]\b")
 VRANGE = re.compile(r"v\[(\d+):(\d+)\]")
 
 
+@lru_cache(maxsize=None)
 def _assembly(src: str, extra=()) -> str:
     try:
         cc = hip_build.hipcc()
@@ -96,7 +98,7 @@ def test_every_hip_source_is_checked():
                     reason="hipcc not available")
 @pytest.mark.parametrize("src", _hip_sources())
 def test_wide_buffer_stores_have_no_data_hazard(src):
-    extra = hip_build.SOURCES.get(src, [])
+    extra = tuple(hip_build.SOURCES.get(src, []))
     n_wide, bad = _exposed_stores(_assembly(src, extra))
     if src in ("kernels.hip", "longn.hip", "head.hip", "train.hip"):
         assert n_wide > 0, src  # these issue 128-bit stores: the check must see them
@@ -119,3 +121,44 @@ def test_checker_flags_register_soffset_and_early_rewrite():
     n_wide, bad = _exposed_stores(asm)
     assert n_wide == 3
     assert [b[0].split()[0] for b in bad] == ["register", "data"]
+
+
+# Kernels of the measured paths that must keep every value in registers: a
+# spill puts scratch traffic into the transform loops.  Patterns are on the
+# mangled names (k_forward at n = 1024, every aligned-row backward with
+# parameter gradients, the fused training-step kernels).
+NO_SCRATCH = {
+    "kernels.hip": [r"9k_forwardILi10ELi4E", r"15k_backward_rowsILi\d+ELb1ELb1E"],
+    "train.hip": [r"16k_forward_logitsILi10ELb1E", r"16k_head_bwd_fusedILi10ELb1E"],
+}
+
+
+def _private_segment_sizes(asm: str):
+    sizes, cur = {}, None
+    for line in asm.splitlines():
+        t = line.strip()
+        if t.startswith(".amdhsa_kernel "):
+            cur = t.split()[1]
+        elif cur and t.startswith(".amdhsa_private_segment_fixed_size "):
+            sizes[cur] = int(t.split()[1])
+            cur = None
+    return sizes
+
+
+@pytest.mark.skipif(shutil.which("hipcc") is None and not os.path.exists("/opt/rocm/bin/hipcc"),
+                    reason="hipcc not available")
+@pytest.mark.parametrize("src", sorted(NO_SCRATCH))
+def test_hot_kernels_use_no_scratch(src):
+    sizes = _private_segment_sizes(_assembly(src, tuple(hip_build.SOURCES.get(src, []))))
+    for pat in NO_SCRATCH[src]:
+        hit = {k: v for k, v in sizes.items() if re.search(pat, k)}
+        assert hit, pat
+        assert all(v == 0 for v in hit.values()), {k: v for k, v in hit.items() if v}
+
+
+def test_private_segment_parser():
+    asm = "\n".join([
+        "\t.amdhsa_kernel _Z1a", "\t\t.amdhsa_private_segment_fixed_size 0", "\t.end_amdhsa_kernel",
+        "\t.amdhsa_kernel _Z1b", "\t\t.amdhsa_private_segment_fixed_size 36", "\t.end_amdhsa_kernel",
+    ])
+    assert _private_segment_sizes(asm) == {"_Z1a": 0, "_Z1b": 36}
