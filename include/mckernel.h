@@ -31,6 +31,12 @@
  *    a cached parameter plan in device memory; building it allocates memory,
  *    launches the generator kernels on `stream` and waits for them.  Calls
  *    that reuse a cached plan allocate nothing except where noted.
+ *    "Stream-ordered" temporaries come from a few blocks per device that
+ *    the library allocates once (growing them when a call needs more) and
+ *    reuses: a block last used on another stream is taken after a
+ *    device-side wait for that use, so a call never waits on the host for
+ *    earlier work.  Under stream capture temporaries are graph-owned
+ *    stream-ordered allocations.  mck_shutdown() frees the blocks.
  *    The cache is thread-safe and holds at most 32 plans / 2 GiB per
  *    process, evicting the least recently used.  Each call pins its plan
  *    from lookup until its last launch is enqueued, so an eviction or
@@ -453,9 +459,10 @@ mck_status mck_fastfood_train_step(const float* x, const int32_t* labels, int64_
 mck_status mck_axpy(float* y, const float* x, int64_t count, float alpha, mck_stream stream);
 
 /* Frees every cached plan (waits for the device first) except those held by
- * a live mck_batched_graph or a call in progress on another thread.  Plans
- * that calls under stream capture used are freed too: graphs captured from
- * library calls must be destroyed before this is called. */
+ * a live mck_batched_graph or a call in progress on another thread, and
+ * the cached blocks of the temporaries.  Plans that calls under
+ * stream capture used are freed too: graphs captured from library calls
+ * must be destroyed before this is called. */
 void mck_shutdown(void);
 
 #ifdef __cplusplus

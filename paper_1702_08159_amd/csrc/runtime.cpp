@@ -33,6 +33,150 @@ mck_status hip_fail(hipError_t err, const char* where)
     return fail(MCK_ERR_HIP, std::string(where) + ": " + hipGetErrorString(err));
 }
 
+// Temporaries.  Each device keeps a few cached blocks, each with an event
+// recorded after the last launch of the call that used it.  A call takes a
+// free block, preferring one last used on its own stream (stream order alone
+// protects it); a block last used on another stream is taken after making
+// this stream wait, on the device, for that event.  So a call never waits on
+// the host for earlier work, which the stream-ordered allocator does here:
+// an allocation and a free on a busy stream return only once the stream has
+// drained.  A call under stream capture, or one that finds every block busy
+// (calls in progress on other host threads), takes stream-ordered memory
+// from a pool that keeps what is freed (graph-owned under capture).
+constexpr int kTempSlots = 8;
+struct TempSlot {
+    char* ptr = nullptr;
+    size_t bytes = 0;
+    hipEvent_t done = nullptr;
+    hipStream_t last = nullptr;
+    bool used = false;  // `done` marks the end of the last call that used it
+    bool busy = false;  // taken by a call that has not released it yet
+};
+struct DeviceTemps {
+    TempSlot slot[kTempSlots];
+    hipMemPool_t pool = nullptr;
+};
+std::mutex g_temp_mutex;
+std::map<int, DeviceTemps> g_temps;
+
+hipError_t pool_alloc(DeviceTemps& dt, int dev, void** p, size_t bytes, hipStream_t s)
+{
+    if (dt.pool == nullptr) {
+        hipMemPoolProps props;
+        std::memset(&props, 0, sizeof(props));
+        props.allocType = hipMemAllocationTypePinned;
+        props.location.type = hipMemLocationTypeDevice;
+        props.location.id = dev;
+        hipError_t err = hipMemPoolCreate(&dt.pool, &props);
+        if (err != hipSuccess) {
+            dt.pool = nullptr;
+            return err;
+        }
+        uint64_t keep = UINT64_MAX;
+        err = hipMemPoolSetAttribute(dt.pool, hipMemPoolAttrReleaseThreshold, &keep);
+        if (err != hipSuccess) {
+            (void)hipMemPoolDestroy(dt.pool);
+            dt.pool = nullptr;
+            return err;
+        }
+    }
+    return hipMallocFromPoolAsync(p, bytes, dt.pool, s);
+}
+
+hipError_t temp_alloc(void** p, size_t bytes, hipStream_t s)
+{
+    *p = nullptr;
+    int dev = 0;
+    hipError_t err = hipStreamGetDevice(s, &dev);
+    if (err != hipSuccess)
+        return err;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    err = hipStreamIsCapturing(s, &cap);
+    if (err != hipSuccess)
+        return err;
+    std::lock_guard<std::mutex> lock(g_temp_mutex);
+    DeviceTemps& dt = g_temps[dev];
+    if (cap != hipStreamCaptureStatusNone)
+        return pool_alloc(dt, dev, p, bytes, s);
+    int pick = -1;
+    for (int pass = 0; pass < 4 && pick < 0; ++pass) {
+        for (int k = 0; k < kTempSlots && pick < 0; ++k) {
+            const TempSlot& t = dt.slot[k];
+            if (t.busy)
+                continue;
+            const bool same = t.used && t.last == s;
+            if ((pass == 0 && same && t.bytes >= bytes) || (pass == 1 && !t.used) || (pass == 2 && same) || pass == 3)
+                pick = k;
+        }
+    }
+    if (pick < 0)
+        return pool_alloc(dt, dev, p, bytes, s);
+    TempSlot& t = dt.slot[pick];
+    if (t.bytes < bytes) {
+        // grow (rare): the old block is freed once its last user is done
+        if (t.ptr != nullptr) {
+            if (t.used)
+                (void)hipEventSynchronize(t.done);
+            (void)hipFree(t.ptr);
+            t.ptr = nullptr;
+            t.bytes = 0;
+        }
+        size_t want = bytes + bytes / 4;
+        want = (want + (size_t(1) << 20) - 1) & ~((size_t(1) << 20) - 1);
+        void* q = nullptr;
+        err = hipMalloc(&q, want);
+        if (err != hipSuccess)
+            return pool_alloc(dt, dev, p, bytes, s);
+        t.ptr = static_cast<char*>(q);
+        t.bytes = want;
+        t.used = false;
+    }
+    if (t.done == nullptr) {
+        err = hipEventCreateWithFlags(&t.done, hipEventDisableTiming);
+        if (err != hipSuccess) {
+            t.done = nullptr;
+            return err;
+        }
+    }
+    if (t.used && t.last != s) {
+        err = hipStreamWaitEvent(s, t.done, 0);
+        if (err != hipSuccess)
+            return err;
+    }
+    t.busy = true;
+    *p = t.ptr;
+    return hipSuccess;
+}
+
+// Ends a temporary's use by the calling call: the block is free for the next
+// call once the work enqueued on `s` so far is done.
+void temp_free(void* p, hipStream_t s)
+{
+    if (p == nullptr)
+        return;
+    {
+        std::lock_guard<std::mutex> lock(g_temp_mutex);
+        for (auto& kv : g_temps) {
+            for (TempSlot& t : kv.second.slot) {
+                if (t.busy && t.ptr == p) {
+                    const hipError_t err = hipEventRecord(t.done, s);
+                    if (err != hipSuccess) {
+                        // no event: wait here rather than hand out a block in use
+                        (void)hipStreamSynchronize(s);
+                        t.used = false;
+                    } else {
+                        t.used = true;
+                    }
+                    t.last = s;
+                    t.busy = false;
+                    return;
+                }
+            }
+        }
+    }
+    (void)hipFreeAsync(p, s);
+}
+
 bool is_pow2(int64_t v) { return v >= 1 && (v & (v - 1)) == 0; }
 
 int log2i(int64_t v)
@@ -396,7 +540,7 @@ mck_status make_temp_plan(int64_t n, int64_t E, const int32_t* perm, const float
     const bool shared = ab == 0;  // the same register split in both directions: one set of offsets
     hipError_t err = hipSuccess;
     if (mem == nullptr) {
-        err = hipMallocAsync(&tp->block, z.bytes(), s);
+        err = temp_alloc(&tp->block, z.bytes(), s);
         if (err != hipSuccess) {
             tp->block = nullptr;
             return fail(MCK_ERR_NO_MEMORY, std::string("temporary plan: ") + hipGetErrorString(err));
@@ -412,7 +556,7 @@ mck_status make_temp_plan(int64_t n, int64_t E, const int32_t* perm, const float
                              tp->GkB, tp->Sh, s);
     if (err != hipSuccess) {
         if (tp->block)
-            (void)hipFreeAsync(tp->block, s);
+            temp_free(tp->block, s);
         tp->block = nullptr;
         return hip_fail(err, "derive kernel");
     }
@@ -483,14 +627,14 @@ mck_status run_backward(const float* x, const float* dphi, int64_t batch, int64_
         if (ws) {
             partial = reinterpret_cast<float*>(ws);
         } else {
-            err = hipMallocAsync(reinterpret_cast<void**>(&partial), need.partial_bytes, s);
+            err = temp_alloc(reinterpret_cast<void**>(&partial), need.partial_bytes, s);
             if (err != hipSuccess)
                 return fail(MCK_ERR_NO_MEMORY, std::string("backward partials: ") + hipGetErrorString(err));
         }
     }
     auto release = [&](void* p) {
         if (p && !ws)
-            (void)hipFreeAsync(p, s);
+            temp_free(p, s);
     };
     const bool vec = vec_ok(x, dphi, d, n) && (dx == nullptr || aligned16(dx));
     const float cs = feature_scale(n, E);
@@ -506,7 +650,7 @@ mck_status run_backward(const float* x, const float* dphi, int64_t batch, int64_
             if (ws) {
                 dxs = dxs_ws;
             } else {
-                err = hipMallocAsync(reinterpret_cast<void**>(&dxs), (size_t)(geo.esplit * rows * d) * sizeof(float),
+                err = temp_alloc(reinterpret_cast<void**>(&dxs), (size_t)(geo.esplit * rows * d) * sizeof(float),
                                      s);
                 if (err != hipSuccess) {
                     release(partial);
@@ -730,13 +874,13 @@ static mck_status forward_long(const Plan* p, const void* x, int xt, int64_t bat
     float* u = nullptr;
     const size_t ub = (size_t)long_scratch_floats(batch, n, E) * sizeof(float);
     if (ub > 0) {
-        const hipError_t err = hipMallocAsync(reinterpret_cast<void**>(&u), ub, s);
+        const hipError_t err = temp_alloc(reinterpret_cast<void**>(&u), ub, s);
         if (err != hipSuccess)
             return fail(MCK_ERR_NO_MEMORY, std::string("long-vector scratch: ") + hipGetErrorString(err));
     }
     const mck_status st = forward_long_launch(p, x, xt, batch, d, n, E, phi, yt, u, s, cs, xexp);
     if (u != nullptr)
-        (void)hipFreeAsync(u, s);
+        temp_free(u, s);
     return st;
 }
 
@@ -1429,7 +1573,7 @@ mck_status mck_fastfood_forward_p(const float* x, int64_t batch, int64_t d, int6
     hipError_t err = mck::launch_forward(log2i(n), tp.PF, current_tuning(log2i(n)).waves, false, vec_ok(x, phi, d, n),
                                          true, x, batch, (int)d, E, B, tp.goffF, tp.GsF, tp.Sh, feature_scale(n, E),
                                          phi, s);
-    (void)hipFreeAsync(tp.block, s);
+    temp_free(tp.block, s);
     return err == hipSuccess ? MCK_OK : hip_fail(err, "forward launch");
 }
 
@@ -1457,7 +1601,7 @@ mck_status mck_fastfood_backward_p(const float* x, const float* dphi, int64_t ba
     const size_t zt = align_up(temp_plan_sizes(n, E, PF).bytes());
     const BwdScratch bs = backward_scratch(batch, d, n, E, dx != nullptr, dB || dG || dS);
     void* block = nullptr;
-    hipError_t err = hipMallocAsync(&block, zt + bs.bytes(), s);
+    hipError_t err = temp_alloc(&block, zt + bs.bytes(), s);
     if (err != hipSuccess)
         return fail(MCK_ERR_NO_MEMORY, std::string("backward temporaries: ") + hipGetErrorString(err));
     TempPlan tp;
@@ -1465,7 +1609,7 @@ mck_status mck_fastfood_backward_p(const float* x, const float* dphi, int64_t ba
     if (st == MCK_OK)
         st = run_backward(x, dphi, batch, d, n, E, B, tp.goffB, tp.GkB, S, tp.Sh, dx, dB, dG, dS, s,
                           static_cast<char*>(block) + zt);
-    (void)hipFreeAsync(block, s);
+    temp_free(block, s);
     return st;
 }
 
@@ -1541,7 +1685,7 @@ mck_status train_step_fused(const float* x, const int32_t* labels, int64_t batch
     // one allocation for every temporary of the step (each stream-ordered
     // free costs the host tens of microseconds while the GPU is busy)
     void* block = nullptr;
-    hipError_t err = hipMallocAsync(&block, zf + 2 * zl + zr + zp + zt + bs.bytes(), s);
+    hipError_t err = temp_alloc(&block, zf + 2 * zl + zr + zp + zt + bs.bytes(), s);
     if (err != hipSuccess)
         return fail(MCK_ERR_NO_MEMORY, std::string("training step scratch: ") + hipGetErrorString(err));
     char* base = static_cast<char*>(block);
@@ -1555,7 +1699,7 @@ mck_status train_step_fused(const float* x, const int32_t* labels, int64_t batch
     TempPlan tp;
     mck_status st = make_temp_plan(n, E, perm, G, S, s, &tp, kPF, tmem);
     if (st != MCK_OK) {
-        (void)hipFreeAsync(block, s);
+        temp_free(block, s);
         return st;
     }
     const bool vec = aligned16(x) && d % 4 == 0;
@@ -1583,7 +1727,7 @@ mck_status train_step_fused(const float* x, const int32_t* labels, int64_t batch
         st = run_backward(x, dphi, batch, d, n, E, B, tp.goffB, tp.GkB, S, tp.Sh, dx, dB, dG, dS, s, bws,
                           lr != 0.f ? B : nullptr, lr != 0.f ? G : nullptr, lr != 0.f ? S : nullptr, alpha);
         if (st != MCK_OK) {
-            (void)hipFreeAsync(block, s);
+            temp_free(block, s);
             return st;
         }
     }
@@ -1602,7 +1746,7 @@ mck_status train_step_fused(const float* x, const int32_t* labels, int64_t batch
         if (k > 0)
             err = mck::launch_axpy_multi(ys, xs, cnt, k, alpha, s);
     }
-    (void)hipFreeAsync(block, s);
+    temp_free(block, s);
     return err == hipSuccess ? MCK_OK : hip_fail(err, "training step launch");
 }
 
@@ -1645,7 +1789,7 @@ mck_status mck_fastfood_train_step(const float* x, const int32_t* labels, int64_
                  zt = align_up(temp_plan_sizes(n, E, PF).bytes());
     // one allocation for every temporary of the step
     void* block = nullptr;
-    hipError_t err = hipMallocAsync(&block, 2 * zf + 2 * zl + zr + zp + zt + bs.bytes(), s);
+    hipError_t err = temp_alloc(&block, 2 * zf + 2 * zl + zr + zp + zt + bs.bytes(), s);
     if (err != hipSuccess)
         return fail(MCK_ERR_NO_MEMORY, std::string("training step scratch: ") + hipGetErrorString(err));
     char* base = static_cast<char*>(block);
@@ -1660,7 +1804,7 @@ mck_status mck_fastfood_train_step(const float* x, const int32_t* labels, int64_
     TempPlan tp;
     st = make_temp_plan(n, E, perm, G, S, s, &tp, PF, tmem);
     if (st != MCK_OK) {
-        (void)hipFreeAsync(block, s);
+        temp_free(block, s);
         return st;
     }
     const int M = log2i(n);
@@ -1677,7 +1821,7 @@ mck_status mck_fastfood_train_step(const float* x, const int32_t* labels, int64_
     if (err == hipSuccess) {
         st = run_backward(x, dphi, batch, d, n, E, B, tp.goffB, tp.GkB, S, tp.Sh, dx, dB, dG, dS, s, bws);
         if (st != MCK_OK) {
-            (void)hipFreeAsync(block, s);
+            temp_free(block, s);
             return st;
         }
     }
@@ -1688,7 +1832,7 @@ mck_status mck_fastfood_train_step(const float* x, const int32_t* labels, int64_
         const int64_t cnt[5] = {C * F, C, n * E, n * E, n * E};
         err = mck::launch_axpy_multi(ys, xs, cnt, 5, -lr, s);
     }
-    (void)hipFreeAsync(block, s);
+    temp_free(block, s);
     return err == hipSuccess ? MCK_OK : hip_fail(err, "training step launch");
 }
 
@@ -1716,11 +1860,11 @@ mck_status mck_softmax_xent(const float* logits, const int32_t* labels, int64_t 
         return fail(MCK_ERR_INVALID_ARG, "logits, labels or dlogits is NULL");
     hipStream_t s = static_cast<hipStream_t>(stream);
     float* row_loss = nullptr;
-    hipError_t err = hipMallocAsync(reinterpret_cast<void**>(&row_loss), (size_t)batch * sizeof(float), s);
+    hipError_t err = temp_alloc(reinterpret_cast<void**>(&row_loss), (size_t)batch * sizeof(float), s);
     if (err != hipSuccess)
         return fail(MCK_ERR_NO_MEMORY, std::string("softmax scratch: ") + hipGetErrorString(err));
     err = mck::launch_softmax_xent(logits, labels, batch, (int)C, row_loss, dlogits, loss, db, s);
-    (void)hipFreeAsync(row_loss, s);
+    temp_free(row_loss, s);
     if (err != hipSuccess)
         return hip_fail(err, "softmax cross-entropy launch");
     return MCK_OK;
@@ -1753,12 +1897,12 @@ mck_status mck_head_logits(const float* phi, const float* W, const float* b, int
         return fail(MCK_ERR_INVALID_ARG, "phi and W must be 16-byte aligned");
     hipStream_t s = static_cast<hipStream_t>(stream);
     float* part = nullptr;
-    hipError_t err = hipMallocAsync(reinterpret_cast<void**>(&part),
+    hipError_t err = temp_alloc(reinterpret_cast<void**>(&part),
                                     (size_t)(mck::head_logit_slabs(F) * batch * C) * sizeof(float), s);
     if (err != hipSuccess)
         return fail(MCK_ERR_NO_MEMORY, std::string("head logits partials: ") + hipGetErrorString(err));
     err = mck::launch_head_logits(phi, W, b, batch, F, (int)C, part, logits, s);
-    (void)hipFreeAsync(part, s);
+    temp_free(part, s);
     return err == hipSuccess ? MCK_OK : hip_fail(err, "head logits launch");
 }
 
@@ -1782,7 +1926,7 @@ mck_status mck_head_backward(const float* phi, const float* dlogits, const float
         float* part = nullptr;
         hipError_t err = hipSuccess;
         if (groups > 0) {
-            err = hipMallocAsync(reinterpret_cast<void**>(&part), (size_t)(groups * C * F) * sizeof(float), s);
+            err = temp_alloc(reinterpret_cast<void**>(&part), (size_t)(groups * C * F) * sizeof(float), s);
             if (err != hipSuccess)
                 return fail(MCK_ERR_NO_MEMORY, std::string("head partials: ") + hipGetErrorString(err));
         }
@@ -1790,7 +1934,7 @@ mck_status mck_head_backward(const float* phi, const float* dlogits, const float
         if (err == hipSuccess)
             err = mck::launch_sum_groups(part, groups, C * F, dW, s);
         if (part)
-            (void)hipFreeAsync(part, s);
+            temp_free(part, s);
         return err == hipSuccess ? MCK_OK : hip_fail(err, "head backward launch");
     }
     const hipError_t err = mck::launch_head_bwd(phi, dlogits, W, batch, F, (int)C, slabs, groups, rpg, dphi, dW, s);
@@ -1823,6 +1967,27 @@ void mck_shutdown(void)
         (void)hipSetDevice(cur);
         free_plan(p);
     });
+    // the cached temporaries (except those of calls in progress) and what the
+    // pools keep
+    std::lock_guard<std::mutex> tlock(g_temp_mutex);
+    for (auto& kv : g_temps) {
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(kv.first);
+        (void)hipDeviceSynchronize();
+        for (TempSlot& t : kv.second.slot) {
+            if (t.busy)
+                continue;
+            if (t.ptr != nullptr)
+                (void)hipFree(t.ptr);
+            if (t.done != nullptr)
+                (void)hipEventDestroy(t.done);
+            t = TempSlot();
+        }
+        if (kv.second.pool != nullptr)
+            (void)hipMemPoolTrimTo(kv.second.pool, 0);
+        (void)hipSetDevice(cur);
+    }
 }
 
 }  // extern "C"
