@@ -1508,7 +1508,7 @@ mck_status mck_fastfood_backward(const float* x, const float* dphi, int64_t batc
         hipError_t err = hipSuccess;
         for (float* o : {dB, dG, dS})
             if (o && err == hipSuccess)
-                err = hipMemsetAsync(o, 0, (size_t)(n * E) * sizeof(float), s);
+                err = mck::launch_sum_groups(nullptr, 0, n * E, o, s);  // a fill kernel: zeros
         return err == hipSuccess ? MCK_OK : hip_fail(err, "zero gradients");
     }
     st = p.acquire(seed, n, E, sigma, calib, s);

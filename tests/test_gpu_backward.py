@@ -119,3 +119,29 @@ def test_backward_passes_sweep(mk, orc, d, batch, E, passes, esplit):
     dphi = workloads.grad_features(batch, 2 * n * E, seed=batch)
     print("case: backward d=%d batch=%d E=%d shape %s" % (d, batch, E, shape), flush=True)
     run_case(mk, orc, x, dphi, E, 91, float(n) ** 0.5, shape)
+
+
+def test_backward_empty_batch_zeroes_parameter_gradients(mk):
+    # the sums over an empty batch are zero; every entry point writes them
+    # (with a fill kernel, so the call can be captured into a graph)
+    import torch
+
+    E, d = 3, 100
+    n = mk.padded_dim(d)
+    x = torch.zeros((0, d), device="cuda")
+    g = torch.zeros((0, 2 * n * E), device="cuda")
+    p = mk.params(3, n, E, 1.0)
+    B, perm, G, S = (p[k].contiguous() for k in ("B", "perm", "G", "S"))
+    calls = {
+        "seed": lambda out: mk.backward(x, g, E, seed=3, sigma=1.0, out=out),
+        "explicit": lambda out: mk.backward_p(x, g, B, perm, G, S, out=out),
+        "explicit without allocation": lambda out: mk.backward_p(x, g, B, perm, G, S, out=out, noalloc=True),
+    }
+    for name, call in calls.items():
+        print("empty batch:", name, flush=True)
+        out = (torch.empty((0, d), device="cuda"),) + tuple(
+            torch.full((E, n), float("nan"), device="cuda") for _ in range(3))
+        call(out)
+        torch.cuda.synchronize()
+        for o in out[1:]:
+            assert bool((o == 0).all()), name
