@@ -626,8 +626,21 @@ constexpr int kRedSlices = 4;
 __global__ void __launch_bounds__(64 * kRedSlices)
     k_reduce(const float* __restrict__ partial, int64_t blocks, int64_t E, int64_t n, float* __restrict__ dS,
              float* __restrict__ dG, float* __restrict__ dB, float* __restrict__ uS, float* __restrict__ uG,
-             float* __restrict__ uB, float alpha)
+             float* __restrict__ uB, float alpha, GroupSum gs, int64_t rblocks)
 {
+    if ((int64_t)blockIdx.x >= rblocks) {
+        // the carried group sum, one output per thread
+        const int64_t i = ((int64_t)blockIdx.x - rblocks) * (64 * kRedSlices) + threadIdx.x;
+        if (i < gs.count) {
+            float s = 0.f;
+            for (int64_t g = 0; g < gs.groups; ++g)
+                s += gs.part[g * gs.count + i];
+            gs.out[i] = s;
+            if (gs.y != nullptr)
+                gs.y[i] += gs.alpha * s;
+        }
+        return;
+    }
     __shared__ float part[kRedSlices][64];
     const int64_t en = E * n;
     const int64_t idx = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
@@ -1083,11 +1096,15 @@ hipError_t launch_backward(int M, bool vec, const float* x, const float* dphi, i
 }
 
 hipError_t launch_reduce(const float* partial, int64_t blocks, int64_t E, int64_t n, float* dS, float* dG,
-                         float* dB, hipStream_t s, float* uS, float* uG, float* uB, float alpha)
+                         float* dB, hipStream_t s, float* uS, float* uG, float* uB, float alpha,
+                         const GroupSum* extra)
 {
     const int64_t total = 3 * E * n;
-    k_reduce<<<dim3((unsigned)((total + 63) / 64)), dim3(64 * kRedSlices), 0, s>>>(partial, blocks, E, n, dS, dG,
-                                                                                  dB, uS, uG, uB, alpha);
+    const int64_t rblocks = (total + 63) / 64;
+    const GroupSum gs = extra ? *extra : GroupSum{nullptr, 0, 0, nullptr, nullptr, 0.f};
+    const int64_t gblocks = (gs.count + 64 * kRedSlices - 1) / (64 * kRedSlices);
+    k_reduce<<<dim3((unsigned)(rblocks + gblocks)), dim3(64 * kRedSlices), 0, s>>>(
+        partial, blocks, E, n, dS, dG, dB, uS, uG, uB, alpha, gs, rblocks);
     return hipGetLastError();
 }
 

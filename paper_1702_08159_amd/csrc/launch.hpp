@@ -151,9 +151,20 @@ hipError_t launch_backward(int M, bool vec, const float* x, const float* dphi, i
 // for a = 0 (S), 1 (G), 2 (B); null outputs skipped.  With uS, uG, uB
 // (nullable) each sum also updates u_a[e][i] += alpha out_a[e][i] (the SGD
 // step of the training step, after every reader of those arrays).
+// A second sum the same launch can carry (the training step's dW from its
+// row-range partials): out[i] = sum over g ascending of part[g count + i],
+// and with y, y[i] += alpha out[i] -- the same order as launch_sum_groups.
+struct GroupSum {
+    const float* part;
+    int64_t groups;
+    int64_t count;
+    float* out;
+    float* y;
+    float alpha;
+};
 hipError_t launch_reduce(const float* partial, int64_t blocks, int64_t E, int64_t n, float* dS, float* dG,
                          float* dB, hipStream_t s, float* uS = nullptr, float* uG = nullptr, float* uB = nullptr,
-                         float alpha = 0.f);
+                         float alpha = 0.f, const GroupSum* extra = nullptr);
 
 // Classifier head (head.hip): per-row softmax cross-entropy and its
 // gradient (dlogits = (softmax - onehot) / batch), then the mean loss and

@@ -614,7 +614,8 @@ BwdScratch backward_scratch(int64_t batch, int64_t d, int64_t n, int64_t E, bool
 mck_status run_backward(const float* x, const float* dphi, int64_t batch, int64_t d, int64_t n, int64_t E,
                         const float* B, const uint32_t* goff, const float* Gk, const float* S32, const float* Sh,
                         float* dx, float* dB, float* dG, float* dS, hipStream_t s, char* ws = nullptr,
-                        float* uB = nullptr, float* uG = nullptr, float* uS = nullptr, float alpha = 0.f)
+                        float* uB = nullptr, float* uG = nullptr, float* uS = nullptr, float alpha = 0.f,
+                        const mck::GroupSum* extra = nullptr)
 {
     const int M = log2i(n);
     const bool want_params = dB || dG || dS;
@@ -667,8 +668,12 @@ mck_status run_backward(const float* x, const float* dphi, int64_t batch, int64_
         }
         done_blocks += geo.rowblocks;
     }
+    // `extra` (a group sum of the caller's) rides in the reduction's launch
     if (err == hipSuccess && want_params)
-        err = mck::launch_reduce(partial, need.total_blocks, E, n, dS, dG, dB, s, uS, uG, uB, alpha);
+        err = mck::launch_reduce(partial, need.total_blocks, E, n, dS, dG, dB, s, uS, uG, uB, alpha, extra);
+    else if (err == hipSuccess && extra != nullptr)
+        err = mck::launch_sum_groups(extra->part, extra->groups, extra->count, extra->out, s, extra->y,
+                                     extra->alpha);
     release(partial);
     if (err != hipSuccess)
         return hip_fail(err, "backward launch");
@@ -1721,11 +1726,13 @@ mck_status train_step_fused(const float* x, const int32_t* labels, int64_t batch
     if (err == hipSuccess)
         err = mck::launch_head_bwd_fused(vec, x, batch, (int)d, E, B, tp.goffF, tp.GsF, tp.Sh, cs, dl, W, (int)C,
                                          ranges, rpr, dphi, ranges > 1 ? part : dW, s);
-    if (err == hipSuccess && ranges > 1)
-        err = mck::launch_sum_groups(part, ranges, C * F, dW, s, lr != 0.f ? W : nullptr, alpha);
+    // dW from its row-range partials (and the W update) in the launch of the
+    // adjoint's sums: nothing after the head backward reads W
+    const mck::GroupSum wsum{part, ranges, C * F, dW, lr != 0.f ? W : nullptr, alpha};
     if (err == hipSuccess) {
         st = run_backward(x, dphi, batch, d, n, E, B, tp.goffB, tp.GkB, S, tp.Sh, dx, dB, dG, dS, s, bws,
-                          lr != 0.f ? B : nullptr, lr != 0.f ? G : nullptr, lr != 0.f ? S : nullptr, alpha);
+                          lr != 0.f ? B : nullptr, lr != 0.f ? G : nullptr, lr != 0.f ? S : nullptr, alpha,
+                          ranges > 1 ? &wsum : nullptr);
         if (st != MCK_OK) {
             temp_free(block, s);
             return st;
