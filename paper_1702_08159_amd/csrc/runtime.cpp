@@ -40,9 +40,9 @@ mck_status hip_fail(hipError_t err, const char* where)
 // this stream wait, on the device, for that event.  So a call never waits on
 // the host for earlier work, which the stream-ordered allocator does here:
 // an allocation and a free on a busy stream return only once the stream has
-// drained.  A call under stream capture, or one that finds every block busy
-// (calls in progress on other host threads), takes stream-ordered memory
-// from a pool that keeps what is freed (graph-owned under capture).
+// drained.  A call under stream capture takes graph-owned stream-ordered
+// memory; one that finds every block busy (calls in progress on other host
+// threads) takes stream-ordered memory from a pool that keeps what is freed.
 constexpr int kTempSlots = 8;
 struct TempSlot {
     char* ptr = nullptr;
@@ -97,7 +97,7 @@ hipError_t temp_alloc(void** p, size_t bytes, hipStream_t s)
     std::lock_guard<std::mutex> lock(g_temp_mutex);
     DeviceTemps& dt = g_temps[dev];
     if (cap != hipStreamCaptureStatusNone)
-        return pool_alloc(dt, dev, p, bytes, s);
+        return hipMallocAsync(p, bytes, s);  // graph-owned memory
     int pick = -1;
     for (int pass = 0; pass < 4 && pick < 0; ++pass) {
         for (int k = 0; k < kTempSlots && pick < 0; ++k) {

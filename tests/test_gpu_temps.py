@@ -94,3 +94,44 @@ def test_calls_with_temporaries_do_not_wait_on_the_host(env):
         # the queued work takes tens of milliseconds: a call that waited for
         # it would return only after it, leaving nothing to drain
         assert drain_ms > 10.0 and host_ms < drain_ms, (name, host_ms, drain_ms)
+
+
+def test_calls_with_temporaries_replay_from_a_graph(env):
+    # under capture the temporaries are graph-owned allocations: every
+    # replay, with eager calls (which use the cached blocks) and
+    # synchronisation in between, reproduces the eager results bit for bit
+    mk, torch = env
+    batch, d, n, E, C = 1024, 784, 1024, 16, 10
+    x, g = _inputs(torch, 14, batch, d, n, E)
+    p = mk.params(workloads.FASTFOOD_SEED, n, E, 1.0)
+    B, perm, G, S = (t.contiguous() for t in (p["B"], p["perm"], p["G"], p["S"]))
+    W = torch.from_numpy(np.random.default_rng(15).standard_normal((C, 2 * n * E)).astype(np.float32) * 0.01).cuda()
+    bias = torch.zeros(C, device="cuda")
+    labels = torch.from_numpy(np.arange(batch, dtype=np.int32) % C).cuda()
+    ref_b = [t.clone() for t in mk.backward(x, g, E, seed=5, sigma=2.0, need_params=True)]
+    ref_t = {k: v.clone() for k, v in mk.train_step(x, labels, W, bias, B, perm, G, S).items() if v is not None}
+    torch.cuda.synchronize()
+    outb = tuple(torch.empty_like(t) for t in ref_b)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        mk.backward(x, g, E, seed=5, sigma=2.0, out=outb)
+        mk.train_step(x, labels, W, bias, B, perm, G, S)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    print("capturing backward and training step", flush=True)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        mk.backward(x, g, E, seed=5, sigma=2.0, out=outb)
+        outt = mk.train_step(x, labels, W, bias, B, perm, G, S)
+    for k in range(3):
+        for t in outb:
+            t.fill_(float("nan"))
+        graph.replay()
+        torch.cuda.synchronize()
+        for r, o in zip(ref_b, outb):
+            assert torch.equal(r, o), ("backward", k)
+        for name, r in ref_t.items():
+            assert torch.equal(r, outt[name]), (name, k)
+        mk.backward(x[:100], g[:100], E, seed=5, sigma=2.0, need_params=True)  # eager work between replays
+        torch.cuda.synchronize()
