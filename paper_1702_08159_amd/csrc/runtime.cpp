@@ -16,6 +16,7 @@
 
 #include "mckernel.h"
 #include "launch.hpp"
+#include "temp_slots.hpp"
 #include "plan_cache.hpp"
 
 namespace {
@@ -98,17 +99,7 @@ hipError_t temp_alloc(void** p, size_t bytes, hipStream_t s)
     DeviceTemps& dt = g_temps[dev];
     if (cap != hipStreamCaptureStatusNone)
         return hipMallocAsync(p, bytes, s);  // graph-owned memory
-    int pick = -1;
-    for (int pass = 0; pass < 4 && pick < 0; ++pass) {
-        for (int k = 0; k < kTempSlots && pick < 0; ++k) {
-            const TempSlot& t = dt.slot[k];
-            if (t.busy)
-                continue;
-            const bool same = t.used && t.last == s;
-            if ((pass == 0 && same && t.bytes >= bytes) || (pass == 1 && !t.used) || (pass == 2 && same) || pass == 3)
-                pick = k;
-        }
-    }
+    const int pick = mck::pick_temp_slot(dt.slot, kTempSlots, s, bytes);
     if (pick < 0)
         return pool_alloc(dt, dev, p, bytes, s);
     TempSlot& t = dt.slot[pick];
