@@ -44,6 +44,7 @@ mck_status hip_fail(hipError_t err, const char* where)
 // drained.  A call under stream capture takes graph-owned stream-ordered
 // memory; one that finds every block busy (calls in progress on other host
 // threads) takes stream-ordered memory from a pool that keeps what is freed.
+// Streams are told apart by their handles.
 constexpr int kTempSlots = 8;
 struct TempSlot {
     char* ptr = nullptr;
@@ -84,6 +85,24 @@ hipError_t pool_alloc(DeviceTemps& dt, int dev, void** p, size_t bytes, hipStrea
     return hipMallocFromPoolAsync(p, bytes, dt.pool, s);
 }
 
+// Makes `dev` current for its lifetime (allocations and events belong to
+// the current device, which need not be the stream's).
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev)
+            (void)hipSetDevice(dev);
+        else
+            prev = -1;
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0)
+            (void)hipSetDevice(prev);
+    }
+};
+
 hipError_t temp_alloc(void** p, size_t bytes, hipStream_t s)
 {
     *p = nullptr;
@@ -96,6 +115,7 @@ hipError_t temp_alloc(void** p, size_t bytes, hipStream_t s)
     if (err != hipSuccess)
         return err;
     std::lock_guard<std::mutex> lock(g_temp_mutex);
+    const DeviceGuard on_dev(dev);
     DeviceTemps& dt = g_temps[dev];
     if (cap != hipStreamCaptureStatusNone)
         return hipMallocAsync(p, bytes, s);  // graph-owned memory
