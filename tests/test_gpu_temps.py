@@ -61,6 +61,28 @@ def test_backward_on_two_streams_matches_single_calls(env, batch, d, E):
             assert torch.equal(r, o), k
 
 
+@pytest.mark.parametrize("d,batch,E", [(131067, 3, 2), (262144, 2, 1)])
+def test_long_forward_on_two_streams_matches_single_calls(env, d, batch, E):
+    # the long-vector path's scratch rows are temporaries too
+    mk, torch = env
+    rng = np.random.default_rng(21)
+    xa = torch.from_numpy(rng.standard_normal((batch, d)).astype(np.float32)).cuda()
+    xb = torch.from_numpy(rng.standard_normal((batch + 1, d)).astype(np.float32)).cuda()
+    print("long forward on two streams: d %d batch %d E %d" % (d, batch, E), flush=True)
+    ref_a = mk.forward(xa, E, 9, 1.5)
+    ref_b = mk.forward(xb, E, 9, 1.5)
+    torch.cuda.synchronize()
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    outs = []
+    for k in range(4):
+        s, x = (sa, xa) if k % 2 == 0 else (sb, xb)
+        with torch.cuda.stream(s):
+            outs.append(mk.forward(x, E, 9, 1.5))
+    torch.cuda.synchronize()
+    for k, got in enumerate(outs):
+        assert torch.equal(got, ref_a if k % 2 == 0 else ref_b), k
+
+
 def _host_ms_behind_busy_stream(torch, call, busy_cycles=200_000_000):
     torch.cuda.synchronize()
     torch.cuda._sleep(busy_cycles)  # tens of milliseconds of queued work
